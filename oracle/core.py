@@ -1,0 +1,215 @@
+"""Oracle (test infrastructure only): ctypes binding of the C core.
+
+Arrays are numpy, C-contiguous, in the layouts documented in csrc/oracle.h.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import params as P
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        path = os.path.join(_HERE, "liboracle.so")
+        if not os.path.exists(path):
+            from .build import build
+            build()
+        L = C.CDLL(path)
+        u64p = np.ctypeslib.ndpointer(np.uint64, flags="C_CONTIGUOUS")
+        u32p = np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS")
+        u16p = np.ctypeslib.ndpointer(np.uint16, flags="C_CONTIGUOUS")
+        i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+        i8p = np.ctypeslib.ndpointer(np.int8, flags="C_CONTIGUOUS")
+        vp = C.c_void_p
+        u64, i = C.c_uint64, C.c_int
+        sig = {
+            "or_mulmod": (u64, [u64, u64, u64]),
+            "or_poly_mul_schoolbook": (None, [u64p, u64p, u64p, i, u64]),
+            "or_poly_eval_point": (u64, [u64p, i, u64, u64]),
+            "or_eval_fwd": (None, [u64p, i, u64, u64]),
+            "or_eval_inv": (None, [u64p, i, u64, u64]),
+            "or_poly_mul_eval": (None, [u64p, u64p, u64p, i, u64, u64]),
+            "or_ctx_create": (vp, [i, i, u64p, u64p, u64, u64]),
+            "or_ctx_destroy": (None, [vp]),
+            "or_ctx_delta": (None, [vp, u64p, C.POINTER(C.c_int), C.POINTER(C.c_uint64)]),
+            "or_encode": (None, [vp, u32p, u32p]),
+            "or_decode": (None, [vp, u32p, u32p]),
+            "or_encrypt": (None, [vp, i8p, u32p, u64p, i32p, u64p]),
+            "or_decrypt_poly": (None, [vp, i8p, u64p, u32p]),
+            "or_noise_budget": (i, [vp, i8p, u64p]),
+            "or_keygen_relin": (None, [vp, i8p, u64p, i32p, u64p]),
+            "or_mul_plain": (None, [vp, u64p, u32p, u64p]),
+            "or_add_plain_const": (None, [vp, u64p, C.c_uint32]),
+            "or_add_plain": (None, [vp, u64p, u32p]),
+            "or_mul_const": (None, [vp, u64p, C.c_uint32]),
+            "or_multiply": (None, [vp, u64p, u64p, u64p]),
+            "or_relin": (None, [vp, u64p, u64p, u64p]),
+            "or_select_sum": (None, [vp, i, i, u64p, u16p, u64p]),
+            "or_server_batch": (None, [vp, i, i, u64p, u16p, u64p, u64p]),
+            "or_server_eval": (None, [vp, i, i, i, i, u64p, u16p, u64p, vp, i, u64p]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+class Context:
+    """Scheme parameters: ring degree n, the L ciphertext primes, t = 65537."""
+
+    def __init__(self, n: int, primes, t: int = P.T_PLAIN):
+        self.n, self.t = n, t
+        self.primes = [int(q) for q in primes]
+        self.L = len(self.primes)
+        self.psis = [P.primitive_root_2n(q, n) for q in self.primes]
+        self.psi_t = P.primitive_root_2n(t, n)
+        self.Q = 1
+        for q in self.primes:
+            self.Q *= q
+        self.delta = self.Q // t
+        self._h = lib().or_ctx_create(n, self.L, _c(self.primes, np.uint64),
+                                      _c(self.psis, np.uint64), t, self.psi_t)
+        if not self._h:
+            raise ValueError("bad oracle context")
+
+    @classmethod
+    def standard(cls, n: int, L: int):
+        return cls(n, P.select_primes(n, L))
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _LIB is not None:
+            _LIB.or_ctx_destroy(self._h)
+            self._h = None
+
+    # shapes
+    def ct_shape(self, k: int = 2):
+        return (k, self.L, self.n)
+
+    def zeros_ct(self, k: int = 2):
+        return np.zeros(self.ct_shape(k), dtype=np.uint64)
+
+    # batching
+    def encode(self, slots):
+        out = np.zeros(self.n, dtype=np.uint32)
+        lib().or_encode(self._h, _c(slots, np.uint32), out)
+        return out
+
+    def decode(self, poly):
+        out = np.zeros(self.n, dtype=np.uint32)
+        lib().or_decode(self._h, _c(poly, np.uint32), out)
+        return out
+
+    # FV
+    def encrypt(self, sk, m_poly, a, e):
+        ct = self.zeros_ct()
+        lib().or_encrypt(self._h, _c(sk, np.int8), _c(m_poly, np.uint32), _c(a, np.uint64),
+                         _c(e, np.int32), ct)
+        return ct
+
+    def decrypt_poly(self, sk, ct):
+        out = np.zeros(self.n, dtype=np.uint32)
+        lib().or_decrypt_poly(self._h, _c(sk, np.int8), _c(ct, np.uint64), out)
+        return out
+
+    def decrypt_slots(self, sk, ct):
+        return self.decode(self.decrypt_poly(sk, ct))
+
+    def noise_budget(self, sk, ct) -> int:
+        return int(lib().or_noise_budget(self._h, _c(sk, np.int8), _c(ct, np.uint64)))
+
+    def keygen_relin(self, sk, a, e):
+        rlk = np.zeros((self.L, 2, self.L, self.n), dtype=np.uint64)
+        lib().or_keygen_relin(self._h, _c(sk, np.int8), _c(a, np.uint64), _c(e, np.int32), rlk)
+        return rlk
+
+    def mul_plain(self, ct, p_poly):
+        out = self.zeros_ct()
+        lib().or_mul_plain(self._h, _c(ct, np.uint64), _c(p_poly, np.uint32), out)
+        return out
+
+    def add_plain_const(self, ct, kappa: int):
+        ct = _c(ct, np.uint64).copy()
+        lib().or_add_plain_const(self._h, ct, kappa % self.t)
+        return ct
+
+    def add_plain(self, ct, p_poly):
+        ct = _c(ct, np.uint64).copy()
+        lib().or_add_plain(self._h, ct, _c(p_poly, np.uint32))
+        return ct
+
+    def mul_const(self, ct, k: int):
+        ct = _c(ct, np.uint64).copy()
+        lib().or_mul_const(self._h, ct, k % self.t)
+        return ct
+
+    def multiply(self, x, y):
+        out = self.zeros_ct(3)
+        lib().or_multiply(self._h, _c(x, np.uint64), _c(y, np.uint64), out)
+        return out
+
+    def relin(self, ct3, rlk):
+        out = self.zeros_ct()
+        lib().or_relin(self._h, _c(ct3, np.uint64), _c(rlk, np.uint64), out)
+        return out
+
+    # server computation
+    def select_sum(self, cts, cw_batch, h: int):
+        out = self.zeros_ct()
+        cts = _c(cts, np.uint64)
+        lib().or_select_sum(self._h, cts.shape[0], h, cts, _c(cw_batch, np.uint16), out)
+        return out
+
+    def server_batch(self, cts, cw_batch, rlk, h: int):
+        out = self.zeros_ct()
+        cts = _c(cts, np.uint64)
+        lib().or_server_batch(self._h, cts.shape[0], h, cts, _c(cw_batch, np.uint16),
+                              _c(rlk, np.uint64), out)
+        return out
+
+    def server_eval(self, cts, cw_table, rlk, h: int, mask=None, finalize=True,
+                    begin: int = 0, end: int | None = None):
+        out = self.zeros_ct()
+        cts = _c(cts, np.uint64)
+        cw_table = _c(cw_table, np.uint16)
+        end = cw_table.shape[0] if end is None else end
+        m = None
+        if mask is not None:
+            m = _c(mask, np.uint32)
+        lib().or_server_eval(self._h, cts.shape[0], h, begin, end, cts, cw_table,
+                             _c(rlk, np.uint64), None if m is None else m.ctypes.data,
+                             1 if finalize else 0, out)
+        return out
+
+    # integer views used by the pins
+    def residues_to_int(self, res):
+        """CRT of one coefficient's residues (list of L ints) -> integer in [0, Q)."""
+        x = 0
+        for q, r in zip(self.primes, res):
+            Qi = self.Q // q
+            x += (int(r) * pow(Qi, -1, q) % q) * Qi
+        return x % self.Q
+
+    def poly_to_ints(self, poly):
+        """limb-major [L][n] -> list of integers in [0, Q)."""
+        poly = np.asarray(poly)
+        return [self.residues_to_int([int(poly[l, i]) for l in range(self.L)]) for i in range(self.n)]
+
+    def ints_to_poly(self, ints):
+        out = np.zeros((self.L, self.n), dtype=np.uint64)
+        for l, q in enumerate(self.primes):
+            out[l] = [int(v) % q for v in ints]
+        return out

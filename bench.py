@@ -1,0 +1,238 @@
+#!/usr/bin/env python3
+"""Benchmark of the PEPSI PSI-cardinality server computation on one MI355X.
+
+Workload (the paper-shaped single query, plain path): N = 8192 bins/slots,
+L = 4 ciphertext primes (216-bit Q), t = 65537, Hamming weight h = 4, code
+length 569 (32-bit elements, eq. (1)), server maximum bin load mu = 526 (the
+paper's value for n = 2^20, b = 8192), server set n = 2^20 random 32-bit
+items, client set m = 1024 with 256 planted common items; cardinality output
+with a zero-sum mask.  Synthetic seeded data (workload/).
+
+A step is one server evaluation of one client request (every step of the
+path: client-ciphertext NTTs, select-and-sum over all server batches, the
+equality product with relinearisation, accumulation, (h!)^-1, mask, inverse
+NTT), with the request, relinearisation key and the server's prepared set
+resident in HBM.  The metric counts slot comparisons b * mu per query
+(Arith-CW-Eq evaluations between a client bin entry and a server bin entry,
+dummies included).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+CONFIGS = {
+    # log_n, L, h, item_bits, mu, n_server, m_client, planted
+    "paper": dict(log_n=13, L=4, h=4, item_bits=32, mu=526, n_server=1 << 20, m_client=1024, planted=256),
+    "toy": dict(log_n=12, L=2, h=2, item_bits=16, mu=11, n_server=256, m_client=16, planted=4),
+}
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def dev(a: np.ndarray):
+    import torch
+    a = np.ascontiguousarray(a)
+    view = {8: np.int64, 4: np.int32, 2: np.int16, 1: np.int8}[a.dtype.itemsize]
+    return torch.from_numpy(a.view(view).copy()).cuda()
+
+
+def traffic_record(kernel: str):
+    """HBM traffic from committed rocprofv3 counter runs, if they match the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, "paper_2310_14565_amd", "csrc", rec.get("source", "rns.hip"))
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if sha != rec.get("source_sha256"):
+        return None
+    return rec
+
+
+def cpu_baseline(cfg, params, server_items, seed):
+    """The oracle timed on a bounded sample: the client-ciphertext transforms plus one server batch,
+    extrapolated linearly to all mu batches of one query."""
+    from oracle import protocol as PR
+    from oracle.core import Context
+    import workload as W
+    n, L, h = 1 << cfg["log_n"], cfg["L"], cfg["h"]
+    ctx = Context(n, params.q_primes)
+    pcfg = PR.Config(n=n, L=L, h=h, item_bits=cfg["item_bits"], mu=cfg["mu"])
+    _, _, spos, _ = PR.server_prepare(pcfg, server_items)
+    ell = pcfg.ell
+    cts = W.uniform_residues((ell, 2), ctx.primes, n, seed, "cpu-cts")
+    rlk = W.uniform_residues((L, 2), ctx.primes, n, seed, "cpu-rlk")
+    t0 = time.perf_counter()
+    ctx.server_eval(cts, spos, rlk, h, finalize=False, begin=0, end=0)
+    t_prep = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ctx.server_eval(cts, spos, rlk, h, finalize=False, begin=0, end=1)
+    t_one = time.perf_counter() - t0
+    t_batch = max(t_one - t_prep, 1e-9)
+    t_query = t_prep + cfg["mu"] * t_batch
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": n * cfg["mu"] / t_query,
+        "unit": "slot-comparisons/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": (f"client-ciphertext transforms ({t_prep:.2f} s) + 1 of {cfg['mu']} server batches "
+                   f"({t_batch:.2f} s), extrapolated linearly to one query ({t_query:.0f} s)"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", choices=sorted(CONFIGS), default="paper")
+    ap.add_argument("--mode", choices=["cached", "generate"], default="cached",
+                    help="server plaintexts resident in NTT form (cached) or regenerated each query")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--seed", type=int, default=2024)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: every GPU box of this build has one GPU "
+              "(the multi-GPU sharding of the path is a design note, not a measured line)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2310_14565_amd as pk
+    import workload as W
+
+    cfg = CONFIGS[args.config]
+    n = 1 << cfg["log_n"]
+    L = cfg["L"]
+    torch.cuda.set_device(0)
+    log(f"[bench] config={args.config} mode={args.mode} N={n} L={L} h={cfg['h']} mu={cfg['mu']}")
+    params = pk.Params(cfg["log_n"], L, cfg["h"], cfg["item_bits"], cfg["mu"])
+    ell = params.ell
+    server_items = W.server_items(cfg["n_server"], cfg["item_bits"], args.seed)
+    client_items = W.client_items(cfg["m_client"], server_items, cfg["planted"], cfg["item_bits"], args.seed + 1)
+
+    # client request (GPU encryption of the codeword bit planes) and keys
+    table, valid = params.client_table(client_items)
+    planes = params.codeword_planes(table, valid)
+    sk = dev(W.secret_key(n, args.seed + 2))
+    cts = torch.zeros((ell, 2, L, n), dtype=torch.int64, device="cuda")
+    chunk = 64
+    for j0 in range(0, ell, chunk):
+        j1 = min(ell, j0 + chunk)
+        a = W.uniform_residues((j1 - j0,), params.q_primes, n, args.seed + 3 + j0, "enc-a")
+        e = W.errors((j1 - j0, n), args.seed + 3 + j0, "enc-e")
+        params.encrypt(sk, dev(planes[j0:j1]), dev(a), dev(e), cts[j0:j1])
+    rlk = torch.zeros((L, 2, L, n), dtype=torch.int64, device="cuda")
+    params.keygen_relin(sk, dev(W.uniform_residues((L,), params.q_primes, n, args.seed + 4, "rlk-a")),
+                        dev(W.errors((L, n), args.seed + 4, "rlk-e")), rlk)
+    mask = dev(W.zero_sum_mask(n, 65537, args.seed + 5))
+    torch.cuda.synchronize()
+
+    log("[bench] server preparation")
+    t0 = time.perf_counter()
+    server = pk.Server(params, server_items, cache_plaintexts=(args.mode == "cached"))
+    torch.cuda.synchronize()
+    offline_s = time.perf_counter() - t0
+    log(f"[bench] offline {offline_s:.2f} s, max load {server.max_load}, cached={server.cached}")
+
+    out = torch.zeros((2, L, n), dtype=torch.int64, device="cuda")
+    for _ in range(args.warmup):
+        server.eval(cts, rlk, mask, out)
+    torch.cuda.synchronize()
+    log("[bench] warmup done")
+
+    server.timing(enable=True, reset=True)
+    per_step = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        s0 = time.perf_counter()
+        server.eval(cts, rlk, mask, out)
+        torch.cuda.synchronize()
+        per_step.append(time.perf_counter() - s0)
+    t_total = time.perf_counter() - t_start
+    tm = server.timing(enable=False)
+    log(f"[bench] timed {args.steps} steps in {t_total:.3f} s")
+
+    # the result of the last step must decrypt to the planted cardinality
+    slots = torch.zeros((1, n), dtype=torch.int32, device="cuda")
+    params.decrypt(sk, out.reshape(1, 2, L, n), slots)
+    torch.cuda.synchronize()
+    card = int(slots.cpu().numpy().view(np.uint32).astype(np.int64).sum() % 65537)
+    budget = params.noise_budget(sk, out)
+    if card != cfg["planted"] or budget <= 0:
+        log(f"[bench] WRONG RESULT: cardinality {card} (want {cfg['planted']}), noise budget {budget}")
+        sys.exit(1)
+
+    ms_per_step = 1e3 * t_total / args.steps
+    comparisons = n * cfg["mu"]
+    value = comparisons * args.steps / t_total
+    launches = max(tm.select_sum_launches, 1)
+    avg_ms = tm.select_sum_ms / launches
+    bytes_per_launch = tm.select_sum_bytes / launches
+    achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9 if avg_ms > 0 else 0.0
+    trec = traffic_record("select_sum")
+    roofline = {
+        "bound": "hbm",
+        "kernel": "k_select_sum",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": None if trec is None else trec["bytes_per_launch"],
+        "launches_per_step": tm.select_sum_launches / args.steps,
+        "avg_launch_ms": round(avg_ms, 4),
+        "algorithmic_bytes_per_launch": int(bytes_per_launch),
+        "select_sum_ms_per_step": round(tm.select_sum_ms / args.steps, 3),
+        "eval_event_ms_per_step": round(tm.eval_ms / max(tm.evals, 1), 3),
+    }
+    line = {
+        "metric": "server item-comparisons/sec at m=1024,n=2^20 (plain one-query-per-launch path)",
+        "value": round(value, 1),
+        "unit": "slot-comparisons/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic (seeded random 32-bit sets, planted intersection)",
+        "config": {
+            "workload": (f"{args.config}: N={n} L={L} t=65537 h={cfg['h']} ell={ell} b={n} mu={cfg['mu']} "
+                         f"n={cfg['n_server']} m={cfg['m_client']} planted={cfg['planted']}, "
+                         f"server plaintexts {args.mode}"),
+            "path": "plain",
+            "global_batch": 1,
+        },
+        "roofline": roofline,
+        "latency_ms": {"p50": round(1e3 * float(np.percentile(per_step, 50)), 3),
+                       "p99": round(1e3 * float(np.percentile(per_step, 99)), 3)},
+        "offline_s": round(offline_s, 3),
+        "server_max_load": server.max_load,
+        "check": {"cardinality": card, "noise_budget_bits": budget},
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle sample)")
+        line["cpu_baseline"] = cpu_baseline(cfg, params, server_items, args.seed)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,259 @@
+/*
+ * pepsi.h -- C-ABI of the MI355X (gfx950) implementation of the server
+ * computation of PEPSI PSI-cardinality (Mahdavi, Lukas, Kerschbaum et al.,
+ * "PEPSI: Practically Efficient Private Set Intersection in the Unbalanced
+ * Setting", arXiv 2310.14565).
+ *
+ * The calls follow the paper's statement of the protocol (Sec. 4):
+ *   parameters and keys  ->  client preparation (Alg. 6, ClientDataPrep:
+ *   hashing, constant-weight encoding, batching, encryption)  ->  server
+ *   preparation (Alg. 6, ServerDataPrep)  ->  server computation (Alg. 1
+ *   Arith-CW-Eq inside Alg. 2 Intersect / Alg. 5 PSI-Sum with unit values,
+ *   i.e. PSI-Cardinality)  ->  result extraction (Alg. 3 / Alg. 5 decrypt).
+ * Single evaluator steps (NTT, batching, select-and-sum, ciphertext product,
+ * relinearisation) are exported too so that each can be checked on its own.
+ *
+ * Conventions
+ *   - Ring R = Z[X]/(X^N + 1), N = 2^log_n; plaintext modulus t = 65537.
+ *   - Ciphertext modulus Q = q_0 ... q_{L-1}: the L largest primes below 2^54
+ *     with q = 1 mod 2N, in descending order.
+ *   - A polynomial mod Q is limb-major: uint64 [L][N], residues in [0, q_l).
+ *     A ciphertext is [2][L][N] (c0 then c1); a product before
+ *     relinearisation is [3][L][N].  Every ciphertext crossing this boundary
+ *     is in COEFFICIENT form.
+ *   - Slots: slot k of a plaintext is its value at psi_t^(2k+1) (natural
+ *     order), psi_t a primitive 2N-th root of unity mod t.  Plaintext
+ *     polynomials are uint32 [N] with coefficients in [0, t); when a
+ *     plaintext enters the ciphertext ring it is lifted to its centred
+ *     representative in (-t/2, t/2].
+ *   - Randomness is never drawn inside the library: the caller passes the
+ *     secret key, the uniform polynomials and the errors.
+ *   - "d_" arguments are device pointers on the library's current HIP device,
+ *     "stream" is a hipStream_t (NULL = the default stream).  Device work is
+ *     enqueued on the stream and the call returns; results are ready when the
+ *     stream is synchronised.  Calls named "*_sync" or returning host values
+ *     synchronise the stream themselves.
+ *   - The caller owns every buffer it passes; the library owns its handles
+ *     and the device memory behind them until the matching *_destroy.
+ *   - Every function returns PEPSI_OK (0) or a negative pepsi_status; the
+ *     thread's last message is in pepsi_last_error().  A protocol failure
+ *     (cuckoo insertion or server bin overflow) is an error, never a silently
+ *     wrong answer.
+ */
+#ifndef PEPSI_H
+#define PEPSI_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PEPSI_OK = 0,
+  PEPSI_E_ARG = -1,          /* null or inconsistent argument                          */
+  PEPSI_E_PARAMS = -2,       /* unsupported parameters (N, L, h, code length, ...)     */
+  PEPSI_E_CUCKOO = -3,       /* client insertion needs more evictions than allowed
+                                (cuckoo hashing without a stash, Sec. 3.3 / 4.1)       */
+  PEPSI_E_BIN_OVERFLOW = -4, /* a server bin holds more than mu elements (Sec. 4.1)    */
+  PEPSI_E_RANGE = -5,        /* item out of range or duplicated                        */
+  PEPSI_E_NOMEM = -6,        /* device or host allocation failed                       */
+  PEPSI_E_DEVICE = -7        /* a HIP call failed (message names it)                   */
+} pepsi_status;
+
+/* Message of the calling thread's last failure ("" if none). */
+const char* pepsi_last_error(void);
+
+/* ------------------------------------------------------------------ */
+/* Parameters (Table "notation"; eq. (1) for the code length)          */
+/* ------------------------------------------------------------------ */
+typedef struct pepsi_params pepsi_params;
+
+typedef struct {
+  uint32_t log_n;          /* N = 2^log_n = number of bins b; 10..14                   */
+  uint32_t n_q;            /* L, number of ciphertext primes; 1..8                     */
+  uint32_t h;              /* Hamming weight of the constant-weight code; 1..16        */
+  uint32_t item_bits;      /* element bit length (effective bitlength); 1..32          */
+  uint32_t mu;             /* server maximum bin load                                  */
+  uint32_t n_hash;         /* number of hash functions k (3 in the paper)             */
+  uint32_t max_evictions;  /* cuckoo eviction limit per insertion                     */
+  uint32_t reserved;       /* must be 0                                                */
+  uint64_t hash_seed;      /* seed of the hash functions H_1..H_k                      */
+} pepsi_params_desc;
+
+#define PEPSI_MAX_PRIMES 17
+
+typedef struct {
+  uint32_t n, n_q, n_aux;  /* N, L and the auxiliary primes K used inside products      */
+  uint32_t h, ell, mu;     /* ell = code length from eq. (1)                           */
+  uint32_t item_bits, n_hash;
+  uint64_t t;              /* 65537                                                    */
+  uint64_t primes[PEPSI_MAX_PRIMES];  /* q_0..q_{L-1}, then the K auxiliary primes     */
+  uint64_t psi[PEPSI_MAX_PRIMES];     /* primitive 2N-th roots used by the NTTs        */
+  uint32_t psi_t;          /* primitive 2N-th root mod t defining the slot order       */
+  uint32_t q_bits;         /* bit length of Q                                          */
+  uint64_t query_bytes;    /* ell * 2 * L * N * 8: one client request                  */
+  uint64_t ct_bytes;       /* 2 * L * N * 8                                            */
+  uint64_t rlk_bytes;      /* L * 2 * L * N * 8                                        */
+  uint64_t cache_bytes;    /* mu * ell * L * N * 8: the server plaintexts in NTT form  */
+} pepsi_params_info;
+
+/* Creates a parameter set on the current HIP device: primes, NTT tables and RNS
+ * constants are built on the host and copied to device memory owned by the
+ * handle.  Errors: PEPSI_E_ARG (null), PEPSI_E_PARAMS (ranges above, or a code
+ * length above 65534), PEPSI_E_NOMEM / PEPSI_E_DEVICE. */
+int pepsi_params_create(const pepsi_params_desc* desc, pepsi_params** out);
+int pepsi_params_get_info(const pepsi_params* params, pepsi_params_info* out);
+void pepsi_params_destroy(pepsi_params* params);
+/* Number of coefficients that took the exact multiword path of a rounding
+ * decision (base extension, rescale, decryption) since the handle was created;
+ * diagnostic only.  Synchronises the device. */
+int pepsi_exact_path_count(const pepsi_params* params, uint64_t* out);
+
+/* ------------------------------------------------------------------ */
+/* Client preparation (Alg. 6 ClientDataPrep), host memory             */
+/* ------------------------------------------------------------------ */
+/* Cuckoo hashing of m distinct items (< 2^item_bits) into N bins with the
+ * hash functions H_i(x) = mix64(x ^ (seed + i * 0x9E3779B97F4A7C15)) mod N,
+ * i = 1..k, mix64 the SplitMix64 finaliser; an evicted element moves on to its
+ * next hash function cyclically (Sec. 3.3).  table [N] receives the item of
+ * each bin, valid [N] 1 for a real item and 0 for a dummy.
+ * Errors: PEPSI_E_RANGE (duplicate / out of range), PEPSI_E_CUCKOO. */
+int pepsi_client_table(const pepsi_params* params, const uint32_t* items, uint64_t m,
+                       uint32_t* table, uint8_t* valid);
+/* Constant-weight encoding (Sec. 3.2, perfect mapping read as the
+ * combinatorial number system) of a binned table and batching across bins:
+ * planes [ell][N], planes[j][k] = 1 iff bit j of the codeword of bin k is set
+ * (dummies encode to the all-zero word).  These are the slot vectors of the
+ * ell client plaintexts pt_c[j]. */
+int pepsi_codeword_planes(const pepsi_params* params, const uint32_t* table,
+                          const uint8_t* valid, uint32_t* planes);
+
+/* ------------------------------------------------------------------ */
+/* Keys, encryption, decryption (FV, Sec. 3.1), device memory          */
+/* ------------------------------------------------------------------ */
+/* Secret-key encryption of count slot vectors (Alg. 6):
+ *   ct = ([-(a s + e) + Delta [m]_t]_Q, a),  m = encode(slots), Delta = floor(Q / t).
+ * d_sk int8 [N] in {-1,0,1}; d_slots uint32 [count][N] (values mod t);
+ * d_a uint64 [count][L][N] uniform residues; d_e int32 [count][N];
+ * d_ct uint64 [count][2][L][N]. */
+int pepsi_encrypt(const pepsi_params* params, const int8_t* d_sk, const uint32_t* d_slots,
+                  const uint64_t* d_a, const int32_t* d_e, uint32_t count, uint64_t* d_ct,
+                  void* stream);
+/* Relinearisation key with the RNS gadget (the paper relies on its library's
+ * relinearisation and does not describe it):
+ *   rlk_i = ([-(a_i s + e_i) + (Q/q_i) s^2]_Q, a_i),  i in [L].
+ * d_a uint64 [L][L][N], d_e int32 [L][N], d_rlk uint64 [L][2][L][N]. */
+int pepsi_keygen_relin(const pepsi_params* params, const int8_t* d_sk, const uint64_t* d_a,
+                       const int32_t* d_e, uint64_t* d_rlk, void* stream);
+/* Decryption and decoding: slots = decode([round(t/Q [c0 + c1 s]_Q)]_t).
+ * d_ct [count][2][L][N] -> d_slots uint32 [count][N] in [0, t). */
+int pepsi_decrypt(const pepsi_params* params, const int8_t* d_sk, const uint64_t* d_ct,
+                  uint32_t count, uint32_t* d_slots, void* stream);
+/* Invariant-noise budget in bits of one ciphertext:
+ *   bitlen(Q) - bitlen(max_k |[t (c0 + c1 s)]_Q|_k) - 1   (decryption is correct iff > 0).
+ * Synchronises the stream; *budget is a host int. */
+int pepsi_noise_budget(const pepsi_params* params, const int8_t* d_sk, const uint64_t* d_ct,
+                       int32_t* budget, void* stream);
+
+/* ------------------------------------------------------------------ */
+/* Server preparation and computation (Alg. 6 ServerDataPrep; Alg. 1,  */
+/* 2 and 5)                                                            */
+/* ------------------------------------------------------------------ */
+typedef struct pepsi_server pepsi_server;
+
+#define PEPSI_SERVER_CACHE_PLAINTEXTS 1u  /* keep every server plaintext in NTT form in HBM */
+
+typedef struct {
+  uint32_t mu;             /* batches of the table                                     */
+  uint32_t max_load;       /* fullest bin; batches at or above it hold only dummies    */
+  uint32_t cached;         /* 1 if the plaintext cache is resident                     */
+  uint32_t reserved;
+  uint64_t device_bytes;   /* device memory held by the handle                         */
+} pepsi_server_info;
+
+/* Server preparation: each of the n distinct items (< 2^item_bits) is appended to
+ * each distinct bin among H_1..H_k (input order inside a bin), bins are padded to
+ * mu with dummies, every entry is constant-weight encoded, and the codeword
+ * positions uint16 [mu][N][h] (0xFFFF for dummies) are copied to device memory
+ * owned by the handle.  With PEPSI_SERVER_CACHE_PLAINTEXTS every server plaintext
+ * pt_s[i'][j] is also batch-encoded and transformed into NTT form once, here
+ * (mu * ell * L * N * 8 bytes of HBM); otherwise each evaluation regenerates them.
+ * Synchronises the stream.  Errors: PEPSI_E_RANGE, PEPSI_E_BIN_OVERFLOW,
+ * PEPSI_E_NOMEM. */
+int pepsi_server_create(const pepsi_params* params, const uint32_t* items, uint64_t n,
+                        uint32_t flags, void* stream, pepsi_server** out);
+int pepsi_server_get_info(const pepsi_server* server, pepsi_server_info* out);
+/* Copy of the codeword-position table uint16 [mu][N][h] to host memory. */
+int pepsi_server_codewords(const pepsi_server* server, uint16_t* out);
+void pepsi_server_destroy(pepsi_server* server);
+
+/* Server computation, PSI-Cardinality (Alg. 5 with unit server values) or the
+ * indicator of Alg. 2 when d_mask is NULL:
+ *   for every server batch i':  S = sum_j ct_j (*) pt_s[i'][j]          (Alg. 1, h')
+ *                               e = prod_{r in [h]} (S + Delta [-r]_t)  (balanced tree,
+ *                                   relinearised after every product)
+ *   out = [(h!)^-1]_t * sum_i' e  (+ Delta [encode(mask)]_t on c0 when d_mask != NULL).
+ * d_cts uint64 [ell][2][L][N] (the client request), d_rlk [L][2][L][N],
+ * d_mask uint32 [N] with sum = 0 mod t (or NULL), d_out [2][L][N]; all coefficient
+ * form.  Workspace is allocated by the handle on first use and kept. */
+int pepsi_server_eval(pepsi_server* server, const uint64_t* d_cts, const uint64_t* d_rlk,
+                      const uint32_t* d_mask, uint64_t* d_out, void* stream);
+/* The same over server batches [batch_begin, batch_end) only; with finalize = 0
+ * the output is sum_i' e (no (h!)^-1, no mask).  Sums over disjoint ranges add
+ * up to the full sum mod Q. */
+int pepsi_server_eval_range(pepsi_server* server, const uint64_t* d_cts, const uint64_t* d_rlk,
+                            uint32_t batch_begin, uint32_t batch_end, uint32_t finalize,
+                            const uint32_t* d_mask, uint64_t* d_out, void* stream);
+
+/* Event timing of a server's evaluations, for measurement.  While enabled,
+ * every select-and-sum launch (the kernel that streams the server plaintexts)
+ * and every whole evaluation is bracketed by HIP events on the evaluation's
+ * stream.  The call synchronises the device, folds finished event pairs into
+ * the totals, then applies reset (zero the totals) and enable (1 on, 0 off). */
+typedef struct {
+  uint64_t select_sum_launches;
+  uint64_t select_sum_bytes;   /* algorithmic bytes: plaintexts + client ciphertexts
+                                  read once + sums written, per launch */
+  double select_sum_ms;
+  uint64_t evals;
+  double eval_ms;
+} pepsi_timing;
+int pepsi_server_timing(pepsi_server* server, int enable, int reset, pepsi_timing* out);
+
+/* ------------------------------------------------------------------ */
+/* Single evaluator steps                                              */
+/* ------------------------------------------------------------------ */
+/* Negacyclic NTT of rows [rows][N] in place; row r is taken modulo prime
+ * (first_prime + r % n_primes) of the primes listed in pepsi_params_info.
+ * Forward output order: out[k] = a(psi^(2 brv(k) + 1)) (bit-reversed); inverse
+ * = its exact inverse.  Inputs must be reduced (< the row's prime). */
+int pepsi_ntt(const pepsi_params* params, uint64_t* d_data, uint32_t rows, uint32_t first_prime,
+              uint32_t n_primes, int inverse, void* stream);
+/* Batch encoding over Z_t (Sec. 4.1, "batching"): slots [rows][N] -> plaintext
+ * polynomials [rows][N], and back. */
+int pepsi_encode(const pepsi_params* params, const uint32_t* d_slots, uint32_t rows,
+                 uint32_t* d_poly, void* stream);
+int pepsi_decode(const pepsi_params* params, const uint32_t* d_poly, uint32_t rows,
+                 uint32_t* d_slots, void* stream);
+/* Select-and-sum of one server batch (Alg. 1, first line, over all bins):
+ *   out = sum_j ct_j (*) p_j,  p_j = encode(slots with slot k = [j in cw[k][0..h)]).
+ * d_cts [ell][2][L][N], d_cw uint16 [N][h] (0xFFFF = no position), d_out [2][L][N]. */
+int pepsi_select_sum(const pepsi_params* params, const uint64_t* d_cts, const uint16_t* d_cw,
+                     uint64_t* d_out, void* stream);
+/* FV ciphertext product without relinearisation (Sec. 3.1, "Multiplication"):
+ *   out_k = [round(t/Q * (x (x) y)_k)]_Q,  x, y lifted to centred integers,
+ *   (x (x) y) = (x0 y0, x0 y1 + x1 y0, x1 y1) over Z[X]/(X^N + 1).
+ * d_x, d_y [2][L][N]; d_out [3][L][N]. */
+int pepsi_multiply(const pepsi_params* params, const uint64_t* d_x, const uint64_t* d_y,
+                   uint64_t* d_out, void* stream);
+/* Relinearisation with the RNS gadget: digits D_i = [d2 (Q/q_i)^-1]_{q_i} in
+ * [0, q_i); out = (d0 + sum_i D_i rlk_i0, d1 + sum_i D_i rlk_i1).
+ * d_ct3 [3][L][N], d_rlk [L][2][L][N], d_out [2][L][N]. */
+int pepsi_relin(const pepsi_params* params, const uint64_t* d_ct3, const uint64_t* d_rlk,
+                uint64_t* d_out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PEPSI_H */

@@ -44,6 +44,8 @@ def lib():
             "or_decode": (None, [vp, u32p, u32p]),
             "or_encrypt": (None, [vp, i8p, u32p, u64p, i32p, u64p]),
             "or_decrypt_poly": (None, [vp, i8p, u64p, u32p]),
+            "or_encode_many": (None, [vp, u32p, i, u32p]),
+            "or_encrypt_many": (None, [vp, i8p, u32p, u64p, i32p, i, u64p]),
             "or_noise_budget": (i, [vp, i8p, u64p]),
             "or_keygen_relin": (None, [vp, i8p, u64p, i32p, u64p]),
             "or_mul_plain": (None, [vp, u64p, u32p, u64p]),
@@ -119,6 +121,19 @@ class Context:
         lib().or_encrypt(self._h, _c(sk, np.int8), _c(m_poly, np.uint32), _c(a, np.uint64),
                          _c(e, np.int32), ct)
         return ct
+
+    def encode_many(self, slots):
+        slots = _c(slots, np.uint32)
+        out = np.zeros_like(slots)
+        lib().or_encode_many(self._h, slots, slots.shape[0], out)
+        return out
+
+    def encrypt_many(self, sk, m_polys, a, e):
+        m_polys = _c(m_polys, np.uint32)
+        out = np.zeros((m_polys.shape[0], 2, self.L, self.n), dtype=np.uint64)
+        lib().or_encrypt_many(self._h, _c(sk, np.int8), m_polys, _c(a, np.uint64), _c(e, np.int32),
+                              m_polys.shape[0], out)
+        return out
 
     def decrypt_poly(self, sk, ct):
         out = np.zeros(self.n, dtype=np.uint32)

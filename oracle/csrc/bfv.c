@@ -355,3 +355,19 @@ void or_relin(const or_ctx* c, const uint64_t* ct3, const uint64_t* rlk, uint64_
   }
   free(D); free(Dj); free(prod);
 }
+
+/* ---------- many at once (independent, so spread over threads) ---------- */
+
+void or_encode_many(const or_ctx* c, const uint32_t* slots, int count, uint32_t* polys) {
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int i = 0; i < count; i++)
+    or_encode(c, slots + (size_t)i * c->n, polys + (size_t)i * c->n);
+}
+
+void or_encrypt_many(const or_ctx* c, const int8_t* sk, const uint32_t* m_polys, const uint64_t* a,
+                     const int32_t* e, int count, uint64_t* ct) {
+#pragma omp parallel for schedule(dynamic, 2)
+  for (int i = 0; i < count; i++)
+    or_encrypt(c, sk, m_polys + (size_t)i * c->n, a + (size_t)i * c->L * c->n,
+               e + (size_t)i * c->n, ct + (size_t)i * 2 * c->L * c->n);
+}

@@ -63,6 +63,10 @@ void or_decode(const or_ctx* c, const uint32_t* poly, uint32_t* slots);
 /* ct = ([-(a*s+e) + Delta*[m]_t]_Q, a); a: [L][N] residues, e: [N] small. */
 void or_encrypt(const or_ctx* c, const int8_t* sk, const uint32_t* m_poly,
                 const uint64_t* a, const int32_t* e, uint64_t* ct);
+/* count independent encodings / encryptions (threads over the count) */
+void or_encode_many(const or_ctx* c, const uint32_t* slots, int count, uint32_t* polys);
+void or_encrypt_many(const or_ctx* c, const int8_t* sk, const uint32_t* m_polys, const uint64_t* a,
+                     const int32_t* e, int count, uint64_t* ct);
 /* m = [round(t/Q * [c0 + c1*s]_Q)]_t, coefficients in [0,t). */
 void or_decrypt_poly(const or_ctx* c, const int8_t* sk, const uint64_t* ct, uint32_t* m_poly);
 /* invariant-noise budget in bits: bitlen(Q) - bitlen(max |[t*(c0+c1*s)]_Q|) - 1 */

@@ -124,7 +124,8 @@ void or_server_eval(const or_ctx* c, int ell, int h, int mu_begin, int mu_end,
   size_t csz = (size_t)2 * L * n;
   uint64_t* E = eval_cts(c, ell, cts);
   memset(out, 0, sizeof(uint64_t) * csz);
-#pragma omp parallel
+  /* few batches: run them one after another so the products inside use every core */
+#pragma omp parallel if (mu_end - mu_begin >= 8)
   {
     uint64_t* S = (uint64_t*)malloc(sizeof(uint64_t) * csz);
     uint64_t* e = (uint64_t*)malloc(sizeof(uint64_t) * csz);

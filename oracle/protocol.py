@@ -49,10 +49,7 @@ def server_prepare(cfg: Config, items):
 
 def encrypt_planes(ctx: Context, sk, planes, a, e):
     """a: [l][L][N] uniform residues, e: [l][N] errors -> cts [l][2][L][N]."""
-    out = np.zeros((planes.shape[0], 2, ctx.L, ctx.n), dtype=np.uint64)
-    for j in range(planes.shape[0]):
-        out[j] = ctx.encrypt(sk, ctx.encode(planes[j]), a[j], e[j])
-    return out
+    return ctx.encrypt_many(sk, ctx.encode_many(planes), a, e)
 
 
 def plaintext_membership(client_table, client_valid, server_table, server_valid):

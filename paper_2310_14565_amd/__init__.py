@@ -1,0 +1,265 @@
+"""Python binding of libpepsi.so: the gfx950 server computation of PEPSI PSI-cardinality.
+
+Argument marshalling only: every step runs in the library's HIP kernels.  Device
+buffers are torch tensors on the current HIP device (torch is used for device
+memory and streams); host buffers are numpy arrays.  Names follow include/pepsi.h
+without the ``pepsi_`` prefix.  The library is loaded from this directory; if it
+is missing, importing the binding raises (there is no other implementation).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpepsi.so")
+
+PEPSI_SERVER_CACHE_PLAINTEXTS = 1
+MAX_PRIMES = 17
+
+
+class PepsiError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"pepsi error {code}: {msg}")
+        self.code = code
+
+
+class ParamsDesc(C.Structure):
+    _fields_ = [("log_n", C.c_uint32), ("n_q", C.c_uint32), ("h", C.c_uint32),
+                ("item_bits", C.c_uint32), ("mu", C.c_uint32), ("n_hash", C.c_uint32),
+                ("max_evictions", C.c_uint32), ("reserved", C.c_uint32),
+                ("hash_seed", C.c_uint64)]
+
+
+class ParamsInfo(C.Structure):
+    _fields_ = [("n", C.c_uint32), ("n_q", C.c_uint32), ("n_aux", C.c_uint32),
+                ("h", C.c_uint32), ("ell", C.c_uint32), ("mu", C.c_uint32),
+                ("item_bits", C.c_uint32), ("n_hash", C.c_uint32), ("t", C.c_uint64),
+                ("primes", C.c_uint64 * MAX_PRIMES), ("psi", C.c_uint64 * MAX_PRIMES),
+                ("psi_t", C.c_uint32), ("q_bits", C.c_uint32),
+                ("query_bytes", C.c_uint64), ("ct_bytes", C.c_uint64),
+                ("rlk_bytes", C.c_uint64), ("cache_bytes", C.c_uint64)]
+
+
+class ServerInfo(C.Structure):
+    _fields_ = [("mu", C.c_uint32), ("max_load", C.c_uint32), ("cached", C.c_uint32),
+                ("reserved", C.c_uint32), ("device_bytes", C.c_uint64)]
+
+
+class Timing(C.Structure):
+    _fields_ = [("select_sum_launches", C.c_uint64), ("select_sum_bytes", C.c_uint64),
+                ("select_sum_ms", C.c_double), ("evals", C.c_uint64), ("eval_ms", C.c_double)]
+
+
+_SIGS = {
+    "pepsi_last_error": (C.c_char_p, []),
+    "pepsi_params_create": (C.c_int, [C.POINTER(ParamsDesc), C.POINTER(C.c_void_p)]),
+    "pepsi_params_get_info": (C.c_int, [C.c_void_p, C.POINTER(ParamsInfo)]),
+    "pepsi_params_destroy": (None, [C.c_void_p]),
+    "pepsi_exact_path_count": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint64)]),
+    "pepsi_client_table": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p]),
+    "pepsi_codeword_planes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pepsi_encrypt": (C.c_int, [C.c_void_p] * 5 + [C.c_uint32, C.c_void_p, C.c_void_p]),
+    "pepsi_keygen_relin": (C.c_int, [C.c_void_p] * 6),
+    "pepsi_decrypt": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]),
+    "pepsi_noise_budget": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int32), C.c_void_p]),
+    "pepsi_server_create": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_uint32, C.c_void_p,
+                                      C.POINTER(C.c_void_p)]),
+    "pepsi_server_get_info": (C.c_int, [C.c_void_p, C.POINTER(ServerInfo)]),
+    "pepsi_server_codewords": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "pepsi_server_destroy": (None, [C.c_void_p]),
+    "pepsi_server_eval": (C.c_int, [C.c_void_p] * 6),
+    "pepsi_server_timing": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(Timing)]),
+    "pepsi_server_eval_range": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32,
+                                          C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pepsi_ntt": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int,
+                            C.c_void_p]),
+    "pepsi_encode": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]),
+    "pepsi_decode": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]),
+    "pepsi_select_sum": (C.c_int, [C.c_void_p] * 5),
+    "pepsi_multiply": (C.c_int, [C.c_void_p] * 5),
+    "pepsi_relin": (C.c_int, [C.c_void_p] * 5),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2310_14565_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise PepsiError(rc, lib().pepsi_last_error().decode())
+
+
+def _dev(t):
+    """Device pointer of a contiguous torch tensor (None passes NULL)."""
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _host(a):
+    if not a.flags["C_CONTIGUOUS"]:
+        raise ValueError("array must be C-contiguous")
+    return C.c_void_p(a.ctypes.data)
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Params:
+    """A parameter set on the current HIP device (pepsi_params_*)."""
+
+    def __init__(self, log_n: int, n_q: int, h: int, item_bits: int, mu: int, n_hash: int = 3,
+                 max_evictions: int = 500, hash_seed: int = 0x5EED):
+        d = ParamsDesc(log_n, n_q, h, item_bits, mu, n_hash, max_evictions, 0, hash_seed)
+        h_ = C.c_void_p()
+        _check(lib().pepsi_params_create(C.byref(d), C.byref(h_)))
+        self._h = h_
+        info = ParamsInfo()
+        _check(lib().pepsi_params_get_info(self._h, C.byref(info)))
+        self.info = info
+        self.n, self.L, self.K = info.n, info.n_q, info.n_aux
+        self.h, self.ell, self.mu = info.h, info.ell, info.mu
+        self.primes = [int(info.primes[i]) for i in range(self.L + self.K)]
+        self.q_primes = self.primes[:self.L]
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pepsi_params_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def exact_path_count(self) -> int:
+        v = C.c_uint64()
+        _check(lib().pepsi_exact_path_count(self._h, C.byref(v)))
+        return int(v.value)
+
+    # client preparation (host numpy)
+    def client_table(self, items: np.ndarray):
+        items = np.ascontiguousarray(items, dtype=np.uint32)
+        table = np.zeros(self.n, np.uint32)
+        valid = np.zeros(self.n, np.uint8)
+        _check(lib().pepsi_client_table(self._h, _host(items), items.shape[0], _host(table), _host(valid)))
+        return table, valid
+
+    def codeword_planes(self, table: np.ndarray, valid: np.ndarray):
+        planes = np.zeros((self.ell, self.n), np.uint32)
+        _check(lib().pepsi_codeword_planes(self._h, _host(np.ascontiguousarray(table, np.uint32)),
+                                           _host(np.ascontiguousarray(valid, np.uint8)), _host(planes)))
+        return planes
+
+    # device operations (torch tensors)
+    def encrypt(self, sk, slots, a, e, out, stream=None):
+        _check(lib().pepsi_encrypt(self._h, _dev(sk), _dev(slots), _dev(a), _dev(e), slots.shape[0],
+                                   _dev(out), _stream(stream)))
+
+    def keygen_relin(self, sk, a, e, out, stream=None):
+        _check(lib().pepsi_keygen_relin(self._h, _dev(sk), _dev(a), _dev(e), _dev(out), _stream(stream)))
+
+    def decrypt(self, sk, ct, out_slots, stream=None):
+        count = ct.shape[0] if ct.dim() == 4 else 1
+        _check(lib().pepsi_decrypt(self._h, _dev(sk), _dev(ct), count, _dev(out_slots), _stream(stream)))
+
+    def noise_budget(self, sk, ct, stream=None) -> int:
+        b = C.c_int32()
+        _check(lib().pepsi_noise_budget(self._h, _dev(sk), _dev(ct), C.byref(b), _stream(stream)))
+        return int(b.value)
+
+    def ntt(self, data, rows: int, first_prime: int, n_primes: int, inverse: bool, stream=None):
+        _check(lib().pepsi_ntt(self._h, _dev(data), rows, first_prime, n_primes, 1 if inverse else 0,
+                               _stream(stream)))
+
+    def encode(self, slots, out, stream=None):
+        _check(lib().pepsi_encode(self._h, _dev(slots), slots.shape[0], _dev(out), _stream(stream)))
+
+    def decode(self, poly, out, stream=None):
+        _check(lib().pepsi_decode(self._h, _dev(poly), poly.shape[0], _dev(out), _stream(stream)))
+
+    def select_sum(self, cts, cw, out, stream=None):
+        _check(lib().pepsi_select_sum(self._h, _dev(cts), _dev(cw), _dev(out), _stream(stream)))
+
+    def multiply(self, x, y, out, stream=None):
+        _check(lib().pepsi_multiply(self._h, _dev(x), _dev(y), _dev(out), _stream(stream)))
+
+    def relin(self, ct3, rlk, out, stream=None):
+        _check(lib().pepsi_relin(self._h, _dev(ct3), _dev(rlk), _dev(out), _stream(stream)))
+
+
+class Server:
+    """The server's prepared set on the device (pepsi_server_*)."""
+
+    def __init__(self, params: Params, items: np.ndarray, cache_plaintexts: bool = False, stream=None):
+        items = np.ascontiguousarray(items, dtype=np.uint32)
+        h_ = C.c_void_p()
+        flags = PEPSI_SERVER_CACHE_PLAINTEXTS if cache_plaintexts else 0
+        _check(lib().pepsi_server_create(params.handle, _host(items), items.shape[0], flags,
+                                         _stream(stream), C.byref(h_)))
+        self._h = h_
+        self.params = params
+        info = ServerInfo()
+        _check(lib().pepsi_server_get_info(self._h, C.byref(info)))
+        self.max_load, self.cached, self.device_bytes = info.max_load, bool(info.cached), info.device_bytes
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pepsi_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def codewords(self) -> np.ndarray:
+        p = self.params
+        out = np.zeros((p.mu, p.n, p.h), np.uint16)
+        _check(lib().pepsi_server_codewords(self._h, _host(out)))
+        return out
+
+    def eval(self, cts, rlk, mask, out, stream=None):
+        _check(lib().pepsi_server_eval(self._h, _dev(cts), _dev(rlk), _dev(mask), _dev(out), _stream(stream)))
+
+    def timing(self, enable: bool, reset: bool = False) -> Timing:
+        t = Timing()
+        _check(lib().pepsi_server_timing(self._h, 1 if enable else 0, 1 if reset else 0, C.byref(t)))
+        return t
+
+    def eval_range(self, cts, rlk, begin: int, end: int, finalize: bool, mask, out, stream=None):
+        _check(lib().pepsi_server_eval_range(self._h, _dev(cts), _dev(rlk), begin, end,
+                                             1 if finalize else 0, _dev(mask), _dev(out), _stream(stream)))

@@ -1,0 +1,862 @@
+// C-ABI of the PEPSI server computation on gfx950 (see include/pepsi.h).
+#include "../../include/pepsi.h"
+
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <unordered_set>
+#include <vector>
+
+#include "kernels.hpp"
+#include "params.hpp"
+#include "protocol.hpp"
+
+using namespace pepsi;
+
+// ------------------------------------------------------------------ errors
+namespace {
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(PEPSI_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));     \
+  } while (0)
+
+inline hipStream_t S(void* s) { return static_cast<hipStream_t>(s); }
+
+// Device buffer that only grows; growing waits for the device first.
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  int ensure(size_t bytes) {
+    if (bytes <= cap) return 0;
+    if (p) {
+      HIPCHK(hipDeviceSynchronize());
+      HIPCHK(hipFree(p));
+      p = nullptr;
+      cap = 0;
+    }
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      p = nullptr;
+      return fail(PEPSI_E_NOMEM, "hipMalloc of %zu bytes failed", bytes);
+    }
+    cap = bytes;
+    return 0;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+  template <class T> T* as(size_t word_offset = 0) const {
+    return reinterpret_cast<T*>(p) + word_offset;
+  }
+};
+}  // namespace
+
+extern "C" const char* pepsi_last_error(void) { return g_err.c_str(); }
+
+// ------------------------------------------------------------------ params
+struct pepsi_params {
+  HostParams H;
+  int device = 0;
+  Tables T{};
+  DevBuf consts, tw, twt, fallback;
+  DevBuf scratch;                 // single-step operations
+  std::vector<TensorJob> one_job;
+  DevBuf job_dev;
+  size_t words_poly() const { return (size_t)H.n; }
+};
+
+namespace {
+
+uint64_t powm(uint64_t a, uint64_t e, uint64_t m) {
+  uint64_t r = 1 % m;
+  a %= m;
+  for (; e; e >>= 1) {
+    if (e & 1) r = (uint64_t)(((u128)r * a) % m);
+    a = (uint64_t)(((u128)a * a) % m);
+  }
+  return r;
+}
+uint32_t brv(uint32_t k, int logn) {
+  uint32_t r = 0;
+  for (int i = 0; i < logn; ++i) r |= ((k >> i) & 1u) << (logn - 1 - i);
+  return r;
+}
+
+int upload_tables(pepsi_params* P) {
+  const HostParams& H = P->H;
+  const int n = H.n, np = H.L + H.K;
+  std::vector<uint64_t> tw((size_t)4 * np * n);
+  uint64_t* psi_rev = tw.data();
+  uint64_t* psi_rev_q = psi_rev + (size_t)np * n;
+  uint64_t* ipsi_rev = psi_rev_q + (size_t)np * n;
+  uint64_t* ipsi_rev_q = ipsi_rev + (size_t)np * n;
+  for (int i = 0; i < np; ++i) {
+    const uint64_t p = H.primes[i];
+    const uint64_t psi = H.psi[i], ipsi = powm(psi, p - 2, p);
+    for (int k = 0; k < n; ++k) {
+      const uint64_t e = brv(k, H.logn);
+      const uint64_t w = powm(psi, e, p), iw = powm(ipsi, e, p);
+      psi_rev[(size_t)i * n + k] = w;
+      psi_rev_q[(size_t)i * n + k] = shoup_companion(w, p);
+      ipsi_rev[(size_t)i * n + k] = iw;
+      ipsi_rev_q[(size_t)i * n + k] = shoup_companion(iw, p);
+    }
+  }
+  std::vector<uint32_t> twt((size_t)2 * n);
+  const uint64_t ipt = powm(H.psi_t, PEPSI_T - 2, PEPSI_T);
+  for (int k = 0; k < n; ++k) {
+    const uint64_t e = brv(k, H.logn);
+    twt[k] = (uint32_t)powm(H.psi_t, e, PEPSI_T);
+    twt[n + k] = (uint32_t)powm(ipt, e, PEPSI_T);
+  }
+  int rc;
+  if ((rc = P->consts.ensure(sizeof(Consts)))) return rc;
+  if ((rc = P->tw.ensure(tw.size() * 8))) return rc;
+  if ((rc = P->twt.ensure(twt.size() * 4))) return rc;
+  if ((rc = P->fallback.ensure(64))) return rc;
+  HIPCHK(hipMemcpy(P->consts.p, &H.consts, sizeof(Consts), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(P->tw.p, tw.data(), tw.size() * 8, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(P->twt.p, twt.data(), twt.size() * 4, hipMemcpyHostToDevice));
+  HIPCHK(hipMemset(P->fallback.p, 0, 64));
+  P->T.c = P->consts.as<Consts>();
+  P->T.psi_rev = P->tw.as<uint64_t>();
+  P->T.psi_rev_shoup = P->tw.as<uint64_t>((size_t)np * n);
+  P->T.ipsi_rev = P->tw.as<uint64_t>((size_t)2 * np * n);
+  P->T.ipsi_rev_shoup = P->tw.as<uint64_t>((size_t)3 * np * n);
+  P->T.psit_rev = P->twt.as<uint32_t>();
+  P->T.ipsit_rev = P->twt.as<uint32_t>(n);
+  return 0;
+}
+
+}  // namespace
+
+extern "C" int pepsi_params_create(const pepsi_params_desc* d, pepsi_params** out) {
+  if (!d || !out) return fail(PEPSI_E_ARG, "null argument");
+  *out = nullptr;
+  if (d->reserved) return fail(PEPSI_E_ARG, "reserved must be 0");
+  pepsi_params* P = new pepsi_params();
+  char err[256] = {0};
+  int rc = build_host_params((int)d->log_n, (int)d->n_q, (int)d->h, (int)d->item_bits, (int)d->mu,
+                             (int)d->n_hash, d->hash_seed, (int)d->max_evictions, &P->H, err,
+                             sizeof(err));
+  if (rc) {
+    delete P;
+    return fail(rc, "%s", err);
+  }
+  if (hipGetDevice(&P->device) != hipSuccess) {
+    delete P;
+    return fail(PEPSI_E_DEVICE, "no HIP device");
+  }
+  if ((rc = upload_tables(P))) {
+    std::string msg = g_err;
+    pepsi_params_destroy(P);
+    return fail(rc, "%s", msg.c_str());
+  }
+  *out = P;
+  return PEPSI_OK;
+}
+
+extern "C" int pepsi_params_get_info(const pepsi_params* P, pepsi_params_info* o) {
+  if (!P || !o) return fail(PEPSI_E_ARG, "null argument");
+  const HostParams& H = P->H;
+  memset(o, 0, sizeof(*o));
+  o->n = H.n; o->n_q = H.L; o->n_aux = H.K; o->h = H.h; o->ell = H.ell; o->mu = H.mu;
+  o->item_bits = H.item_bits; o->n_hash = H.n_hash; o->t = PEPSI_T;
+  for (int i = 0; i < H.L + H.K; ++i) { o->primes[i] = H.primes[i]; o->psi[i] = H.psi[i]; }
+  o->psi_t = H.psi_t;
+  int bits = 0;
+  for (int w = PEPSI_MW - 1; w >= 0; --w)
+    if (H.consts.Qw.w[w]) { bits = 64 * w + 64 - __builtin_clzll(H.consts.Qw.w[w]); break; }
+  o->q_bits = bits;
+  const uint64_t n = H.n, L = H.L;
+  o->ct_bytes = 2 * L * n * 8;
+  o->query_bytes = (uint64_t)H.ell * o->ct_bytes;
+  o->rlk_bytes = L * o->ct_bytes;
+  o->cache_bytes = (uint64_t)H.mu * H.ell * L * n * 8;
+  return PEPSI_OK;
+}
+
+extern "C" void pepsi_params_destroy(pepsi_params* P) {
+  if (!P) return;
+  (void)hipDeviceSynchronize();
+  P->consts.release(); P->tw.release(); P->twt.release(); P->fallback.release();
+  P->scratch.release(); P->job_dev.release();
+  delete P;
+}
+
+extern "C" int pepsi_exact_path_count(const pepsi_params* P, uint64_t* out) {
+  if (!P || !out) return fail(PEPSI_E_ARG, "null argument");
+  uint32_t v = 0;
+  HIPCHK(hipDeviceSynchronize());
+  HIPCHK(hipMemcpy(&v, P->fallback.p, 4, hipMemcpyDeviceToHost));
+  *out = v;
+  return PEPSI_OK;
+}
+
+// ------------------------------------------------------------------ client preparation
+extern "C" int pepsi_client_table(const pepsi_params* P, const uint32_t* items, uint64_t m,
+                                  uint32_t* table, uint8_t* valid) {
+  if (!P || (!items && m) || !table || !valid) return fail(PEPSI_E_ARG, "null argument");
+  const HostParams& H = P->H;
+  std::unordered_set<uint32_t> seen;
+  for (uint64_t i = 0; i < m; ++i) {
+    if (H.item_bits < 32 && (items[i] >> H.item_bits)) return fail(PEPSI_E_RANGE, "item %llu out of range", (unsigned long long)i);
+    if (!seen.insert(items[i]).second) return fail(PEPSI_E_RANGE, "duplicate client item");
+  }
+  if (m > (uint64_t)H.n) return fail(PEPSI_E_CUCKOO, "more items than bins");
+  if (cuckoo_insert(items, m, H.n, H.hash_seed, H.n_hash, H.max_evictions, table, valid))
+    return fail(PEPSI_E_CUCKOO, "cuckoo insertion exceeded %d evictions", H.max_evictions);
+  return PEPSI_OK;
+}
+
+extern "C" int pepsi_codeword_planes(const pepsi_params* P, const uint32_t* table, const uint8_t* valid,
+                                     uint32_t* planes) {
+  if (!P || !table || !valid || !planes) return fail(PEPSI_E_ARG, "null argument");
+  const HostParams& H = P->H;
+  CwEncoder enc(H.ell, H.h);
+  memset(planes, 0, sizeof(uint32_t) * (size_t)H.ell * H.n);
+  std::vector<uint16_t> pos(H.h);
+  for (int k = 0; k < H.n; ++k) {
+    if (!valid[k]) continue;
+    if (H.item_bits < 32 && (table[k] >> H.item_bits)) return fail(PEPSI_E_RANGE, "item out of range");
+    enc.encode(table[k], pos.data());
+    for (int r = 0; r < H.h; ++r) planes[(size_t)pos[r] * H.n + k] = 1;
+  }
+  return PEPSI_OK;
+}
+
+// ------------------------------------------------------------------ keys and encryption
+extern "C" int pepsi_encrypt(const pepsi_params* Pc, const int8_t* sk, const uint32_t* slots,
+                             const uint64_t* a, const int32_t* e, uint32_t count, uint64_t* ct,
+                             void* stream) {
+  pepsi_params* P = const_cast<pepsi_params*>(Pc);
+  if (!P || !sk || !slots || !a || !e || !ct) return fail(PEPSI_E_ARG, "null argument");
+  if (!count) return PEPSI_OK;
+  const HostParams& H = P->H;
+  const size_t n = H.n, L = H.L;
+  // scratch: m (u32 count*n) | ahat (count*L*n) | shat (L*n)
+  const size_t w_m = (count * n + 1) / 2, w_ah = count * L * n, w_sh = L * n;
+  int rc = P->scratch.ensure((w_m + w_ah + w_sh) * 8);
+  if (rc) return rc;
+  uint32_t* m = P->scratch.as<uint32_t>();
+  uint64_t* ah = P->scratch.as<uint64_t>(w_m);
+  uint64_t* sh = ah + w_ah;
+  hipStream_t s = S(stream);
+  encode_slots(P->T, H.logn, slots, m, count, s);
+  ntt_forward(P->T, H.logn, a, LOAD_U64, ah, STORE_U64, (int)(count * L), (int)L, 0, s);
+  ntt_forward(P->T, H.logn, sk, LOAD_I8, sh, STORE_U64, (int)L, (int)L, 0, s);
+  pointwise_mul(P->T, H.consts, ah, sh, ah, (int)count, (int)L, true, s);
+  ntt_inverse(P->T, H.logn, ah, ah, (int)(count * L), (int)L, 0, s);
+  encrypt_finish(P->T, H.consts, m, ah, e, a, ct, (int)count, s);
+  HIPCHK(hipGetLastError());
+  return PEPSI_OK;
+}
+
+extern "C" int pepsi_keygen_relin(const pepsi_params* Pc, const int8_t* sk, const uint64_t* a,
+                                  const int32_t* e, uint64_t* rlk, void* stream) {
+  pepsi_params* P = const_cast<pepsi_params*>(Pc);
+  if (!P || !sk || !a || !e || !rlk) return fail(PEPSI_E_ARG, "null argument");
+  const HostParams& H = P->H;
+  const size_t n = H.n, L = H.L;
+  // scratch: shat (L n) | s2 (L n) | as (L L n)
+  int rc = P->scratch.ensure((2 * L * n + L * L * n) * 8);
+  if (rc) return rc;
+  uint64_t* sh = P->scratch.as<uint64_t>();
+  uint64_t* s2 = sh + L * n;
+  uint64_t* as = s2 + L * n;
+  hipStream_t s = S(stream);
+  ntt_forward(P->T, H.logn, sk, LOAD_I8, sh, STORE_U64, (int)L, (int)L, 0, s);
+  pointwise_mul(P->T, H.consts, sh, sh, s2, 1, (int)L, false, s);
+  ntt_inverse(P->T, H.logn, s2, s2, (int)L, (int)L, 0, s);
+  ntt_forward(P->T, H.logn, a, LOAD_U64, as, STORE_U64, (int)(L * L), (int)L, 0, s);
+  pointwise_mul(P->T, H.consts, as, sh, as, (int)L, (int)L, true, s);
+  ntt_inverse(P->T, H.logn, as, as, (int)(L * L), (int)L, 0, s);
+  keygen_finish(P->T, H.consts, s2, as, e, a, rlk, s);
+  HIPCHK(hipGetLastError());
+  return PEPSI_OK;
+}
+
+namespace {
+// x = c0 + c1 s (coefficient form) for count ciphertexts into scratch; returns pointer
+int phase_coeff(pepsi_params* P, const int8_t* sk, const uint64_t* ct, uint32_t count, uint64_t** x_out,
+                size_t extra_words, hipStream_t s) {
+  const HostParams& H = P->H;
+  const size_t n = H.n, L = H.L;
+  const size_t w_ch = count * 2 * L * n, w_sh = L * n, w_x = count * L * n;
+  int rc = P->scratch.ensure((w_ch + w_sh + w_x + extra_words) * 8);
+  if (rc) return rc;
+  uint64_t* ch = P->scratch.as<uint64_t>();
+  uint64_t* sh = ch + w_ch;
+  uint64_t* x = sh + w_sh;
+  ntt_forward(P->T, H.logn, ct, LOAD_U64, ch, STORE_U64, (int)(count * 2 * L), (int)L, 0, s);
+  ntt_forward(P->T, H.logn, sk, LOAD_I8, sh, STORE_U64, (int)L, (int)L, 0, s);
+  phase_ntt(P->T, H.consts, ch, sh, x, (int)count, s);
+  ntt_inverse(P->T, H.logn, x, x, (int)(count * L), (int)L, 0, s);
+  *x_out = x;
+  return 0;
+}
+}  // namespace
+
+extern "C" int pepsi_decrypt(const pepsi_params* Pc, const int8_t* sk, const uint64_t* ct,
+                             uint32_t count, uint32_t* slots, void* stream) {
+  pepsi_params* P = const_cast<pepsi_params*>(Pc);
+  if (!P || !sk || !ct || !slots) return fail(PEPSI_E_ARG, "null argument");
+  if (!count) return PEPSI_OK;
+  const HostParams& H = P->H;
+  hipStream_t s = S(stream);
+  uint64_t* x;
+  const size_t w_m = (count * (size_t)H.n + 1) / 2;
+  int rc = phase_coeff(P, sk, ct, count, &x, w_m, s);
+  if (rc) return rc;
+  uint32_t* m = reinterpret_cast<uint32_t*>(x + (size_t)count * H.L * H.n);
+  decrypt_round(P->T, H.consts, x, m, (int)count, P->fallback.as<uint32_t>(), s);
+  decode_slots(P->T, H.logn, m, slots, (int)count, s);
+  HIPCHK(hipGetLastError());
+  return PEPSI_OK;
+}
+
+extern "C" int pepsi_noise_budget(const pepsi_params* Pc, const int8_t* sk, const uint64_t* ct,
+                                  int32_t* budget, void* stream) {
+  pepsi_params* P = const_cast<pepsi_params*>(Pc);
+  if (!P || !sk || !ct || !budget) return fail(PEPSI_E_ARG, "null argument");
+  hipStream_t s = S(stream);
+  uint64_t* x;
+  int rc = phase_coeff(P, sk, ct, 1, &x, 1, s);
+  if (rc) return rc;
+  uint32_t* bits = reinterpret_cast<uint32_t*>(x + (size_t)P->H.L * P->H.n);
+  HIPCHK(hipMemsetAsync(bits, 0, 4, s));
+  noise_bits(P->T, P->H.consts, x, 1, bits, s);
+  uint32_t hb = 0;
+  HIPCHK(hipMemcpyAsync(&hb, bits, 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  pepsi_params_info info;
+  pepsi_params_get_info(P, &info);
+  *budget = (int32_t)info.q_bits - (int32_t)hb - 1;
+  return PEPSI_OK;
+}
+
+// ------------------------------------------------------------------ evaluation engine
+namespace {
+
+struct EventTimer {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  struct Pend { hipEvent_t a, b; int kind; uint64_t bytes; };
+  std::vector<Pend> pending;
+  pepsi_timing tot{};
+  hipEvent_t get() {
+    if (pool.empty()) {
+      hipEvent_t e;
+      (void)hipEventCreate(&e);
+      return e;
+    }
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  int fold() {
+    for (auto& p : pending) {
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess) return -1;
+      if (p.kind == 0) { tot.select_sum_launches++; tot.select_sum_ms += ms; tot.select_sum_bytes += p.bytes; }
+      else { tot.evals++; tot.eval_ms += ms; }
+      pool.push_back(p.a);
+      pool.push_back(p.b);
+    }
+    pending.clear();
+    return 0;
+  }
+  ~EventTimer() {
+    for (auto& p : pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+
+struct Operand { const uint64_t* q; const uint64_t* b; const uint64_t* alpha; };
+
+// Workspace for the equality product of up to TB server batches at once.
+struct Engine {
+  pepsi_params* P = nullptr;
+  int TB = 0, levels = 0;
+  std::vector<int> jobs_at;            // jobs per batch at each tree level
+  DevBuf chat, rlkhat, acc;            // query-level
+  DevBuf sq, scoef, sb, alpha, e;      // per tile
+  DevBuf d, c3, c3h, D, rcoef;         // per multiply
+  std::vector<DevBuf> rq, rb;          // per tree level outputs
+  DevBuf jobs;                         // device TensorJob arrays, all levels
+  std::vector<size_t> job_off;
+  DevBuf gen_poly, gen_p;              // on-the-fly plaintext generation
+  int GB = 0;
+  EventTimer* timer = nullptr;
+
+  void timed_select_sum(const uint64_t* phat, int nb, uint64_t* Sx, hipStream_t s) {
+    const HostParams& H = P->H;
+    const size_t n = H.n, L = H.L;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (timer && timer->on) { a = timer->get(); b = timer->get(); (void)hipEventRecord(a, s); }
+    select_sum(P->T, H.consts, chat.as<uint64_t>(), phat, H.ell, nb, Sx, (long)(2 * L * n), s);
+    if (a) {
+      (void)hipEventRecord(b, s);
+      const uint64_t bytes = 8ull * n * L * ((uint64_t)nb * H.ell + 2ull * H.ell + 2ull * nb);
+      timer->pending.push_back({a, b, 0, bytes});
+    }
+  }
+
+  ~Engine() {
+    for (DevBuf* b : {&chat, &rlkhat, &acc, &sq, &scoef, &sb, &alpha, &e, &d, &c3, &c3h, &D, &rcoef,
+                      &jobs, &gen_poly, &gen_p})
+      b->release();
+    for (auto& b : rq) b.release();
+    for (auto& b : rb) b.release();
+  }
+
+  size_t N() const { return P->H.n; }
+  int L() const { return P->H.L; }
+  int K() const { return P->H.K; }
+
+  // allocate for tiles of TB batches (h >= 2 tree buffers, generation buffers if needed)
+  int setup(pepsi_params* params, int tb, bool need_gen) {
+    P = params;
+    const HostParams& H = P->H;
+    const size_t n = H.n, L = H.L, K = H.K, Pn = L + K;
+    TB = tb;
+    int rc;
+    if ((rc = chat.ensure((size_t)H.ell * 2 * L * n * 8))) return rc;
+    if ((rc = rlkhat.ensure(L * 2 * L * n * 8))) return rc;
+    if ((rc = acc.ensure(2 * L * n * 8))) return rc;
+    if ((rc = sq.ensure(TB * 2 * L * n * 8))) return rc;
+    if ((rc = e.ensure(TB * 2 * L * n * 8))) return rc;
+    // tree shape
+    jobs_at.clear();
+    for (int cnt = H.h; cnt > 1; cnt = cnt / 2 + cnt % 2) jobs_at.push_back(cnt / 2);
+    levels = (int)jobs_at.size();
+    if (levels > 0) {
+      const size_t J = (size_t)TB * jobs_at[0];
+      if ((rc = scoef.ensure(TB * 2 * L * n * 8))) return rc;
+      if ((rc = sb.ensure(TB * 2 * K * n * 8))) return rc;
+      if ((rc = alpha.ensure((size_t)TB * H.h * Pn * 8))) return rc;
+      if ((rc = d.ensure(J * 3 * Pn * n * 8))) return rc;
+      if ((rc = c3.ensure(J * 3 * L * n * 8))) return rc;
+      if ((rc = c3h.ensure(J * 3 * L * n * 8))) return rc;
+      if ((rc = D.ensure(J * L * L * n * 8))) return rc;
+      if ((rc = rcoef.ensure(J * 2 * L * n * 8))) return rc;
+      rq.resize(levels);
+      rb.resize(levels);
+      for (int lv = 0; lv + 1 < levels; ++lv) {
+        const size_t Jl = (size_t)TB * jobs_at[lv];
+        if ((rc = rq[lv].ensure(Jl * 2 * L * n * 8))) return rc;
+        if ((rc = rb[lv].ensure(Jl * 2 * K * n * 8))) return rc;
+      }
+      if ((rc = build_jobs())) return rc;
+    }
+    if (need_gen) {
+      GB = std::min(TB, 8);
+      if ((rc = gen_poly.ensure((size_t)GB * H.ell * n * 4))) return rc;
+      if ((rc = gen_p.ensure((size_t)GB * H.ell * L * n * 8))) return rc;
+    }
+    return 0;
+  }
+
+  // Tensor jobs of every level for a full tile, batch-major (job = b * pairs + u), so a
+  // partial tile of nb batches uses the first nb * pairs jobs of each level.
+  int build_jobs() {
+    const HostParams& H = P->H;
+    const size_t n = H.n, L = H.L, K = H.K, Pn = L + K;
+    std::vector<TensorJob> all;
+    job_off.clear();
+    std::vector<std::vector<Operand>> ops(TB);
+    for (int b = 0; b < TB; ++b)
+      for (int r = 0; r < H.h; ++r)
+        ops[b].push_back(Operand{sq.as<uint64_t>((size_t)b * 2 * L * n), sb.as<uint64_t>((size_t)b * 2 * K * n),
+                                 alpha.as<uint64_t>(((size_t)b * H.h + r) * Pn)});
+    for (int lv = 0; lv < levels; ++lv) {
+      const int pairs = jobs_at[lv];
+      job_off.push_back(all.size());
+      for (int b = 0; b < TB; ++b)
+        for (int u = 0; u < pairs; ++u) {
+          const Operand& x = ops[b][2 * u];
+          const Operand& y = ops[b][2 * u + 1];
+          const size_t j = (size_t)b * pairs + u;
+          all.push_back(TensorJob{x.q, x.b, y.q, y.b, x.alpha, y.alpha, d.as<uint64_t>(j * 3 * Pn * n)});
+        }
+      if (lv + 1 < levels) {
+        for (int b = 0; b < TB; ++b) {
+          std::vector<Operand> next;
+          for (int u = 0; u < pairs; ++u) {
+            const size_t j = (size_t)b * pairs + u;
+            next.push_back(Operand{rq[lv].as<uint64_t>(j * 2 * L * n), rb[lv].as<uint64_t>(j * 2 * K * n), nullptr});
+          }
+          if (ops[b].size() % 2) next.push_back(ops[b].back());
+          ops[b] = next;
+        }
+      }
+    }
+    int rc = jobs.ensure(all.size() * sizeof(TensorJob));
+    if (rc) return rc;
+    HIPCHK(hipMemcpy(jobs.p, all.data(), all.size() * sizeof(TensorJob), hipMemcpyHostToDevice));
+    return 0;
+  }
+
+  // Ciphertext products + relinearisation of njobs jobs (device array), results in NTT form
+  // into out [njobs][2][L][N]; when ext_out is set also the Q -> B extension in NTT form.
+  void multiply_relin(const TensorJob* dev_jobs, int njobs, const uint64_t* rlk_hat, uint64_t* out,
+                      uint64_t* ext_out, hipStream_t s) {
+    const HostParams& H = P->H;
+    const int L = H.L, K = H.K, Pn = L + K;
+    uint64_t* dd = d.as<uint64_t>();
+    tensor(P->T, H.consts, dev_jobs, njobs, s);
+    ntt_inverse(P->T, H.logn, dd, dd, njobs * 3 * Pn, Pn, 0, s);
+    scale_round(P->T, H.consts, dd, c3.as<uint64_t>(), njobs, P->fallback.as<uint32_t>(), s);
+    relin_digits(P->T, H.consts, c3.as<uint64_t>(), D.as<uint64_t>(), njobs, s);
+    ntt_forward(P->T, H.logn, D.p, LOAD_U64, D.p, STORE_U64, njobs * L * L, L, 0, s);
+    ntt_forward(P->T, H.logn, c3.p, LOAD_U64, c3h.p, STORE_U64, njobs * 3 * L, L, 0, s);
+    relin_inner(P->T, H.consts, c3h.as<uint64_t>(), D.as<uint64_t>(), rlk_hat, out, njobs, s);
+    if (ext_out) {
+      ntt_inverse(P->T, H.logn, out, rcoef.as<uint64_t>(), njobs * 2 * L, L, 0, s);
+      ext_q_to_b(P->T, H.consts, rcoef.as<uint64_t>(), ext_out, (long)K * H.n, njobs * 2,
+                 P->fallback.as<uint32_t>(), s);
+      ntt_forward(P->T, H.logn, ext_out, LOAD_U64, ext_out, STORE_U64, njobs * 2 * K, K, L, s);
+    }
+  }
+
+  // Query preparation: client ciphertexts and relinearisation key to NTT form; acc = 0.
+  void begin_query(const uint64_t* cts, const uint64_t* rlk, hipStream_t s) {
+    const HostParams& H = P->H;
+    const int L = H.L;
+    ntt_forward(P->T, H.logn, cts, LOAD_U64, chat.p, STORE_U64, H.ell * 2 * L, L, 0, s);
+    ntt_forward(P->T, H.logn, rlk, LOAD_U64, rlkhat.p, STORE_U64, L * 2 * L, L, 0, s);
+    (void)hipMemsetAsync(acc.p, 0, 2 * (size_t)L * H.n * 8, s);
+  }
+
+  // One tile of nb batches: P-hat given (cache) or generated from the codewords.
+  void run_tile(const uint16_t* cw, int b0, int nb, const uint64_t* phat, hipStream_t s) {
+    const HostParams& H = P->H;
+    const size_t n = H.n, L = H.L, K = H.K;
+    uint64_t* Sq = sq.as<uint64_t>();
+    if (phat) {
+      timed_select_sum(phat, nb, Sq, s);
+    } else {
+      for (int g0 = 0; g0 < nb; g0 += GB) {
+        const int g = std::min(GB, nb - g0);
+        encode_server_planes(P->T, H.logn, cw, H.h, H.ell, b0 + g0, g, gen_poly.as<uint32_t>(), s);
+        ntt_forward(P->T, H.logn, gen_poly.p, LOAD_LIFT_T, gen_p.p, STORE_SPLIT27, g * H.ell * (int)L,
+                    (int)L, 0, s);
+        timed_select_sum(gen_p.as<uint64_t>(), g, Sq + (size_t)g0 * 2 * L * n, s);
+      }
+    }
+    if (levels == 0) {                                           // h = 1: e = S
+      accumulate(P->T, H.consts, Sq, (long)(2 * L * n), nb, acc.as<uint64_t>(), s);
+      return;
+    }
+    ntt_inverse(P->T, H.logn, Sq, scoef.as<uint64_t>(), nb * 2 * (int)L, (int)L, 0, s);
+    ext_q_to_b(P->T, H.consts, scoef.as<uint64_t>(), sb.as<uint64_t>(), (long)(K * n), nb * 2,
+               P->fallback.as<uint32_t>(), s);
+    ntt_forward(P->T, H.logn, sb.p, LOAD_U64, sb.p, STORE_U64, nb * 2 * (int)K, (int)K, (int)L, s);
+    factor_constants(P->T, H.consts, scoef.as<uint64_t>(), nb, H.h, alpha.as<uint64_t>(),
+                     P->fallback.as<uint32_t>(), s);
+    for (int lv = 0; lv < levels; ++lv) {
+      const int njobs = nb * jobs_at[lv];
+      const TensorJob* jl = jobs.as<TensorJob>() + job_off[lv];
+      const bool last = lv + 1 == levels;
+      multiply_relin(jl, njobs, rlkhat.as<uint64_t>(), last ? e.as<uint64_t>() : rq[lv].as<uint64_t>(),
+                     last ? nullptr : rb[lv].as<uint64_t>(), s);
+    }
+    accumulate(P->T, H.consts, e.as<uint64_t>(), (long)(2 * L * n), nb, acc.as<uint64_t>(), s);
+  }
+
+  // out = coefficient form of acc, optionally times (h!)^-1 and plus Delta [encode(mask)]_t
+  void finish(bool finalize, const uint32_t* mask, uint64_t* out, hipStream_t s) {
+    const HostParams& H = P->H;
+    const int L = H.L;
+    uint64_t* a = acc.as<uint64_t>();
+    if (finalize) {
+      uint64_t hf = 1;
+      for (int r = 2; r <= H.h; ++r) hf = hf * r % PEPSI_T;
+      const uint64_t k = powm(hf, PEPSI_T - 2, PEPSI_T);       // (h!)^-1 mod t
+      const int64_t kc = k <= (PEPSI_T - 1) / 2 ? (int64_t)k : (int64_t)k - PEPSI_T;
+      uint64_t kq[PEPSI_MAXL];
+      for (int l = 0; l < L; ++l) kq[l] = kc >= 0 ? (uint64_t)kc : H.primes[l] - (uint64_t)(-kc);
+      scale_const(P->T, H.consts, a, kq, s);
+    }
+    ntt_inverse(P->T, H.logn, a, out, 2 * L, L, 0, s);
+    if (finalize && mask) {
+      uint32_t* m = reinterpret_cast<uint32_t*>(sq.p);           // sq is free after the tiles
+      encode_slots(P->T, H.logn, mask, m, 1, s);
+      add_plain_poly(P->T, H.consts, out, m, s);
+    }
+  }
+};
+
+}  // namespace
+
+// ------------------------------------------------------------------ server
+struct pepsi_server {
+  pepsi_params* P = nullptr;
+  EventTimer timer;
+  uint32_t max_load = 0;
+  DevBuf cw;            // [mu][N][h] uint16
+  DevBuf cache;         // [max_load][ell][L][N] split-27 NTT form
+  bool cached = false;
+  Engine eng;
+  bool ready = false;
+};
+
+extern "C" int pepsi_server_create(const pepsi_params* Pc, const uint32_t* items, uint64_t n,
+                                   uint32_t flags, void* stream, pepsi_server** out) {
+  pepsi_params* P = const_cast<pepsi_params*>(Pc);
+  if (!P || (!items && n) || !out) return fail(PEPSI_E_ARG, "null argument");
+  *out = nullptr;
+  const HostParams& H = P->H;
+  {
+    std::unordered_set<uint32_t> seen;
+    seen.reserve(n * 2);
+    for (uint64_t i = 0; i < n; ++i) {
+      if (H.item_bits < 32 && (items[i] >> H.item_bits)) return fail(PEPSI_E_RANGE, "server item out of range");
+      if (!seen.insert(items[i]).second) return fail(PEPSI_E_RANGE, "duplicate server item");
+    }
+  }
+  std::vector<uint32_t> table;
+  std::vector<uint8_t> valid;
+  uint32_t max_load = 0;
+  if (simple_hash(items, n, H.n, H.hash_seed, H.n_hash, H.mu, &table, &valid, &max_load))
+    return fail(PEPSI_E_BIN_OVERFLOW, "a server bin exceeds mu = %d", H.mu);
+  std::vector<uint16_t> cw((size_t)H.mu * H.n * H.h, 0xFFFF);
+  CwEncoder enc(H.ell, H.h);
+  for (size_t i = 0; i < (size_t)H.mu * H.n; ++i)
+    if (valid[i]) enc.encode(table[i], &cw[i * H.h]);
+  pepsi_server* sv = new pepsi_server();
+  sv->P = P;
+  sv->max_load = max_load;
+  int rc = sv->cw.ensure(cw.size() * 2);
+  if (rc) { delete sv; return rc; }
+  if (hipMemcpy(sv->cw.p, cw.data(), cw.size() * 2, hipMemcpyHostToDevice) != hipSuccess) {
+    delete sv;
+    return fail(PEPSI_E_DEVICE, "codeword upload failed");
+  }
+  if ((flags & PEPSI_SERVER_CACHE_PLAINTEXTS) && max_load > 0) {
+    const size_t per = (size_t)H.ell * H.L * H.n;
+    if ((rc = sv->cache.ensure(per * max_load * 8))) { delete sv; return rc; }
+    // generation buffers: 8 batches at a time
+    DevBuf poly;
+    const int G = 8;
+    if ((rc = poly.ensure((size_t)G * H.ell * H.n * 4))) { delete sv; return rc; }
+    hipStream_t s = S(stream);
+    for (uint32_t b0 = 0; b0 < max_load; b0 += G) {
+      const int g = (int)std::min<uint32_t>(G, max_load - b0);
+      encode_server_planes(P->T, H.logn, sv->cw.as<uint16_t>(), H.h, H.ell, (int)b0, g, poly.as<uint32_t>(), s);
+      ntt_forward(P->T, H.logn, poly.p, LOAD_LIFT_T, sv->cache.as<uint64_t>(per * b0), STORE_SPLIT27,
+                  g * H.ell * H.L, H.L, 0, s);
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) { poly.release(); delete sv; return fail(PEPSI_E_DEVICE, "cache build failed"); }
+    poly.release();
+    sv->cached = true;
+  }
+  *out = sv;
+  return PEPSI_OK;
+}
+
+extern "C" int pepsi_server_get_info(const pepsi_server* sv, pepsi_server_info* o) {
+  if (!sv || !o) return fail(PEPSI_E_ARG, "null argument");
+  memset(o, 0, sizeof(*o));
+  o->mu = sv->P->H.mu;
+  o->max_load = sv->max_load;
+  o->cached = sv->cached ? 1 : 0;
+  o->device_bytes = sv->cw.cap + sv->cache.cap;
+  return PEPSI_OK;
+}
+
+extern "C" int pepsi_server_codewords(const pepsi_server* sv, uint16_t* out) {
+  if (!sv || !out) return fail(PEPSI_E_ARG, "null argument");
+  const HostParams& H = sv->P->H;
+  HIPCHK(hipMemcpy(out, sv->cw.p, (size_t)H.mu * H.n * H.h * 2, hipMemcpyDeviceToHost));
+  return PEPSI_OK;
+}
+
+extern "C" void pepsi_server_destroy(pepsi_server* sv) {
+  if (!sv) return;
+  (void)hipDeviceSynchronize();
+  sv->cw.release();
+  sv->cache.release();
+  delete sv;
+}
+
+extern "C" int pepsi_server_eval_range(pepsi_server* sv, const uint64_t* cts, const uint64_t* rlk,
+                                       uint32_t begin, uint32_t end, uint32_t finalize,
+                                       const uint32_t* mask, uint64_t* out, void* stream) {
+  if (!sv || !cts || !rlk || !out) return fail(PEPSI_E_ARG, "null argument");
+  const HostParams& H = sv->P->H;
+  if (begin > end || end > (uint32_t)H.mu) return fail(PEPSI_E_ARG, "bad batch range");
+  hipStream_t s = S(stream);
+  if (!sv->ready) {
+    const int tb = std::min<int>(64, std::max<int>(1, (int)sv->max_load));
+    int rc = sv->eng.setup(sv->P, tb, !sv->cached);
+    if (rc) return rc;
+    sv->eng.timer = &sv->timer;
+    sv->ready = true;
+  }
+  Engine& E = sv->eng;
+  hipEvent_t ea = nullptr, eb = nullptr;
+  if (sv->timer.on) { ea = sv->timer.get(); eb = sv->timer.get(); (void)hipEventRecord(ea, s); }
+  E.begin_query(cts, rlk, s);
+  // batches at or above the fullest bin hold only dummies: their equality ciphertext is (0, 0)
+  const uint32_t stop = std::min(end, sv->max_load);
+  const size_t per = (size_t)H.ell * H.L * H.n;
+  for (uint32_t b0 = begin; b0 < stop; b0 += E.TB) {
+    const int nb = (int)std::min<uint32_t>(E.TB, stop - b0);
+    E.run_tile(sv->cw.as<uint16_t>(), (int)b0, nb, sv->cached ? sv->cache.as<uint64_t>(per * b0) : nullptr, s);
+  }
+  E.finish(finalize != 0, mask, out, s);
+  if (ea) {
+    (void)hipEventRecord(eb, s);
+    sv->timer.pending.push_back({ea, eb, 1, 0});
+  }
+  HIPCHK(hipGetLastError());
+  return PEPSI_OK;
+}
+
+extern "C" int pepsi_server_timing(pepsi_server* sv, int enable, int reset, pepsi_timing* out) {
+  if (!sv) return fail(PEPSI_E_ARG, "null argument");
+  HIPCHK(hipDeviceSynchronize());
+  if (sv->timer.fold()) return fail(PEPSI_E_DEVICE, "event timing failed");
+  if (out) *out = sv->timer.tot;
+  if (reset) sv->timer.tot = pepsi_timing{};
+  sv->timer.on = enable != 0;
+  return PEPSI_OK;
+}
+
+extern "C" int pepsi_server_eval(pepsi_server* sv, const uint64_t* cts, const uint64_t* rlk,
+                                 const uint32_t* mask, uint64_t* out, void* stream) {
+  if (!sv) return fail(PEPSI_E_ARG, "null argument");
+  return pepsi_server_eval_range(sv, cts, rlk, 0, sv->P->H.mu, 1, mask, out, stream);
+}
+
+// ------------------------------------------------------------------ single steps
+extern "C" int pepsi_ntt(const pepsi_params* P, uint64_t* data, uint32_t rows, uint32_t first,
+                         uint32_t nprimes, int inverse, void* stream) {
+  if (!P || !data) return fail(PEPSI_E_ARG, "null argument");
+  const HostParams& H = P->H;
+  if (nprimes == 0 || first + nprimes > (uint32_t)(H.L + H.K)) return fail(PEPSI_E_ARG, "bad prime range");
+  if (inverse)
+    ntt_inverse(P->T, H.logn, data, data, (int)rows, (int)nprimes, (int)first, S(stream));
+  else
+    ntt_forward(P->T, H.logn, data, LOAD_U64, data, STORE_U64, (int)rows, (int)nprimes, (int)first, S(stream));
+  HIPCHK(hipGetLastError());
+  return PEPSI_OK;
+}
+
+extern "C" int pepsi_encode(const pepsi_params* P, const uint32_t* slots, uint32_t rows, uint32_t* poly,
+                            void* stream) {
+  if (!P || !slots || !poly) return fail(PEPSI_E_ARG, "null argument");
+  encode_slots(P->T, P->H.logn, slots, poly, (int)rows, S(stream));
+  HIPCHK(hipGetLastError());
+  return PEPSI_OK;
+}
+
+extern "C" int pepsi_decode(const pepsi_params* P, const uint32_t* poly, uint32_t rows, uint32_t* slots,
+                            void* stream) {
+  if (!P || !slots || !poly) return fail(PEPSI_E_ARG, "null argument");
+  decode_slots(P->T, P->H.logn, poly, slots, (int)rows, S(stream));
+  HIPCHK(hipGetLastError());
+  return PEPSI_OK;
+}
+
+extern "C" int pepsi_select_sum(const pepsi_params* Pc, const uint64_t* cts, const uint16_t* cw,
+                                uint64_t* out, void* stream) {
+  pepsi_params* P = const_cast<pepsi_params*>(Pc);
+  if (!P || !cts || !cw || !out) return fail(PEPSI_E_ARG, "null argument");
+  const HostParams& H = P->H;
+  const size_t n = H.n, L = H.L, ell = H.ell;
+  // scratch: chat (ell 2 L n) | phat (ell L n) | poly (ell n u32) | S (2 L n)
+  const size_t w_c = ell * 2 * L * n, w_p = ell * L * n, w_poly = (ell * n + 1) / 2, w_s = 2 * L * n;
+  int rc = P->scratch.ensure((w_c + w_p + w_poly + w_s) * 8);
+  if (rc) return rc;
+  uint64_t* ch = P->scratch.as<uint64_t>();
+  uint64_t* ph = ch + w_c;
+  uint32_t* poly = reinterpret_cast<uint32_t*>(ph + w_p);
+  uint64_t* Sx = ph + w_p + w_poly;
+  hipStream_t s = S(stream);
+  ntt_forward(P->T, H.logn, cts, LOAD_U64, ch, STORE_U64, (int)(ell * 2 * L), (int)L, 0, s);
+  encode_server_planes(P->T, H.logn, cw, H.h, (int)ell, 0, 1, poly, s);
+  ntt_forward(P->T, H.logn, poly, LOAD_LIFT_T, ph, STORE_SPLIT27, (int)(ell * L), (int)L, 0, s);
+  select_sum(P->T, H.consts, ch, ph, (int)ell, 1, Sx, (long)(2 * L * n), s);
+  ntt_inverse(P->T, H.logn, Sx, out, (int)(2 * L), (int)L, 0, s);
+  HIPCHK(hipGetLastError());
+  return PEPSI_OK;
+}
+
+extern "C" int pepsi_multiply(const pepsi_params* Pc, const uint64_t* x, const uint64_t* y,
+                              uint64_t* out, void* stream) {
+  pepsi_params* P = const_cast<pepsi_params*>(Pc);
+  if (!P || !x || !y || !out) return fail(PEPSI_E_ARG, "null argument");
+  const HostParams& H = P->H;
+  const size_t n = H.n, L = H.L, K = H.K, Pn = L + K;
+  // scratch: xq yq (2 L n each) | xb yb (2 K n each) | d (3 P n)
+  const size_t w_q = 2 * L * n, w_b = 2 * K * n, w_d = 3 * Pn * n;
+  int rc = P->scratch.ensure((2 * w_q + 2 * w_b + w_d) * 8);
+  if (rc) return rc;
+  uint64_t* xq = P->scratch.as<uint64_t>();
+  uint64_t* yq = xq + w_q;
+  uint64_t* xb = yq + w_q;
+  uint64_t* yb = xb + w_b;
+  uint64_t* dd = yb + w_b;
+  hipStream_t s = S(stream);
+  ext_q_to_b(P->T, H.consts, x, xb, (long)(K * n), 2, P->fallback.as<uint32_t>(), s);
+  ext_q_to_b(P->T, H.consts, y, yb, (long)(K * n), 2, P->fallback.as<uint32_t>(), s);
+  ntt_forward(P->T, H.logn, x, LOAD_U64, xq, STORE_U64, (int)(2 * L), (int)L, 0, s);
+  ntt_forward(P->T, H.logn, y, LOAD_U64, yq, STORE_U64, (int)(2 * L), (int)L, 0, s);
+  ntt_forward(P->T, H.logn, xb, LOAD_U64, xb, STORE_U64, (int)(2 * K), (int)K, (int)L, s);
+  ntt_forward(P->T, H.logn, yb, LOAD_U64, yb, STORE_U64, (int)(2 * K), (int)K, (int)L, s);
+  TensorJob job{xq, xb, yq, yb, nullptr, nullptr, dd};
+  if ((rc = P->job_dev.ensure(sizeof(TensorJob)))) return rc;
+  HIPCHK(hipMemcpyAsync(P->job_dev.p, &job, sizeof(job), hipMemcpyHostToDevice, s));
+  tensor(P->T, H.consts, P->job_dev.as<TensorJob>(), 1, s);
+  ntt_inverse(P->T, H.logn, dd, dd, (int)(3 * Pn), (int)Pn, 0, s);
+  scale_round(P->T, H.consts, dd, out, 1, P->fallback.as<uint32_t>(), s);
+  HIPCHK(hipStreamSynchronize(s));       // the job record lives on the host stack
+  return PEPSI_OK;
+}
+
+extern "C" int pepsi_relin(const pepsi_params* Pc, const uint64_t* ct3, const uint64_t* rlk,
+                           uint64_t* out, void* stream) {
+  pepsi_params* P = const_cast<pepsi_params*>(Pc);
+  if (!P || !ct3 || !rlk || !out) return fail(PEPSI_E_ARG, "null argument");
+  const HostParams& H = P->H;
+  const size_t n = H.n, L = H.L;
+  // scratch: c3h (3 L n) | D (L L n) | rlkh (L 2 L n) | o (2 L n)
+  const size_t w_c = 3 * L * n, w_D = L * L * n, w_r = 2 * L * L * n, w_o = 2 * L * n;
+  int rc = P->scratch.ensure((w_c + w_D + w_r + w_o) * 8);
+  if (rc) return rc;
+  uint64_t* c3h = P->scratch.as<uint64_t>();
+  uint64_t* Dd = c3h + w_c;
+  uint64_t* rh = Dd + w_D;
+  uint64_t* o = rh + w_r;
+  hipStream_t s = S(stream);
+  relin_digits(P->T, H.consts, ct3, Dd, 1, s);
+  ntt_forward(P->T, H.logn, Dd, LOAD_U64, Dd, STORE_U64, (int)(L * L), (int)L, 0, s);
+  ntt_forward(P->T, H.logn, ct3, LOAD_U64, c3h, STORE_U64, (int)(3 * L), (int)L, 0, s);
+  ntt_forward(P->T, H.logn, rlk, LOAD_U64, rh, STORE_U64, (int)(2 * L * L), (int)L, 0, s);
+  relin_inner(P->T, H.consts, c3h, Dd, rh, o, 1, s);
+  ntt_inverse(P->T, H.logn, o, out, (int)(2 * L), (int)L, 0, s);
+  HIPCHK(hipGetLastError());
+  return PEPSI_OK;
+}

@@ -1,0 +1,98 @@
+// Kernel launchers (all asynchronous on the given stream).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include "params.hpp"
+
+namespace pepsi {
+
+// ---------------- negacyclic NTT over the RNS primes ----------------
+// Row r of a [rows][N] array is transformed modulo prime (first + r % nprimes).
+// Forward: coefficient order in, bit-reversed evaluation order out:
+//   out[k] = a(psi^(2 brv(k) + 1)).   Inverse: the exact inverse.
+enum NttLoad { LOAD_U64 = 0, LOAD_LIFT_T = 1, LOAD_I8 = 2, LOAD_I32 = 3 };
+enum NttStore { STORE_U64 = 0, STORE_SPLIT27 = 1 };
+
+// in: LOAD_U64 -> const uint64_t[rows][N]; LOAD_LIFT_T -> const uint32_t[rows / nprimes][N]
+// (a plaintext mod t, lifted to its centred representative); LOAD_I8 / LOAD_I32 -> small
+// signed integers [rows / nprimes][N].
+void ntt_forward(const Tables& T, int logn, const void* in, NttLoad load, void* out,
+                 NttStore store, int rows, int nprimes, int first, hipStream_t s);
+void ntt_inverse(const Tables& T, int logn, const uint64_t* in, uint64_t* out, int rows,
+                 int nprimes, int first, hipStream_t s);
+
+// ---------------- batching over Z_t ----------------
+// slots (natural order, slot k <-> psi_t^(2k+1)) -> plaintext polynomial, coefficients in [0, t)
+void encode_slots(const Tables& T, int logn, const uint32_t* slots, uint32_t* poly, int rows,
+                  hipStream_t s);
+// plaintext polynomial -> slots
+void decode_slots(const Tables& T, int logn, const uint32_t* poly, uint32_t* slots, int rows,
+                  hipStream_t s);
+// server plaintexts of batches [b0, b0 + nb): row (b, j) has slot k = [j in cw[b][k][0..h)]
+void encode_server_planes(const Tables& T, int logn, const uint16_t* cw, int h, int ell, int b0,
+                          int nb, uint32_t* poly, hipStream_t s);
+
+// ---------------- RNS kernels ----------------
+// Q -> B extension of the centred lift: in [rows][L][N] (coefficients mod q), out [rows][K][N]
+// (out row stride ostride words between consecutive input rows, starting at limb 0 of B).
+void ext_q_to_b(const Tables& T, const Consts& hc, const uint64_t* in, uint64_t* out,
+                long ostride, int rows, uint32_t* fallback_count, hipStream_t s);
+// The h factor constants of one select-and-sum ciphertext per batch: alpha[b][r][p] is
+// added to every NTT position of c0's limb p for f_r = S + Delta * [-r]_t.
+// scoef: coefficient form [nb][2][L][N] (only coefficient 0 of c0 is read).
+void factor_constants(const Tables& T, const Consts& hc, const uint64_t* scoef, int nb, int h,
+                      uint64_t* alpha, uint32_t* fallback_count, hipStream_t s);
+// Tensor of two extended ciphertexts in NTT form, each given as its Q part [2][L][N] and
+// its B part [2][K][N], with optional constants (per limb of Q u B, may be null) added to
+// every position of c0: d = [3][L+K][N] (limb p of Q u B at row p).
+struct TensorJob {
+  const uint64_t* xq; const uint64_t* xb; const uint64_t* yq; const uint64_t* yb;
+  const uint64_t* ax; const uint64_t* ay; uint64_t* d;
+};
+void tensor(const Tables& T, const Consts& hc, const TensorJob* jobs_dev, int njobs, hipStream_t s);
+// round(t d / Q) for d over Q u B (coefficient form [rows][3][L+K][N]) -> [rows][3][L][N] mod Q
+void scale_round(const Tables& T, const Consts& hc, const uint64_t* d, uint64_t* out, int rows,
+                 uint32_t* fallback_count, hipStream_t s);
+// relinearisation digits: c3 [rows][3][L][N] coefficient form -> D [rows][L][L][N]
+void relin_digits(const Tables& T, const Consts& hc, const uint64_t* c3, uint64_t* D, int rows,
+                  hipStream_t s);
+// out[r][c] = dhat_c + sum_i Dhat_i * rlk_i,c  (all NTT form); dhat: [rows][3][L][N] (first 2
+// polys used), Dhat [rows][L][L][N], rlk [L][2][L][N]; out [rows][2][L][N].
+void relin_inner(const Tables& T, const Consts& hc, const uint64_t* dhat, const uint64_t* Dhat,
+                 const uint64_t* rlk, uint64_t* out, int rows, hipStream_t s);
+// acc[2][L][N] += sum over rows of x[rows][2][L][N] (row stride xstride)
+void accumulate(const Tables& T, const Consts& hc, const uint64_t* x, long xstride, int rows,
+                uint64_t* acc, hipStream_t s);
+// select-and-sum: S[b][c][l][k] = sum_j C[j][c][l][k] * P[b][j][l][k] mod q_l.
+// C: NTT form [ell][2][L][N]; P: split-27 NTT form [nb][ell][L][N]; S rows of stride sstride.
+void select_sum(const Tables& T, const Consts& hc, const uint64_t* C, const uint64_t* P, int ell,
+                int nb, uint64_t* S, long sstride, hipStream_t s);
+
+// ---------------- elementwise helpers ----------------
+// out = a * b pointwise (both [rows][L][N] NTT form, b broadcast over rows if bcast)
+void pointwise_mul(const Tables& T, const Consts& hc, const uint64_t* a, const uint64_t* b,
+                   uint64_t* out, int rows, int nprimes, bool bcast, hipStream_t s);
+// ct[c] *= k_c (per limb constants kq[L]) in place, both components ([2][L][N])
+void scale_const(const Tables& T, const Consts& hc, uint64_t* ct, const uint64_t* kq, hipStream_t s);
+// c0[l] += Delta_l * [m]_t (centred)  for a plaintext polynomial m (coefficient form)
+void add_plain_poly(const Tables& T, const Consts& hc, uint64_t* ct, const uint32_t* m, hipStream_t s);
+// encryption finish: c0 = Delta [m]_t - as - e, c1 = a    (count ciphertexts)
+void encrypt_finish(const Tables& T, const Consts& hc, const uint32_t* m, const uint64_t* as,
+                    const int32_t* e, const uint64_t* a, uint64_t* ct, int count, hipStream_t s);
+// decryption: x = c0 + c1 s (coefficient form [count][L][N]) -> round(t x / Q) mod t
+void decrypt_round(const Tables& T, const Consts& hc, const uint64_t* x, uint32_t* m, int count,
+                   uint32_t* fallback_count, hipStream_t s);
+// noise: max bit length of |[t x]_Q| over count ciphertext phases x -> atomicMax(out)
+void noise_bits(const Tables& T, const Consts& hc, const uint64_t* x, int count, uint32_t* out,
+                hipStream_t s);
+// decryption phase in NTT form: x = c0 + c1 s; cth [count][2][L][N], sh [L][N], x [count][L][N]
+void phase_ntt(const Tables& T, const Consts& hc, const uint64_t* cth, const uint64_t* sh, uint64_t* x,
+               int count, hipStream_t s);
+// relinearisation key finish: rlk_i0 = (Q/q_i) s^2 - a_i s - e_i, rlk_i1 = a_i
+void keygen_finish(const Tables& T, const Consts& hc, const uint64_t* s2, const uint64_t* as,
+                   const int32_t* e, const uint64_t* a, uint64_t* rlk, hipStream_t s);
+// elementwise (a + b) mod q_l, rows [rows][nprimes][N]
+void add_rows(const Tables& T, const Consts& hc, const uint64_t* a, const uint64_t* b, uint64_t* out,
+              int rows, int nprimes, hipStream_t s);
+
+}  // namespace pepsi

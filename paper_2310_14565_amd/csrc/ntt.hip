@@ -1,0 +1,369 @@
+// Negacyclic number-theoretic transforms for gfx950.
+//
+// NTT over an RNS prime p (2^53 < p < 2^54): one workgroup per row of N
+// residues, N/32 threads, 32 residues per thread held in registers.  The
+// log2(N) butterfly stages are done in three register passes of 5, 5 and
+// log2(N) - 10 stages; between passes the row goes through LDS (padded by
+// one word every 32 so that the strided pass patterns spread over banks).
+// Forward: Cooley-Tukey with the bit-reversed power table psi^brv(k), output
+// in bit-reversed evaluation order.  Inverse: Gentleman-Sande with psi^-brv(k)
+// and a final N^-1.  Butterflies are lazy (Harvey): residues live in [0, 4p)
+// in the forward and [0, 2p) in the inverse transform, with one Shoup
+// product per butterfly.
+//
+// Transforms over t = 65537 (batch encoding of slots) are cheap 32-bit
+// radix-2 loops over LDS.
+#include "kernels.hpp"
+
+namespace pepsi {
+namespace {
+
+constexpr int E = 32;  // residues per thread
+
+__device__ __forceinline__ int lds_idx(int j) { return j + (j >> 5); }
+
+template <int LOGN, int S0, int D>
+__device__ __forceinline__ int elem_index(int tid, int u, int m) {
+  constexpr int N = 1 << LOGN, T = N / E, LOW = N >> (S0 + D);
+  const int g = tid + T * u;
+  return (g / LOW) * (N >> S0) + m * LOW + (g % LOW);
+}
+
+// Forward stages [S0, S0 + D) on 32 >> D groups of 2^D registers.
+template <int LOGN, int S0, int D>
+__device__ __forceinline__ void fwd_pass(uint64_t* x, int tid, const uint64_t* __restrict__ W,
+                                         const uint64_t* __restrict__ Wq, uint64_t p) {
+  constexpr int N = 1 << LOGN, T = N / E, LOW = N >> (S0 + D), G = E >> D;
+  const uint64_t two_p = 2 * p;
+#pragma unroll
+  for (int u = 0; u < G; ++u) {
+    const int hi = (tid + T * u) / LOW;
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+      const int half = 1 << (D - 1 - r);
+#pragma unroll
+      for (int blk = 0; blk < (1 << r); ++blk) {
+        const int widx = (1 << (S0 + r)) + ((hi << r) | blk);
+        const uint64_t w = W[widx], wq = Wq[widx];
+#pragma unroll
+        for (int m = 0; m < half; ++m) {
+          const int a = u * (1 << D) + blk * 2 * half + m, b = a + half;
+          uint64_t U = x[a];
+          if (U >= two_p) U -= two_p;
+          const uint64_t V = shoup_lazy(x[b], w, wq, p);
+          x[a] = U + V;
+          x[b] = U - V + two_p;
+        }
+      }
+    }
+  }
+}
+
+// Inverse stages S0 + D - 1 down to S0.
+template <int LOGN, int S0, int D>
+__device__ __forceinline__ void inv_pass(uint64_t* x, int tid, const uint64_t* __restrict__ W,
+                                         const uint64_t* __restrict__ Wq, uint64_t p) {
+  constexpr int N = 1 << LOGN, T = N / E, LOW = N >> (S0 + D), G = E >> D;
+  const uint64_t two_p = 2 * p;
+#pragma unroll
+  for (int u = 0; u < G; ++u) {
+    const int hi = (tid + T * u) / LOW;
+#pragma unroll
+    for (int r = D - 1; r >= 0; --r) {
+      const int half = 1 << (D - 1 - r);
+#pragma unroll
+      for (int blk = 0; blk < (1 << r); ++blk) {
+        const int widx = (1 << (S0 + r)) + ((hi << r) | blk);
+        const uint64_t w = W[widx], wq = Wq[widx];
+#pragma unroll
+        for (int m = 0; m < half; ++m) {
+          const int a = u * (1 << D) + blk * 2 * half + m, b = a + half;
+          const uint64_t U = x[a], V = x[b];
+          uint64_t s = U + V;
+          if (s >= two_p) s -= two_p;
+          x[a] = s;
+          x[b] = shoup_lazy(U - V + two_p, w, wq, p);
+        }
+      }
+    }
+  }
+}
+
+template <int LOGN, int S0, int D>
+__device__ __forceinline__ void to_lds(uint64_t* lds, const uint64_t* x, int tid) {
+#pragma unroll
+  for (int u = 0; u < (E >> D); ++u)
+#pragma unroll
+    for (int m = 0; m < (1 << D); ++m)
+      lds[lds_idx(elem_index<LOGN, S0, D>(tid, u, m))] = x[u * (1 << D) + m];
+}
+template <int LOGN, int S0, int D>
+__device__ __forceinline__ void from_lds(uint64_t* x, const uint64_t* lds, int tid) {
+#pragma unroll
+  for (int u = 0; u < (E >> D); ++u)
+#pragma unroll
+    for (int m = 0; m < (1 << D); ++m)
+      x[u * (1 << D) + m] = lds[lds_idx(elem_index<LOGN, S0, D>(tid, u, m))];
+}
+
+template <NttLoad LD>
+__device__ __forceinline__ uint64_t load_elem(const void* in, size_t row, int nprimes, int N,
+                                              int j, uint64_t p) {
+  if constexpr (LD == LOAD_U64) {
+    return static_cast<const uint64_t*>(in)[row * N + j];
+  } else if constexpr (LD == LOAD_LIFT_T) {
+    const uint32_t v = static_cast<const uint32_t*>(in)[(row / nprimes) * N + j];
+    return v <= (PEPSI_T - 1) / 2 ? (uint64_t)v : p - (uint64_t)(PEPSI_T - v);
+  } else if constexpr (LD == LOAD_I8) {
+    const int v = static_cast<const int8_t*>(in)[(row / nprimes) * N + j];
+    return v >= 0 ? (uint64_t)v : p - (uint64_t)(-v);
+  } else {
+    const int v = static_cast<const int32_t*>(in)[(row / nprimes) * N + j];
+    return v >= 0 ? (uint64_t)v : p - (uint64_t)(-(int64_t)v);
+  }
+}
+
+template <int LOGN, NttLoad LD, NttStore ST>
+__global__ void __launch_bounds__((1 << LOGN) / E)
+k_ntt_fwd(Tables T, const void* __restrict__ in, void* __restrict__ out, int nprimes, int first) {
+  constexpr int N = 1 << LOGN, TT = N / E, D2 = LOGN - 10;
+  __shared__ uint64_t lds[N + N / 32];
+  const size_t row = blockIdx.x;
+  const int pidx = first + (int)(row % nprimes);
+  const uint64_t p = T.c->prm[pidx].p;
+  const uint64_t* W = T.psi_rev + (size_t)pidx * N;
+  const uint64_t* Wq = T.psi_rev_shoup + (size_t)pidx * N;
+  const int tid = threadIdx.x;
+  uint64_t x[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) x[m] = load_elem<LD>(in, row, nprimes, N, m * TT + tid, p);
+  fwd_pass<LOGN, 0, 5>(x, tid, W, Wq, p);
+  to_lds<LOGN, 0, 5>(lds, x, tid);
+  __syncthreads();
+  from_lds<LOGN, 5, 5>(x, lds, tid);
+  fwd_pass<LOGN, 5, 5>(x, tid, W, Wq, p);
+  to_lds<LOGN, 5, 5>(lds, x, tid);
+  __syncthreads();
+  if constexpr (D2 > 0) {
+    from_lds<LOGN, 10, D2>(x, lds, tid);
+    fwd_pass<LOGN, 10, D2>(x, tid, W, Wq, p);
+    __syncthreads();                      // every thread has read its pass-C inputs
+    to_lds<LOGN, 10, D2>(lds, x, tid);
+    __syncthreads();
+  }
+  const uint64_t two_p = 2 * p;
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int j = m * TT + tid;
+    uint64_t v = lds[lds_idx(j)];
+    if (v >= two_p) v -= two_p;
+    if (v >= p) v -= p;
+    if constexpr (ST == STORE_U64) {
+      static_cast<uint64_t*>(out)[row * N + j] = v;
+    } else {
+      static_cast<uint64_t*>(out)[row * N + j] = (v & ((1ull << 27) - 1)) | ((v >> 27) << 32);
+    }
+  }
+}
+
+template <int LOGN>
+__global__ void __launch_bounds__((1 << LOGN) / E)
+k_ntt_inv(Tables T, const uint64_t* __restrict__ in, uint64_t* __restrict__ out, int nprimes, int first) {
+  constexpr int N = 1 << LOGN, TT = N / E, D2 = LOGN - 10;
+  __shared__ uint64_t lds[N + N / 32];
+  const size_t row = blockIdx.x;
+  const int pidx = first + (int)(row % nprimes);
+  const uint64_t p = T.c->prm[pidx].p;
+  const uint64_t* W = T.ipsi_rev + (size_t)pidx * N;
+  const uint64_t* Wq = T.ipsi_rev_shoup + (size_t)pidx * N;
+  const int tid = threadIdx.x;
+  uint64_t x[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int j = m * TT + tid;
+    lds[lds_idx(j)] = in[row * N + j];
+  }
+  __syncthreads();
+  if constexpr (D2 > 0) {
+    from_lds<LOGN, 10, D2>(x, lds, tid);
+    inv_pass<LOGN, 10, D2>(x, tid, W, Wq, p);
+    __syncthreads();
+    to_lds<LOGN, 10, D2>(lds, x, tid);
+    __syncthreads();
+  }
+  from_lds<LOGN, 5, 5>(x, lds, tid);
+  inv_pass<LOGN, 5, 5>(x, tid, W, Wq, p);
+  __syncthreads();
+  to_lds<LOGN, 5, 5>(lds, x, tid);
+  __syncthreads();
+  from_lds<LOGN, 0, 5>(x, lds, tid);
+  inv_pass<LOGN, 0, 5>(x, tid, W, Wq, p);
+  const uint64_t ni = T.c->n_inv[pidx], niq = T.c->n_inv_shoup[pidx];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int j = m * TT + tid;
+    out[row * N + j] = shoup(x[m], ni, niq, p);
+  }
+}
+
+// ---------------- transforms over t ----------------
+
+__device__ __forceinline__ int brv(int k, int logn) { return (int)(__brev((unsigned)k) >> (32 - logn)); }
+
+// Gentleman-Sande inverse over Z_t on an LDS row; the row holds bit-reversed evaluations.
+template <int LOGN>
+__device__ void intt_t_lds(uint32_t* a, const uint32_t* __restrict__ iw, uint32_t n_inv) {
+  constexpr int N = 1 << LOGN;
+  for (int s = LOGN - 1; s >= 0; --s) {
+    const int t = N >> (s + 1);
+    for (int bi = threadIdx.x; bi < N / 2; bi += blockDim.x) {
+      const int i = bi / t, off = bi % t;
+      const int x = i * 2 * t + off, y = x + t;
+      const uint32_t w = iw[(1 << s) + i];
+      const uint32_t U = a[x], V = a[y];
+      a[x] = addmod_t(U, V);
+      a[y] = mulmod_t(submod_t(U, V), w);
+    }
+    __syncthreads();
+  }
+  for (int k = threadIdx.x; k < N; k += blockDim.x) a[k] = mulmod_t(a[k], n_inv);
+  __syncthreads();
+}
+
+template <int LOGN>
+__device__ void ntt_t_lds(uint32_t* a, const uint32_t* __restrict__ w_rev) {
+  constexpr int N = 1 << LOGN;
+  for (int s = 0; s < LOGN; ++s) {
+    const int t = N >> (s + 1);
+    for (int bi = threadIdx.x; bi < N / 2; bi += blockDim.x) {
+      const int i = bi / t, off = bi % t;
+      const int x = i * 2 * t + off, y = x + t;
+      const uint32_t w = w_rev[(1 << s) + i];
+      const uint32_t U = a[x], V = mulmod_t(a[y], w);
+      a[x] = addmod_t(U, V);
+      a[y] = submod_t(U, V);
+    }
+    __syncthreads();
+  }
+}
+
+template <int LOGN>
+__global__ void __launch_bounds__(256) k_encode(Tables T, const uint32_t* __restrict__ slots,
+                                               uint32_t* __restrict__ poly) {
+  constexpr int N = 1 << LOGN;
+  __shared__ uint32_t a[N];
+  const size_t row = blockIdx.x;
+  for (int k = threadIdx.x; k < N; k += blockDim.x) a[k] = slots[row * N + brv(k, LOGN)] % PEPSI_T;
+  __syncthreads();
+  intt_t_lds<LOGN>(a, T.ipsit_rev, T.c->n_inv_t);
+  for (int k = threadIdx.x; k < N; k += blockDim.x) poly[row * N + k] = a[k];
+}
+
+template <int LOGN>
+__global__ void __launch_bounds__(256) k_decode(Tables T, const uint32_t* __restrict__ poly,
+                                               uint32_t* __restrict__ slots) {
+  constexpr int N = 1 << LOGN;
+  __shared__ uint32_t a[N];
+  const size_t row = blockIdx.x;
+  for (int k = threadIdx.x; k < N; k += blockDim.x) a[k] = poly[row * N + k] % PEPSI_T;
+  __syncthreads();
+  ntt_t_lds<LOGN>(a, T.psit_rev);
+  for (int k = threadIdx.x; k < N; k += blockDim.x) slots[row * N + brv(k, LOGN)] = a[k];
+}
+
+// Row (b, j): slot k is 1 iff position j is one of the h codeword positions of bin k.
+template <int LOGN>
+__global__ void __launch_bounds__(256) k_encode_planes(Tables T, const uint16_t* __restrict__ cw, int h,
+                                                      int ell, int b0, uint32_t* __restrict__ poly) {
+  constexpr int N = 1 << LOGN;
+  __shared__ uint32_t a[N];
+  const size_t row = blockIdx.x;
+  const int b = (int)(row / ell) + b0, j = (int)(row % ell);
+  const uint16_t* base = cw + (size_t)b * N * h;
+  for (int k = threadIdx.x; k < N; k += blockDim.x) {
+    const int slot = brv(k, LOGN);
+    uint32_t y = 0;
+    for (int r = 0; r < h; ++r) y |= (base[(size_t)slot * h + r] == j) ? 1u : 0u;
+    a[k] = y;
+  }
+  __syncthreads();
+  intt_t_lds<LOGN>(a, T.ipsit_rev, T.c->n_inv_t);
+  for (int k = threadIdx.x; k < N; k += blockDim.x) poly[row * N + k] = a[k];
+}
+
+template <int LOGN>
+void launch_fwd(const Tables& T, const void* in, NttLoad ld, void* out, NttStore st, int rows,
+                int nprimes, int first, hipStream_t s) {
+  const dim3 grid(rows), block((1 << LOGN) / E);
+#define PEPSI_FWD(L_, S_) hipLaunchKernelGGL((k_ntt_fwd<LOGN, L_, S_>), grid, block, 0, s, T, in, out, nprimes, first)
+  if (st == STORE_U64) {
+    switch (ld) {
+      case LOAD_U64: PEPSI_FWD(LOAD_U64, STORE_U64); break;
+      case LOAD_LIFT_T: PEPSI_FWD(LOAD_LIFT_T, STORE_U64); break;
+      case LOAD_I8: PEPSI_FWD(LOAD_I8, STORE_U64); break;
+      case LOAD_I32: PEPSI_FWD(LOAD_I32, STORE_U64); break;
+    }
+  } else {
+    switch (ld) {
+      case LOAD_U64: PEPSI_FWD(LOAD_U64, STORE_SPLIT27); break;
+      case LOAD_LIFT_T: PEPSI_FWD(LOAD_LIFT_T, STORE_SPLIT27); break;
+      default: break;
+    }
+  }
+#undef PEPSI_FWD
+}
+
+}  // namespace
+
+void ntt_forward(const Tables& T, int logn, const void* in, NttLoad load, void* out, NttStore store,
+                 int rows, int nprimes, int first, hipStream_t s) {
+  if (rows <= 0) return;
+  switch (logn) {
+    case 10: launch_fwd<10>(T, in, load, out, store, rows, nprimes, first, s); break;
+    case 11: launch_fwd<11>(T, in, load, out, store, rows, nprimes, first, s); break;
+    case 12: launch_fwd<12>(T, in, load, out, store, rows, nprimes, first, s); break;
+    case 13: launch_fwd<13>(T, in, load, out, store, rows, nprimes, first, s); break;
+    case 14: launch_fwd<14>(T, in, load, out, store, rows, nprimes, first, s); break;
+  }
+}
+
+void ntt_inverse(const Tables& T, int logn, const uint64_t* in, uint64_t* out, int rows, int nprimes,
+                 int first, hipStream_t s) {
+  if (rows <= 0) return;
+  const dim3 grid(rows), block((1 << logn) / E);
+  switch (logn) {
+    case 10: hipLaunchKernelGGL(k_ntt_inv<10>, grid, block, 0, s, T, in, out, nprimes, first); break;
+    case 11: hipLaunchKernelGGL(k_ntt_inv<11>, grid, block, 0, s, T, in, out, nprimes, first); break;
+    case 12: hipLaunchKernelGGL(k_ntt_inv<12>, grid, block, 0, s, T, in, out, nprimes, first); break;
+    case 13: hipLaunchKernelGGL(k_ntt_inv<13>, grid, block, 0, s, T, in, out, nprimes, first); break;
+    case 14: hipLaunchKernelGGL(k_ntt_inv<14>, grid, block, 0, s, T, in, out, nprimes, first); break;
+  }
+}
+
+#define PEPSI_T_DISPATCH(KERNEL, ...)                                                          \
+  switch (logn) {                                                                              \
+    case 10: hipLaunchKernelGGL(KERNEL<10>, dim3(rows), dim3(256), 0, s, __VA_ARGS__); break;  \
+    case 11: hipLaunchKernelGGL(KERNEL<11>, dim3(rows), dim3(256), 0, s, __VA_ARGS__); break;  \
+    case 12: hipLaunchKernelGGL(KERNEL<12>, dim3(rows), dim3(256), 0, s, __VA_ARGS__); break;  \
+    case 13: hipLaunchKernelGGL(KERNEL<13>, dim3(rows), dim3(256), 0, s, __VA_ARGS__); break;  \
+    case 14: hipLaunchKernelGGL(KERNEL<14>, dim3(rows), dim3(256), 0, s, __VA_ARGS__); break;  \
+  }
+
+void encode_slots(const Tables& T, int logn, const uint32_t* slots, uint32_t* poly, int rows,
+                  hipStream_t s) {
+  if (rows <= 0) return;
+  PEPSI_T_DISPATCH(k_encode, T, slots, poly)
+}
+void decode_slots(const Tables& T, int logn, const uint32_t* poly, uint32_t* slots, int rows,
+                  hipStream_t s) {
+  if (rows <= 0) return;
+  PEPSI_T_DISPATCH(k_decode, T, poly, slots)
+}
+void encode_server_planes(const Tables& T, int logn, const uint16_t* cw, int h, int ell, int b0,
+                          int nb, uint32_t* poly, hipStream_t s) {
+  const int rows = nb * ell;
+  if (rows <= 0) return;
+  PEPSI_T_DISPATCH(k_encode_planes, T, cw, h, ell, b0, poly)
+}
+
+}  // namespace pepsi

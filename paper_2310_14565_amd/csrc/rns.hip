@@ -1,0 +1,595 @@
+// RNS kernels of the BFV evaluation: exact base extension, the exact
+// ciphertext-product rescale round(t d / Q), relinearisation with the RNS
+// gadget, the select-and-sum of the server computation, and elementwise steps.
+//
+// Exactness.  A centred base extension needs v = round(sum_i y_i / q_i) and
+// the rescale needs R = round(sum_i y_i theta_i).  Both are computed in
+// 64.64 fixed point with a proven error below (n + 1) 2^-64; when the
+// fraction lies that close to 1/2 the coefficient takes the exact path
+// (crt_exact: the integer is rebuilt in multiword arithmetic and compared
+// with half the modulus), so every output equals the textbook integer result.
+#include "kernels.hpp"
+
+namespace pepsi {
+namespace {
+
+constexpr int TPB = 256;
+
+struct FixAcc { uint64_t ip, frac; };
+
+// a += y * C, C = floor(c 2^128) with c in [0, 1): keeps the integer part and the top 64
+// fraction bits; the dropped low word and the truncation of C cost < 2^-64 + 2^-74 per term.
+__device__ __forceinline__ void fix_add(FixAcc& a, uint64_t y, const Fix128& C) {
+  const uint64_t p0h = mulhi64(y, C.lo);
+  const uint64_t p1l = y * C.hi, p1h = mulhi64(y, C.hi);
+  const uint64_t w1 = p0h + p1l;
+  const uint64_t w2 = p1h + (w1 < p0h ? 1 : 0);
+  const uint64_t f = a.frac + w1;
+  a.ip += w2 + (f < w1 ? 1 : 0);
+  a.frac = f;
+}
+// round(S) for S in [A, A + (n + 1) 2^-64): floor(A + 1/2), flagged when S may round higher.
+__device__ __forceinline__ uint64_t fix_round(const FixAcc& a, int nterms, bool* ambiguous) {
+  const uint64_t f = a.frac + (1ull << 63);
+  const uint64_t carry = f < a.frac ? 1 : 0;
+  *ambiguous = f > ~0ull - 2ull * (uint64_t)(nterms + 2);
+  return a.ip + carry;
+}
+
+// Exact CRT: X = sum_k y_k * hat_k reduced into [0, M) by v subtractions of M.
+// Returns v; *gt = (2 X > M); X is written to xout when given.
+__device__ __noinline__ int crt_exact(const uint64_t* y, int cnt, const MWord* hat, const MWord& M,
+                                      bool* gt, uint64_t* xout) {
+  uint64_t X[PEPSI_MW];
+  for (int w = 0; w < PEPSI_MW; ++w) X[w] = 0;
+  for (int k = 0; k < cnt; ++k) {
+    uint64_t carry = 0;
+    for (int w = 0; w < PEPSI_MW; ++w) {
+      const u128 t = (u128)y[k] * hat[k].w[w] + X[w] + carry;
+      X[w] = (uint64_t)t;
+      carry = (uint64_t)(t >> 64);
+    }
+  }
+  int v = 0;
+  for (;;) {
+    bool ge = true;                               // X >= M ?
+    for (int w = PEPSI_MW - 1; w >= 0; --w) {
+      if (X[w] != M.w[w]) { ge = X[w] > M.w[w]; break; }
+    }
+    if (!ge) break;
+    uint64_t borrow = 0;
+    for (int w = 0; w < PEPSI_MW; ++w) {
+      const u128 d = (u128)X[w] - M.w[w] - borrow;
+      X[w] = (uint64_t)d;
+      borrow = (uint64_t)(d >> 64) & 1;
+    }
+    ++v;
+  }
+  // 2X > M ?
+  bool g = false;
+  for (int w = PEPSI_MW - 1; w >= 0; --w) {
+    const uint64_t x2 = (X[w] << 1) | (w > 0 ? X[w - 1] >> 63 : 0);
+    const uint64_t top = w == PEPSI_MW - 1 ? (X[w] >> 63) : 0;   // bit shifted out of the top word
+    if (top) { g = true; break; }
+    if (x2 != M.w[w]) { g = x2 > M.w[w]; break; }
+  }
+  *gt = g;
+  if (xout)
+    for (int w = 0; w < PEPSI_MW; ++w) xout[w] = X[w];
+  return v;
+}
+
+// Centred lift of x (residues mod q_0..q_{L-1}) into the residues mod b_0..b_{K-1}.
+__device__ __forceinline__ void ext_one(const Consts& C, const uint64_t* x, uint64_t* out,
+                                        uint32_t* fallback) {
+  const int L = C.L, K = C.K;
+  uint64_t y[PEPSI_MAXL];
+  FixAcc a{0, 0};
+  for (int i = 0; i < L; ++i) {
+    y[i] = shoup(x[i], C.qhat_inv[i], C.qhat_inv_shoup[i], C.prm[i].p);
+    fix_add(a, y[i], C.inv_q[i]);
+  }
+  bool amb;
+  uint64_t v = fix_round(a, L, &amb);
+  if (amb) {
+    bool gt;
+    v = (uint64_t)crt_exact(y, L, C.qhat_w, C.Qw, &gt, nullptr) + (gt ? 1 : 0);
+    if (fallback) atomicAdd(fallback, 1u);
+  }
+  for (int j = 0; j < K; ++j) {
+    const Prime& P = C.prm[L + j];
+    u128 acc = (u128)v * (P.p - C.q_mod_b[j]);
+    for (int i = 0; i < L; ++i) acc += (u128)y[i] * C.qhat_mod_b[i][j];
+    out[j] = reduce116((uint64_t)acc, (uint64_t)(acc >> 64), P);
+  }
+}
+
+__global__ void __launch_bounds__(TPB) k_ext_q_to_b(Tables T, const uint64_t* __restrict__ in,
+                                                   uint64_t* __restrict__ out, long ostride,
+                                                   uint32_t* fallback) {
+  const Consts& C = *T.c;
+  const int N = C.n, L = C.L, K = C.K;
+  const int k = blockIdx.x * TPB + threadIdx.x;
+  const size_t row = blockIdx.y;
+  if (k >= N) return;
+  uint64_t x[PEPSI_MAXL], o[PEPSI_MAXK];
+  for (int i = 0; i < L; ++i) x[i] = in[(row * L + i) * N + k];
+  ext_one(C, x, o, fallback);
+  for (int j = 0; j < K; ++j) out[row * ostride + (size_t)j * N + k] = o[j];
+}
+
+// alpha[b][r][p]: constant added at every NTT position of c0, limb p, for f_r = S + Delta [-r]_t.
+__global__ void k_factor_constants(Tables T, const uint64_t* __restrict__ scoef, int nb, int h,
+                                   uint64_t* __restrict__ alpha, uint32_t* fallback) {
+  const Consts& C = *T.c;
+  const int N = C.n, L = C.L, K = C.K;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nb * h) return;
+  const int b = idx / h, r = idx % h;
+  uint64_t x[PEPSI_MAXL], xr[PEPSI_MAXL], e0[PEPSI_MAXK], er[PEPSI_MAXK];
+  for (int i = 0; i < L; ++i) {
+    const uint64_t q = C.prm[i].p;
+    x[i] = scoef[((size_t)b * 2 * L + i) * N];                     // c0, limb i, coefficient 0
+    const uint64_t rd = mulmod(C.delta[i], (uint64_t)r, C.prm[i]);  // r Delta mod q_i
+    xr[i] = submod(x[i], rd, q);
+  }
+  ext_one(C, x, e0, fallback);
+  ext_one(C, xr, er, fallback);
+  uint64_t* out = alpha + (size_t)idx * (L + K);
+  for (int i = 0; i < L; ++i) out[i] = submod(xr[i], x[i], C.prm[i].p);
+  for (int j = 0; j < K; ++j) out[L + j] = submod(er[j], e0[j], C.prm[L + j].p);
+}
+
+__global__ void __launch_bounds__(TPB) k_tensor(Tables T, const TensorJob* __restrict__ jobs) {
+  const Consts& C = *T.c;
+  const int N = C.n, L = C.L, K = C.K, P = L + K;
+  const int k = blockIdx.x * TPB + threadIdx.x;
+  const int p = blockIdx.y;
+  const TensorJob J = jobs[blockIdx.z];
+  if (k >= N) return;
+  const Prime& pr = C.prm[p];
+  uint64_t x0, x1, y0, y1;
+  if (p < L) {
+    x0 = J.xq[(size_t)p * N + k]; x1 = J.xq[(size_t)(L + p) * N + k];
+    y0 = J.yq[(size_t)p * N + k]; y1 = J.yq[(size_t)(L + p) * N + k];
+  } else {
+    x0 = J.xb[(size_t)(p - L) * N + k]; x1 = J.xb[(size_t)(K + p - L) * N + k];
+    y0 = J.yb[(size_t)(p - L) * N + k]; y1 = J.yb[(size_t)(K + p - L) * N + k];
+  }
+  if (J.ax) x0 = addmod(x0, J.ax[p], pr.p);
+  if (J.ay) y0 = addmod(y0, J.ay[p], pr.p);
+  J.d[(size_t)p * N + k] = mulmod(x0, y0, pr);
+  const u128 m = (u128)x0 * y1 + (u128)x1 * y0;
+  J.d[(size_t)(P + p) * N + k] = reduce116((uint64_t)m, (uint64_t)(m >> 64), pr);
+  J.d[(size_t)(2 * P + p) * N + k] = mulmod(x1, y1, pr);
+}
+
+// round(t d / Q) into B, then the centred B -> Q extension.
+__global__ void __launch_bounds__(TPB) k_scale_round(Tables T, const uint64_t* __restrict__ d,
+                                                    uint64_t* __restrict__ out, uint32_t* fallback) {
+  const Consts& C = *T.c;
+  const int N = C.n, L = C.L, K = C.K, P = L + K;
+  const int k = blockIdx.x * TPB + threadIdx.x;
+  const size_t poly = blockIdx.y;                 // row * 3 + component
+  if (k >= N) return;
+  uint64_t y[PEPSI_MAXP];
+  for (int p = 0; p < P; ++p) {
+    const uint64_t v = d[(poly * P + p) * N + k];
+    y[p] = shoup(v, C.phat_inv[p], C.phat_inv_shoup[p], C.prm[p].p);
+  }
+  FixAcc a{0, 0};
+  for (int i = 0; i < L; ++i) fix_add(a, y[i], C.theta[i]);
+  bool amb;
+  uint64_t R = fix_round(a, L, &amb);
+  if (amb) {
+    // frac(sum y_i r_i / q_i) > 1/2  <=>  the integer with residues y_i r_i (Q/q_i) exceeds Q/2
+    uint64_t z[PEPSI_MAXL];
+    for (int i = 0; i < L; ++i) z[i] = mulmod(y[i], C.tb_mod_q[i], C.prm[i]);
+    bool gt;
+    crt_exact(z, L, C.qhat_w, C.Qw, &gt, nullptr);
+    R = a.ip + (gt ? 1 : 0);
+    if (fallback) atomicAdd(fallback, 1u);
+  }
+  // z_j = round(t d / Q) mod b_j
+  uint64_t yb[PEPSI_MAXK];
+  FixAcc fb{0, 0};
+  for (int j = 0; j < K; ++j) {
+    const Prime& pr = C.prm[L + j];
+    u128 acc = (u128)y[L + j] * C.tbhat_mod_b[j] + R;
+    for (int i = 0; i < L; ++i) acc += (u128)y[i] * C.omega_mod_b[i][j];
+    const uint64_t zj = reduce116((uint64_t)acc, (uint64_t)(acc >> 64), pr);
+    yb[j] = shoup(zj, C.bhat_inv[j], C.bhat_inv_shoup[j], pr.p);
+    fix_add(fb, yb[j], C.inv_b[j]);
+  }
+  uint64_t v = fix_round(fb, K, &amb);
+  if (amb) {
+    bool gt;
+    v = (uint64_t)crt_exact(yb, K, C.bhat_w, C.Bw, &gt, nullptr) + (gt ? 1 : 0);
+    if (fallback) atomicAdd(fallback, 1u);
+  }
+  for (int i = 0; i < L; ++i) {
+    const Prime& pr = C.prm[i];
+    u128 acc = (u128)v * (pr.p - C.b_mod_q[i]);
+    for (int j = 0; j < K; ++j) acc += (u128)yb[j] * C.bhat_mod_q[j][i];
+    out[(poly * L + i) * N + k] = reduce116((uint64_t)acc, (uint64_t)(acc >> 64), pr);
+  }
+}
+
+__global__ void __launch_bounds__(TPB) k_relin_digits(Tables T, const uint64_t* __restrict__ c3,
+                                                     uint64_t* __restrict__ D) {
+  const Consts& C = *T.c;
+  const int N = C.n, L = C.L;
+  const int k = blockIdx.x * TPB + threadIdx.x;
+  const size_t row = blockIdx.y;
+  if (k >= N) return;
+  for (int i = 0; i < L; ++i) {
+    const uint64_t v = c3[((row * 3 + 2) * L + i) * N + k];
+    const uint64_t Di = shoup(v, C.qhat_inv[i], C.qhat_inv_shoup[i], C.prm[i].p);
+    for (int j = 0; j < L; ++j) {
+      const uint64_t q = C.prm[j].p;
+      D[((row * L + i) * L + j) * N + k] = Di >= q ? Di - q : Di;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(TPB) k_relin_inner(Tables T, const uint64_t* __restrict__ dhat,
+                                                    const uint64_t* __restrict__ Dhat,
+                                                    const uint64_t* __restrict__ rlk,
+                                                    uint64_t* __restrict__ out) {
+  const Consts& C = *T.c;
+  const int N = C.n, L = C.L;
+  const int k = blockIdx.x * TPB + threadIdx.x;
+  const int j = blockIdx.y;
+  const size_t row = blockIdx.z;
+  if (k >= N) return;
+  const Prime& pr = C.prm[j];
+  u128 a0 = dhat[((row * 3 + 0) * L + j) * N + k];
+  u128 a1 = dhat[((row * 3 + 1) * L + j) * N + k];
+  for (int i = 0; i < L; ++i) {
+    const uint64_t dv = Dhat[((row * L + i) * L + j) * N + k];
+    a0 += (u128)dv * rlk[(((size_t)i * 2 + 0) * L + j) * N + k];
+    a1 += (u128)dv * rlk[(((size_t)i * 2 + 1) * L + j) * N + k];
+  }
+  out[(row * 2 + 0) * L * N + (size_t)j * N + k] = reduce116((uint64_t)a0, (uint64_t)(a0 >> 64), pr);
+  out[(row * 2 + 1) * L * N + (size_t)j * N + k] = reduce116((uint64_t)a1, (uint64_t)(a1 >> 64), pr);
+}
+
+__global__ void __launch_bounds__(TPB) k_accumulate(Tables T, const uint64_t* __restrict__ x,
+                                                   long xstride, int rows, uint64_t* __restrict__ acc) {
+  const Consts& C = *T.c;
+  const int N = C.n, L = C.L;
+  const int k = blockIdx.x * TPB + threadIdx.x;
+  const int cl = blockIdx.y;                       // component * L + limb
+  if (k >= N) return;
+  const Prime& pr = C.prm[cl % L];
+  uint64_t s = acc[(size_t)cl * N + k];
+  int r = 0;
+  while (r < rows) {
+    u128 t = s;
+    const int end = min(rows, r + 1000);           // 1000 * 2^54 stays below 2^116
+    for (; r < end; ++r) t += x[(size_t)r * xstride + (size_t)cl * N + k];
+    s = reduce116((uint64_t)t, (uint64_t)(t >> 64), pr);
+  }
+  acc[(size_t)cl * N + k] = s;
+}
+
+// Select-and-sum.  Thread = one slot position k of one limb; IB server batches at a time.
+// Products of two 54-bit residues are split into 27-bit halves so that each of the four
+// partial-product accumulators stays below 2^64 over up to 1024 terms (1024 (2^27-1)^2 < 2^64).
+constexpr int IB = 8;
+__global__ void __launch_bounds__(TPB) k_select_sum(Tables T, const uint64_t* __restrict__ Cn,
+                                                   const uint64_t* __restrict__ Pc, int ell, int nb,
+                                                   uint64_t* __restrict__ S, long sstride) {
+  const Consts& C = *T.c;
+  const int N = C.n, L = C.L;
+  const int k = blockIdx.x * TPB + threadIdx.x;
+  const int l = blockIdx.y;
+  const int b0 = blockIdx.z * IB;
+  const int nbl = min(IB, nb - b0);
+  if (k >= N) return;
+  const Prime& pr = C.prm[l];
+  constexpr uint64_t M27 = (1ull << 27) - 1;
+  uint64_t res[2][IB];
+  for (int c = 0; c < 2; ++c)
+    for (int b = 0; b < IB; ++b) res[c][b] = 0;
+  for (int j0 = 0; j0 < ell; j0 += 1024) {
+    const int j1 = min(ell, j0 + 1024);
+    uint64_t acc[2][IB][4];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int b = 0; b < IB; ++b)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[c][b][q] = 0;
+    for (int j = j0; j < j1; ++j) {
+      const uint64_t c0 = Cn[(((size_t)j * 2 + 0) * L + l) * N + k];
+      const uint64_t c1 = Cn[(((size_t)j * 2 + 1) * L + l) * N + k];
+      const uint32_t a[2][2] = {{(uint32_t)(c0 & M27), (uint32_t)(c0 >> 27)},
+                                {(uint32_t)(c1 & M27), (uint32_t)(c1 >> 27)}};
+#pragma unroll
+      for (int b = 0; b < IB; ++b) {
+        if (b < nbl) {
+          const uint64_t w = Pc[(((size_t)(b0 + b) * ell + j) * L + l) * N + k];
+          const uint32_t blo = (uint32_t)w, bhi = (uint32_t)(w >> 32);
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            acc[c][b][0] += (uint64_t)a[c][0] * blo;
+            acc[c][b][1] += (uint64_t)a[c][0] * bhi;
+            acc[c][b][2] += (uint64_t)a[c][1] * blo;
+            acc[c][b][3] += (uint64_t)a[c][1] * bhi;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int b = 0; b < IB; ++b) {
+        const u128 mid = (u128)acc[c][b][1] + acc[c][b][2];
+        const u128 v = (u128)acc[c][b][0] + (mid << 27) + ((u128)acc[c][b][3] << 54) + res[c][b];
+        res[c][b] = reduce128((uint64_t)v, (uint64_t)(v >> 64), pr);
+      }
+  }
+  for (int b = 0; b < nbl; ++b)
+    for (int c = 0; c < 2; ++c)
+      S[(size_t)(b0 + b) * sstride + ((size_t)c * L + l) * N + k] = res[c][b];
+}
+
+__global__ void __launch_bounds__(TPB) k_pointwise(Tables T, const uint64_t* __restrict__ a,
+                                                  const uint64_t* __restrict__ b, uint64_t* __restrict__ out,
+                                                  int nprimes, int bcast) {
+  const Consts& C = *T.c;
+  const int N = C.n;
+  const int k = blockIdx.x * TPB + threadIdx.x;
+  const int p = blockIdx.y;
+  const size_t row = blockIdx.z;
+  if (k >= N) return;
+  const size_t ia = (row * nprimes + p) * N + k;
+  const size_t ib = bcast ? (size_t)p * N + k : ia;
+  out[ia] = mulmod(a[ia], b[ib], C.prm[p]);
+}
+
+__global__ void __launch_bounds__(TPB) k_add_rows(Tables T, const uint64_t* __restrict__ a,
+                                                 const uint64_t* __restrict__ b, uint64_t* __restrict__ out,
+                                                 int nprimes) {
+  const Consts& C = *T.c;
+  const int N = C.n;
+  const int k = blockIdx.x * TPB + threadIdx.x;
+  const int p = blockIdx.y;
+  const size_t row = blockIdx.z;
+  if (k >= N) return;
+  const size_t i = (row * nprimes + p) * N + k;
+  out[i] = addmod(a[i], b[i], C.prm[p].p);
+}
+
+struct KQ { uint64_t k[PEPSI_MAXL]; };
+__global__ void __launch_bounds__(TPB) k_scale_const(Tables T, uint64_t* __restrict__ ct, KQ kq) {
+  const Consts& C = *T.c;
+  const int N = C.n, L = C.L;
+  const int k = blockIdx.x * TPB + threadIdx.x;
+  const int cl = blockIdx.y;
+  if (k >= N) return;
+  const int l = cl % L;
+  uint64_t& v = ct[(size_t)cl * N + k];
+  v = mulmod(v, kq.k[l], C.prm[l]);
+}
+
+__device__ __forceinline__ uint64_t lift_t(uint32_t m, uint64_t q) {
+  return m <= (PEPSI_T - 1) / 2 ? (uint64_t)m : q - (uint64_t)(PEPSI_T - m);
+}
+
+__global__ void __launch_bounds__(TPB) k_add_plain(Tables T, uint64_t* __restrict__ ct,
+                                                  const uint32_t* __restrict__ m) {
+  const Consts& C = *T.c;
+  const int N = C.n;
+  const int k = blockIdx.x * TPB + threadIdx.x;
+  const int l = blockIdx.y;
+  if (k >= N) return;
+  const Prime& pr = C.prm[l];
+  const uint64_t dm = mulmod(C.delta[l], lift_t(m[k], pr.p), pr);
+  uint64_t& v = ct[(size_t)l * N + k];
+  v = addmod(v, dm, pr.p);
+}
+
+__global__ void __launch_bounds__(TPB) k_encrypt_finish(Tables T, const uint32_t* __restrict__ m,
+                                                       const uint64_t* __restrict__ as,
+                                                       const int32_t* __restrict__ e,
+                                                       const uint64_t* __restrict__ a,
+                                                       uint64_t* __restrict__ ct) {
+  const Consts& C = *T.c;
+  const int N = C.n, L = C.L;
+  const int k = blockIdx.x * TPB + threadIdx.x;
+  const int l = blockIdx.y;
+  const size_t idx = blockIdx.z;
+  if (k >= N) return;
+  const Prime& pr = C.prm[l];
+  const uint64_t q = pr.p;
+  const uint64_t dm = mulmod(C.delta[l], lift_t(m[idx * N + k], q), pr);
+  const int32_t ev = e[idx * N + k];
+  const uint64_t eq = ev >= 0 ? (uint64_t)ev : q - (uint64_t)(-(int64_t)ev);
+  const uint64_t v = addmod(as[(idx * L + l) * N + k], eq, q);
+  ct[((idx * 2 + 0) * L + l) * N + k] = submod(dm, v, q);
+  ct[((idx * 2 + 1) * L + l) * N + k] = a[(idx * L + l) * N + k];
+}
+
+__global__ void __launch_bounds__(TPB) k_decrypt_round(Tables T, const uint64_t* __restrict__ x,
+                                                      uint32_t* __restrict__ m, uint32_t* fallback) {
+  const Consts& C = *T.c;
+  const int N = C.n, L = C.L;
+  const int k = blockIdx.x * TPB + threadIdx.x;
+  const size_t idx = blockIdx.y;
+  if (k >= N) return;
+  uint64_t y[PEPSI_MAXL];
+  FixAcc a{0, 0};
+  for (int i = 0; i < L; ++i) {
+    y[i] = shoup(x[(idx * L + i) * N + k], C.qhat_inv[i], C.qhat_inv_shoup[i], C.prm[i].p);
+    fix_add(a, y[i], C.t_over_q[i]);
+  }
+  bool amb;
+  uint64_t R = fix_round(a, L, &amb);
+  if (amb) {
+    uint64_t z[PEPSI_MAXL];
+    for (int i = 0; i < L; ++i) z[i] = mulmod(y[i], C.t_mod_q[i], C.prm[i]);
+    bool gt;
+    crt_exact(z, L, C.qhat_w, C.Qw, &gt, nullptr);
+    R = a.ip + (gt ? 1 : 0);
+    if (fallback) atomicAdd(fallback, 1u);
+  }
+  m[idx * N + k] = (uint32_t)(R % PEPSI_T);
+}
+
+__global__ void __launch_bounds__(TPB) k_noise_bits(Tables T, const uint64_t* __restrict__ x,
+                                                   uint32_t* out) {
+  const Consts& C = *T.c;
+  const int N = C.n, L = C.L;
+  const int k = blockIdx.x * TPB + threadIdx.x;
+  const size_t idx = blockIdx.y;
+  if (k >= N) return;
+  uint64_t z[PEPSI_MAXL];
+  for (int i = 0; i < L; ++i) {
+    const uint64_t tx = mulmod(x[(idx * L + i) * N + k], C.t_mod_q[i], C.prm[i]);
+    z[i] = shoup(tx, C.qhat_inv[i], C.qhat_inv_shoup[i], C.prm[i].p);
+  }
+  bool gt;
+  uint64_t X[PEPSI_MW];
+  crt_exact(z, L, C.qhat_w, C.Qw, &gt, X);
+  if (gt) {                                        // centred magnitude Q - X
+    uint64_t borrow = 0;
+    for (int w = 0; w < PEPSI_MW; ++w) {
+      const u128 d = (u128)C.Qw.w[w] - X[w] - borrow;
+      X[w] = (uint64_t)d;
+      borrow = (uint64_t)(d >> 64) & 1;
+    }
+  }
+  uint32_t bits = 0;
+  for (int w = PEPSI_MW - 1; w >= 0; --w)
+    if (X[w]) { bits = 64 * w + 64 - __clzll(X[w]); break; }
+  atomicMax(out, bits);
+}
+
+__global__ void __launch_bounds__(TPB) k_keygen_finish(Tables T, const uint64_t* __restrict__ s2,
+                                                      const uint64_t* __restrict__ as,
+                                                      const int32_t* __restrict__ e,
+                                                      const uint64_t* __restrict__ a,
+                                                      uint64_t* __restrict__ rlk) {
+  const Consts& C = *T.c;
+  const int N = C.n, L = C.L;
+  const int k = blockIdx.x * TPB + threadIdx.x;
+  const int l = blockIdx.y;
+  const int i = blockIdx.z;
+  if (k >= N) return;
+  const Prime& pr = C.prm[l];
+  const uint64_t q = pr.p;
+  const uint64_t g = (l == i) ? mulmod(C.qhat_mod_q[i], s2[(size_t)l * N + k], pr) : 0;
+  const int32_t ev = e[(size_t)i * N + k];
+  const uint64_t eq = ev >= 0 ? (uint64_t)ev : q - (uint64_t)(-(int64_t)ev);
+  const uint64_t v = addmod(as[((size_t)i * L + l) * N + k], eq, q);
+  rlk[(((size_t)i * 2 + 0) * L + l) * N + k] = submod(g, v, q);
+  rlk[(((size_t)i * 2 + 1) * L + l) * N + k] = a[((size_t)i * L + l) * N + k];
+}
+
+// x = c0 + c1 s in NTT form: cth [count][2][L][N], sh [L][N] -> x [count][L][N]
+__global__ void __launch_bounds__(TPB) k_phase(Tables T, const uint64_t* __restrict__ cth,
+                                              const uint64_t* __restrict__ sh, uint64_t* __restrict__ x) {
+  const Consts& C = *T.c;
+  const int N = C.n, L = C.L;
+  const int k = blockIdx.x * TPB + threadIdx.x;
+  const int l = blockIdx.y;
+  const size_t idx = blockIdx.z;
+  if (k >= N) return;
+  const Prime& pr = C.prm[l];
+  const uint64_t c0 = cth[((idx * 2 + 0) * L + l) * N + k];
+  const uint64_t c1 = cth[((idx * 2 + 1) * L + l) * N + k];
+  x[(idx * L + l) * N + k] = addmod(c0, mulmod(c1, sh[(size_t)l * N + k], pr), pr.p);
+}
+
+inline dim3 grid_for(int N, int y, int z = 1) { return dim3((N + TPB - 1) / TPB, y, z); }
+
+}  // namespace
+
+void ext_q_to_b(const Tables& T, const Consts& hc, const uint64_t* in, uint64_t* out, long ostride,
+                int rows, uint32_t* fb, hipStream_t s) {
+  if (rows <= 0) return;
+  hipLaunchKernelGGL(k_ext_q_to_b, grid_for(hc.n, rows), dim3(TPB), 0, s, T, in, out, ostride, fb);
+}
+void factor_constants(const Tables& T, const Consts& hc, const uint64_t* scoef, int nb, int h,
+                      uint64_t* alpha, uint32_t* fb, hipStream_t s) {
+  const int n = nb * h;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_factor_constants, dim3((n + 63) / 64), dim3(64), 0, s, T, scoef, nb, h, alpha, fb);
+}
+void tensor(const Tables& T, const Consts& hc, const TensorJob* jobs, int njobs, hipStream_t s) {
+  if (njobs <= 0) return;
+  hipLaunchKernelGGL(k_tensor, grid_for(hc.n, hc.L + hc.K, njobs), dim3(TPB), 0, s, T, jobs);
+}
+void scale_round(const Tables& T, const Consts& hc, const uint64_t* d, uint64_t* out, int rows,
+                 uint32_t* fb, hipStream_t s) {
+  if (rows <= 0) return;
+  hipLaunchKernelGGL(k_scale_round, grid_for(hc.n, rows * 3), dim3(TPB), 0, s, T, d, out, fb);
+}
+void relin_digits(const Tables& T, const Consts& hc, const uint64_t* c3, uint64_t* D, int rows,
+                  hipStream_t s) {
+  if (rows <= 0) return;
+  hipLaunchKernelGGL(k_relin_digits, grid_for(hc.n, rows), dim3(TPB), 0, s, T, c3, D);
+}
+void relin_inner(const Tables& T, const Consts& hc, const uint64_t* dhat, const uint64_t* Dhat,
+                 const uint64_t* rlk, uint64_t* out, int rows, hipStream_t s) {
+  if (rows <= 0) return;
+  hipLaunchKernelGGL(k_relin_inner, grid_for(hc.n, hc.L, rows), dim3(TPB), 0, s, T, dhat, Dhat, rlk, out);
+}
+void accumulate(const Tables& T, const Consts& hc, const uint64_t* x, long xstride, int rows,
+                uint64_t* acc, hipStream_t s) {
+  if (rows <= 0) return;
+  hipLaunchKernelGGL(k_accumulate, grid_for(hc.n, 2 * hc.L), dim3(TPB), 0, s, T, x, xstride, rows, acc);
+}
+void select_sum(const Tables& T, const Consts& hc, const uint64_t* Cn, const uint64_t* P, int ell,
+                int nb, uint64_t* S, long sstride, hipStream_t s) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL(k_select_sum, grid_for(hc.n, hc.L, (nb + IB - 1) / IB), dim3(TPB), 0, s, T, Cn,
+                     P, ell, nb, S, sstride);
+}
+void pointwise_mul(const Tables& T, const Consts& hc, const uint64_t* a, const uint64_t* b,
+                   uint64_t* out, int rows, int nprimes, bool bcast, hipStream_t s) {
+  if (rows <= 0) return;
+  hipLaunchKernelGGL(k_pointwise, grid_for(hc.n, nprimes, rows), dim3(TPB), 0, s, T, a, b, out,
+                     nprimes, bcast ? 1 : 0);
+}
+void add_rows(const Tables& T, const Consts& hc, const uint64_t* a, const uint64_t* b, uint64_t* out,
+              int rows, int nprimes, hipStream_t s) {
+  if (rows <= 0) return;
+  hipLaunchKernelGGL(k_add_rows, grid_for(hc.n, nprimes, rows), dim3(TPB), 0, s, T, a, b, out, nprimes);
+}
+void scale_const(const Tables& T, const Consts& hc, uint64_t* ct, const uint64_t* kq, hipStream_t s) {
+  KQ k;
+  for (int l = 0; l < PEPSI_MAXL; ++l) k.k[l] = l < hc.L ? kq[l] : 0;
+  hipLaunchKernelGGL(k_scale_const, grid_for(hc.n, 2 * hc.L), dim3(TPB), 0, s, T, ct, k);
+}
+void add_plain_poly(const Tables& T, const Consts& hc, uint64_t* ct, const uint32_t* m, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_plain, grid_for(hc.n, hc.L), dim3(TPB), 0, s, T, ct, m);
+}
+void encrypt_finish(const Tables& T, const Consts& hc, const uint32_t* m, const uint64_t* as,
+                    const int32_t* e, const uint64_t* a, uint64_t* ct, int count, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_encrypt_finish, grid_for(hc.n, hc.L, count), dim3(TPB), 0, s, T, m, as, e, a, ct);
+}
+void decrypt_round(const Tables& T, const Consts& hc, const uint64_t* x, uint32_t* m, int count,
+                   uint32_t* fb, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_decrypt_round, grid_for(hc.n, count), dim3(TPB), 0, s, T, x, m, fb);
+}
+void noise_bits(const Tables& T, const Consts& hc, const uint64_t* x, int count, uint32_t* out,
+                hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_noise_bits, grid_for(hc.n, count), dim3(TPB), 0, s, T, x, out);
+}
+void phase_ntt(const Tables& T, const Consts& hc, const uint64_t* cth, const uint64_t* sh, uint64_t* x,
+               int count, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_phase, grid_for(hc.n, hc.L, count), dim3(TPB), 0, s, T, cth, sh, x);
+}
+void keygen_finish(const Tables& T, const Consts& hc, const uint64_t* s2, const uint64_t* as,
+                   const int32_t* e, const uint64_t* a, uint64_t* rlk, hipStream_t s) {
+  hipLaunchKernelGGL(k_keygen_finish, grid_for(hc.n, hc.L, hc.L), dim3(TPB), 0, s, T, s2, as, e, a, rlk);
+}
+
+}  // namespace pepsi

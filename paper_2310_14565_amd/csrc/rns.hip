@@ -79,64 +79,93 @@ __device__ __noinline__ int crt_exact(const uint64_t* y, int cnt, const MWord* h
   return v;
 }
 
-// Centred lift of x (residues mod q_0..q_{L-1}) into the residues mod b_0..b_{K-1}.
+// Exact v = round(sum_i y_i / m_i) over Q (resp. B): the rare path of a centred extension.
+template <int L>
+__device__ __noinline__ uint64_t exact_round_q(const Consts& C, const uint64_t* yr, uint32_t* fallback) {
+  uint64_t y[L];
+  for (int i = 0; i < L; ++i) y[i] = yr[i];
+  bool gt;
+  const uint64_t v = (uint64_t)crt_exact(y, L, C.qhat_w, C.Qw, &gt, nullptr) + (gt ? 1 : 0);
+  if (fallback) atomicAdd(fallback, 1u);
+  return v;
+}
+template <int K>
+__device__ __noinline__ uint64_t exact_round_b(const Consts& C, const uint64_t* yr, uint32_t* fallback) {
+  uint64_t y[K];
+  for (int j = 0; j < K; ++j) y[j] = yr[j];
+  bool gt;
+  const uint64_t v = (uint64_t)crt_exact(y, K, C.bhat_w, C.Bw, &gt, nullptr) + (gt ? 1 : 0);
+  if (fallback) atomicAdd(fallback, 1u);
+  return v;
+}
+
+// Centred lift of x (residues mod q_0..q_{L-1}) into the residues mod b_0..b_{K-1}, K = L + 1.
+template <int L>
 __device__ __forceinline__ void ext_one(const Consts& C, const uint64_t* x, uint64_t* out,
                                         uint32_t* fallback) {
-  const int L = C.L, K = C.K;
-  uint64_t y[PEPSI_MAXL];
+  constexpr int K = L + 1;
+  uint64_t y[L];
   FixAcc a{0, 0};
+#pragma unroll
   for (int i = 0; i < L; ++i) {
     y[i] = shoup(x[i], C.qhat_inv[i], C.qhat_inv_shoup[i], C.prm[i].p);
     fix_add(a, y[i], C.inv_q[i]);
   }
   bool amb;
   uint64_t v = fix_round(a, L, &amb);
-  if (amb) {
-    bool gt;
-    v = (uint64_t)crt_exact(y, L, C.qhat_w, C.Qw, &gt, nullptr) + (gt ? 1 : 0);
-    if (fallback) atomicAdd(fallback, 1u);
-  }
+  if (amb) v = exact_round_q<L>(C, y, fallback);
+#pragma unroll
   for (int j = 0; j < K; ++j) {
     const Prime& P = C.prm[L + j];
     u128 acc = (u128)v * (P.p - C.q_mod_b[j]);
+#pragma unroll
     for (int i = 0; i < L; ++i) acc += (u128)y[i] * C.qhat_mod_b[i][j];
     out[j] = reduce116((uint64_t)acc, (uint64_t)(acc >> 64), P);
   }
 }
 
+template <int L>
 __global__ void __launch_bounds__(TPB) k_ext_q_to_b(Tables T, const uint64_t* __restrict__ in,
                                                    uint64_t* __restrict__ out, long ostride,
                                                    uint32_t* fallback) {
   const Consts& C = *T.c;
-  const int N = C.n, L = C.L, K = C.K;
+  constexpr int K = L + 1;
+  const int N = C.n;
   const int k = blockIdx.x * TPB + threadIdx.x;
   const size_t row = blockIdx.y;
   if (k >= N) return;
-  uint64_t x[PEPSI_MAXL], o[PEPSI_MAXK];
+  uint64_t x[L], o[K];
+#pragma unroll
   for (int i = 0; i < L; ++i) x[i] = in[(row * L + i) * N + k];
-  ext_one(C, x, o, fallback);
+  ext_one<L>(C, x, o, fallback);
+#pragma unroll
   for (int j = 0; j < K; ++j) out[row * ostride + (size_t)j * N + k] = o[j];
 }
 
 // alpha[b][r][p]: constant added at every NTT position of c0, limb p, for f_r = S + Delta [-r]_t.
+template <int L>
 __global__ void k_factor_constants(Tables T, const uint64_t* __restrict__ scoef, int nb, int h,
                                    uint64_t* __restrict__ alpha, uint32_t* fallback) {
   const Consts& C = *T.c;
-  const int N = C.n, L = C.L, K = C.K;
+  constexpr int K = L + 1;
+  const int N = C.n;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= nb * h) return;
   const int b = idx / h, r = idx % h;
-  uint64_t x[PEPSI_MAXL], xr[PEPSI_MAXL], e0[PEPSI_MAXK], er[PEPSI_MAXK];
+  uint64_t x[L], xr[L], e0[K], er[K];
+#pragma unroll
   for (int i = 0; i < L; ++i) {
     const uint64_t q = C.prm[i].p;
     x[i] = scoef[((size_t)b * 2 * L + i) * N];                     // c0, limb i, coefficient 0
     const uint64_t rd = mulmod(C.delta[i], (uint64_t)r, C.prm[i]);  // r Delta mod q_i
     xr[i] = submod(x[i], rd, q);
   }
-  ext_one(C, x, e0, fallback);
-  ext_one(C, xr, er, fallback);
+  ext_one<L>(C, x, e0, fallback);
+  ext_one<L>(C, xr, er, fallback);
   uint64_t* out = alpha + (size_t)idx * (L + K);
+#pragma unroll
   for (int i = 0; i < L; ++i) out[i] = submod(xr[i], x[i], C.prm[i].p);
+#pragma unroll
   for (int j = 0; j < K; ++j) out[L + j] = submod(er[j], e0[j], C.prm[L + j].p);
 }
 
@@ -165,25 +194,30 @@ __global__ void __launch_bounds__(TPB) k_tensor(Tables T, const TensorJob* __res
 }
 
 // round(t d / Q) into B, then the centred B -> Q extension.
+template <int L>
 __global__ void __launch_bounds__(TPB) k_scale_round(Tables T, const uint64_t* __restrict__ d,
                                                     uint64_t* __restrict__ out, uint32_t* fallback) {
   const Consts& C = *T.c;
-  const int N = C.n, L = C.L, K = C.K, P = L + K;
+  constexpr int K = L + 1, P = L + K;
+  const int N = C.n;
   const int k = blockIdx.x * TPB + threadIdx.x;
   const size_t poly = blockIdx.y;                 // row * 3 + component
   if (k >= N) return;
-  uint64_t y[PEPSI_MAXP];
+  uint64_t y[P];
+#pragma unroll
   for (int p = 0; p < P; ++p) {
     const uint64_t v = d[(poly * P + p) * N + k];
     y[p] = shoup(v, C.phat_inv[p], C.phat_inv_shoup[p], C.prm[p].p);
   }
   FixAcc a{0, 0};
+#pragma unroll
   for (int i = 0; i < L; ++i) fix_add(a, y[i], C.theta[i]);
   bool amb;
   uint64_t R = fix_round(a, L, &amb);
   if (amb) {
     // frac(sum y_i r_i / q_i) > 1/2  <=>  the integer with residues y_i r_i (Q/q_i) exceeds Q/2
-    uint64_t z[PEPSI_MAXL];
+    uint64_t z[L];
+#pragma unroll
     for (int i = 0; i < L; ++i) z[i] = mulmod(y[i], C.tb_mod_q[i], C.prm[i]);
     bool gt;
     crt_exact(z, L, C.qhat_w, C.Qw, &gt, nullptr);
@@ -191,40 +225,43 @@ __global__ void __launch_bounds__(TPB) k_scale_round(Tables T, const uint64_t* _
     if (fallback) atomicAdd(fallback, 1u);
   }
   // z_j = round(t d / Q) mod b_j
-  uint64_t yb[PEPSI_MAXK];
+  uint64_t yb[K];
   FixAcc fb{0, 0};
+#pragma unroll
   for (int j = 0; j < K; ++j) {
     const Prime& pr = C.prm[L + j];
     u128 acc = (u128)y[L + j] * C.tbhat_mod_b[j] + R;
+#pragma unroll
     for (int i = 0; i < L; ++i) acc += (u128)y[i] * C.omega_mod_b[i][j];
     const uint64_t zj = reduce116((uint64_t)acc, (uint64_t)(acc >> 64), pr);
     yb[j] = shoup(zj, C.bhat_inv[j], C.bhat_inv_shoup[j], pr.p);
     fix_add(fb, yb[j], C.inv_b[j]);
   }
   uint64_t v = fix_round(fb, K, &amb);
-  if (amb) {
-    bool gt;
-    v = (uint64_t)crt_exact(yb, K, C.bhat_w, C.Bw, &gt, nullptr) + (gt ? 1 : 0);
-    if (fallback) atomicAdd(fallback, 1u);
-  }
+  if (amb) v = exact_round_b<K>(C, yb, fallback);
+#pragma unroll
   for (int i = 0; i < L; ++i) {
     const Prime& pr = C.prm[i];
     u128 acc = (u128)v * (pr.p - C.b_mod_q[i]);
+#pragma unroll
     for (int j = 0; j < K; ++j) acc += (u128)yb[j] * C.bhat_mod_q[j][i];
     out[(poly * L + i) * N + k] = reduce116((uint64_t)acc, (uint64_t)(acc >> 64), pr);
   }
 }
 
+template <int L>
 __global__ void __launch_bounds__(TPB) k_relin_digits(Tables T, const uint64_t* __restrict__ c3,
                                                      uint64_t* __restrict__ D) {
   const Consts& C = *T.c;
-  const int N = C.n, L = C.L;
+  const int N = C.n;
   const int k = blockIdx.x * TPB + threadIdx.x;
   const size_t row = blockIdx.y;
   if (k >= N) return;
+#pragma unroll
   for (int i = 0; i < L; ++i) {
     const uint64_t v = c3[((row * 3 + 2) * L + i) * N + k];
     const uint64_t Di = shoup(v, C.qhat_inv[i], C.qhat_inv_shoup[i], C.prm[i].p);
+#pragma unroll
     for (int j = 0; j < L; ++j) {
       const uint64_t q = C.prm[j].p;
       D[((row * L + i) * L + j) * N + k] = Di >= q ? Di - q : Di;
@@ -232,12 +269,13 @@ __global__ void __launch_bounds__(TPB) k_relin_digits(Tables T, const uint64_t* 
   }
 }
 
+template <int L>
 __global__ void __launch_bounds__(TPB) k_relin_inner(Tables T, const uint64_t* __restrict__ dhat,
                                                     const uint64_t* __restrict__ Dhat,
                                                     const uint64_t* __restrict__ rlk,
                                                     uint64_t* __restrict__ out) {
   const Consts& C = *T.c;
-  const int N = C.n, L = C.L;
+  const int N = C.n;
   const int k = blockIdx.x * TPB + threadIdx.x;
   const int j = blockIdx.y;
   const size_t row = blockIdx.z;
@@ -245,6 +283,7 @@ __global__ void __launch_bounds__(TPB) k_relin_inner(Tables T, const uint64_t* _
   const Prime& pr = C.prm[j];
   u128 a0 = dhat[((row * 3 + 0) * L + j) * N + k];
   u128 a1 = dhat[((row * 3 + 1) * L + j) * N + k];
+#pragma unroll
   for (int i = 0; i < L; ++i) {
     const uint64_t dv = Dhat[((row * L + i) * L + j) * N + k];
     a0 += (u128)dv * rlk[(((size_t)i * 2 + 0) * L + j) * N + k];
@@ -273,10 +312,20 @@ __global__ void __launch_bounds__(TPB) k_accumulate(Tables T, const uint64_t* __
   acc[(size_t)cl * N + k] = s;
 }
 
-// Select-and-sum.  Thread = one slot position k of one limb; IB server batches at a time.
-// Products of two 54-bit residues are split into 27-bit halves so that each of the four
-// partial-product accumulators stays below 2^64 over up to 1024 terms (1024 (2^27-1)^2 < 2^64).
+// Select-and-sum.  Thread = one slot position k of one limb, IB server batches at a time (the
+// client ciphertext value is loaded once and used IB times).  A product of two residues below
+// 2^54 is formed from 27-bit halves, a = a1 2^27 + a0 and b = b1 2^27 + b0 (the plaintexts are
+// stored pre-split: b0 in the low and b1 in the high 32-bit word), into three accumulators
+//   lo += a0 b0,  mid += a0 b1 + a1 b0,  hi += a1 b1,
+// each term below 2^54 (2^55 for mid), so 511 terms fit in 64 bits; every 511 terms the value
+// lo + mid 2^27 + hi 2^54 is reduced and restarts lo.  Loads of a partial group are clamped to
+// its last batch so that every load is unconditional (results of padding lanes are dropped).
 constexpr int IB = 8;
+constexpr int FOLD = 511;
+__device__ __forceinline__ uint64_t fold3(uint64_t lo, uint64_t mid, uint64_t hi, const Prime& pr) {
+  const u128 v = (u128)lo + ((u128)mid << 27) + ((u128)hi << 54);
+  return reduce128((uint64_t)v, (uint64_t)(v >> 64), pr);
+}
 __global__ void __launch_bounds__(TPB) k_select_sum(Tables T, const uint64_t* __restrict__ Cn,
                                                    const uint64_t* __restrict__ Pc, int ell, int nb,
                                                    uint64_t* __restrict__ S, long sstride) {
@@ -289,50 +338,53 @@ __global__ void __launch_bounds__(TPB) k_select_sum(Tables T, const uint64_t* __
   if (k >= N) return;
   const Prime& pr = C.prm[l];
   constexpr uint64_t M27 = (1ull << 27) - 1;
-  uint64_t res[2][IB];
+  uint64_t lo[2][IB], mid[2][IB], hi[2][IB];
+#pragma unroll
   for (int c = 0; c < 2; ++c)
-    for (int b = 0; b < IB; ++b) res[c][b] = 0;
-  for (int j0 = 0; j0 < ell; j0 += 1024) {
-    const int j1 = min(ell, j0 + 1024);
-    uint64_t acc[2][IB][4];
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
+    for (int b = 0; b < IB; ++b) lo[c][b] = mid[c][b] = hi[c][b] = 0;
+  const size_t pstep = (size_t)L * N, cstep = (size_t)2 * L * N;
+  const uint64_t* pb[IB];
 #pragma unroll
-      for (int b = 0; b < IB; ++b)
+  for (int b = 0; b < IB; ++b) pb[b] = Pc + ((size_t)(b0 + min(b, nbl - 1)) * ell * L + l) * N + k;
+  const uint64_t* cb = Cn + (size_t)l * N + k;
+  int fold = 0;
+  for (int j = 0; j < ell; ++j) {
+    uint64_t w[IB];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[c][b][q] = 0;
-    for (int j = j0; j < j1; ++j) {
-      const uint64_t c0 = Cn[(((size_t)j * 2 + 0) * L + l) * N + k];
-      const uint64_t c1 = Cn[(((size_t)j * 2 + 1) * L + l) * N + k];
-      const uint32_t a[2][2] = {{(uint32_t)(c0 & M27), (uint32_t)(c0 >> 27)},
-                                {(uint32_t)(c1 & M27), (uint32_t)(c1 >> 27)}};
+    for (int b = 0; b < IB; ++b) w[b] = __builtin_nontemporal_load(pb[b] + j * pstep);
+    const uint64_t c0 = cb[j * cstep], c1 = cb[j * cstep + (size_t)L * N];
+    const uint32_t a00 = (uint32_t)(c0 & M27), a01 = (uint32_t)(c0 >> 27);
+    const uint32_t a10 = (uint32_t)(c1 & M27), a11 = (uint32_t)(c1 >> 27);
 #pragma unroll
-      for (int b = 0; b < IB; ++b) {
-        if (b < nbl) {
-          const uint64_t w = Pc[(((size_t)(b0 + b) * ell + j) * L + l) * N + k];
-          const uint32_t blo = (uint32_t)w, bhi = (uint32_t)(w >> 32);
-#pragma unroll
-          for (int c = 0; c < 2; ++c) {
-            acc[c][b][0] += (uint64_t)a[c][0] * blo;
-            acc[c][b][1] += (uint64_t)a[c][0] * bhi;
-            acc[c][b][2] += (uint64_t)a[c][1] * blo;
-            acc[c][b][3] += (uint64_t)a[c][1] * bhi;
-          }
-        }
-      }
+    for (int b = 0; b < IB; ++b) {
+      const uint32_t blo = (uint32_t)w[b], bhi = (uint32_t)(w[b] >> 32);
+      lo[0][b] += (uint64_t)a00 * blo;
+      mid[0][b] += (uint64_t)a00 * bhi;
+      mid[0][b] += (uint64_t)a01 * blo;
+      hi[0][b] += (uint64_t)a01 * bhi;
+      lo[1][b] += (uint64_t)a10 * blo;
+      mid[1][b] += (uint64_t)a10 * bhi;
+      mid[1][b] += (uint64_t)a11 * blo;
+      hi[1][b] += (uint64_t)a11 * bhi;
     }
+    if (++fold == FOLD) {
+      fold = 0;
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
+      for (int c = 0; c < 2; ++c)
 #pragma unroll
-      for (int b = 0; b < IB; ++b) {
-        const u128 mid = (u128)acc[c][b][1] + acc[c][b][2];
-        const u128 v = (u128)acc[c][b][0] + (mid << 27) + ((u128)acc[c][b][3] << 54) + res[c][b];
-        res[c][b] = reduce128((uint64_t)v, (uint64_t)(v >> 64), pr);
-      }
+        for (int b = 0; b < IB; ++b) {
+          lo[c][b] = fold3(lo[c][b], mid[c][b], hi[c][b], pr);
+          mid[c][b] = hi[c][b] = 0;
+        }
+    }
   }
-  for (int b = 0; b < nbl; ++b)
-    for (int c = 0; c < 2; ++c)
-      S[(size_t)(b0 + b) * sstride + ((size_t)c * L + l) * N + k] = res[c][b];
+#pragma unroll
+  for (int b = 0; b < IB; ++b)
+    if (b < nbl)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+        S[(size_t)(b0 + b) * sstride + ((size_t)c * L + l) * N + k] = fold3(lo[c][b], mid[c][b], hi[c][b], pr);
 }
 
 __global__ void __launch_bounds__(TPB) k_pointwise(Tables T, const uint64_t* __restrict__ a,
@@ -412,15 +464,17 @@ __global__ void __launch_bounds__(TPB) k_encrypt_finish(Tables T, const uint32_t
   ct[((idx * 2 + 1) * L + l) * N + k] = a[(idx * L + l) * N + k];
 }
 
+template <int L>
 __global__ void __launch_bounds__(TPB) k_decrypt_round(Tables T, const uint64_t* __restrict__ x,
                                                       uint32_t* __restrict__ m, uint32_t* fallback) {
   const Consts& C = *T.c;
-  const int N = C.n, L = C.L;
+  const int N = C.n;
   const int k = blockIdx.x * TPB + threadIdx.x;
   const size_t idx = blockIdx.y;
   if (k >= N) return;
-  uint64_t y[PEPSI_MAXL];
+  uint64_t y[L];
   FixAcc a{0, 0};
+#pragma unroll
   for (int i = 0; i < L; ++i) {
     y[i] = shoup(x[(idx * L + i) * N + k], C.qhat_inv[i], C.qhat_inv_shoup[i], C.prm[i].p);
     fix_add(a, y[i], C.t_over_q[i]);
@@ -428,7 +482,8 @@ __global__ void __launch_bounds__(TPB) k_decrypt_round(Tables T, const uint64_t*
   bool amb;
   uint64_t R = fix_round(a, L, &amb);
   if (amb) {
-    uint64_t z[PEPSI_MAXL];
+    uint64_t z[L];
+#pragma unroll
     for (int i = 0; i < L; ++i) z[i] = mulmod(y[i], C.t_mod_q[i], C.prm[i]);
     bool gt;
     crt_exact(z, L, C.qhat_w, C.Qw, &gt, nullptr);
@@ -505,18 +560,30 @@ __global__ void __launch_bounds__(TPB) k_phase(Tables T, const uint64_t* __restr
 
 inline dim3 grid_for(int N, int y, int z = 1) { return dim3((N + TPB - 1) / TPB, y, z); }
 
+#define PEPSI_L_LAUNCH(KERNEL, L, GRID, BLOCK, STREAM, ...)                                  \
+  switch (L) {                                                                               \
+    case 1: hipLaunchKernelGGL(KERNEL<1>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break;       \
+    case 2: hipLaunchKernelGGL(KERNEL<2>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break;       \
+    case 3: hipLaunchKernelGGL(KERNEL<3>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break;       \
+    case 4: hipLaunchKernelGGL(KERNEL<4>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break;       \
+    case 5: hipLaunchKernelGGL(KERNEL<5>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break;       \
+    case 6: hipLaunchKernelGGL(KERNEL<6>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break;       \
+    case 7: hipLaunchKernelGGL(KERNEL<7>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break;       \
+    case 8: hipLaunchKernelGGL(KERNEL<8>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break;       \
+  }
+
 }  // namespace
 
 void ext_q_to_b(const Tables& T, const Consts& hc, const uint64_t* in, uint64_t* out, long ostride,
                 int rows, uint32_t* fb, hipStream_t s) {
   if (rows <= 0) return;
-  hipLaunchKernelGGL(k_ext_q_to_b, grid_for(hc.n, rows), dim3(TPB), 0, s, T, in, out, ostride, fb);
+  PEPSI_L_LAUNCH(k_ext_q_to_b, hc.L, grid_for(hc.n, rows), dim3(TPB), s, T, in, out, ostride, fb);
 }
 void factor_constants(const Tables& T, const Consts& hc, const uint64_t* scoef, int nb, int h,
                       uint64_t* alpha, uint32_t* fb, hipStream_t s) {
   const int n = nb * h;
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_factor_constants, dim3((n + 63) / 64), dim3(64), 0, s, T, scoef, nb, h, alpha, fb);
+  PEPSI_L_LAUNCH(k_factor_constants, hc.L, dim3((n + 63) / 64), dim3(64), s, T, scoef, nb, h, alpha, fb);
 }
 void tensor(const Tables& T, const Consts& hc, const TensorJob* jobs, int njobs, hipStream_t s) {
   if (njobs <= 0) return;
@@ -525,17 +592,17 @@ void tensor(const Tables& T, const Consts& hc, const TensorJob* jobs, int njobs,
 void scale_round(const Tables& T, const Consts& hc, const uint64_t* d, uint64_t* out, int rows,
                  uint32_t* fb, hipStream_t s) {
   if (rows <= 0) return;
-  hipLaunchKernelGGL(k_scale_round, grid_for(hc.n, rows * 3), dim3(TPB), 0, s, T, d, out, fb);
+  PEPSI_L_LAUNCH(k_scale_round, hc.L, grid_for(hc.n, rows * 3), dim3(TPB), s, T, d, out, fb);
 }
 void relin_digits(const Tables& T, const Consts& hc, const uint64_t* c3, uint64_t* D, int rows,
                   hipStream_t s) {
   if (rows <= 0) return;
-  hipLaunchKernelGGL(k_relin_digits, grid_for(hc.n, rows), dim3(TPB), 0, s, T, c3, D);
+  PEPSI_L_LAUNCH(k_relin_digits, hc.L, grid_for(hc.n, rows), dim3(TPB), s, T, c3, D);
 }
 void relin_inner(const Tables& T, const Consts& hc, const uint64_t* dhat, const uint64_t* Dhat,
                  const uint64_t* rlk, uint64_t* out, int rows, hipStream_t s) {
   if (rows <= 0) return;
-  hipLaunchKernelGGL(k_relin_inner, grid_for(hc.n, hc.L, rows), dim3(TPB), 0, s, T, dhat, Dhat, rlk, out);
+  PEPSI_L_LAUNCH(k_relin_inner, hc.L, grid_for(hc.n, hc.L, rows), dim3(TPB), s, T, dhat, Dhat, rlk, out);
 }
 void accumulate(const Tables& T, const Consts& hc, const uint64_t* x, long xstride, int rows,
                 uint64_t* acc, hipStream_t s) {
@@ -575,7 +642,7 @@ void encrypt_finish(const Tables& T, const Consts& hc, const uint32_t* m, const 
 void decrypt_round(const Tables& T, const Consts& hc, const uint64_t* x, uint32_t* m, int count,
                    uint32_t* fb, hipStream_t s) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_decrypt_round, grid_for(hc.n, count), dim3(TPB), 0, s, T, x, m, fb);
+  PEPSI_L_LAUNCH(k_decrypt_round, hc.L, grid_for(hc.n, count), dim3(TPB), s, T, x, m, fb);
 }
 void noise_bits(const Tables& T, const Consts& hc, const uint64_t* x, int count, uint32_t* out,
                 hipStream_t s) {

@@ -95,6 +95,76 @@ def cpu_baseline(cfg, params, server_items, seed):
     }
 
 
+def make_query(params, server_items, cfg, m, planted, seed):
+    """One client request on the GPU: host hashing/encoding, GPU encryption with its own key."""
+    import torch
+    import workload as W
+    n, L, ell = params.n, params.L, params.ell
+    client = W.client_items(m, server_items, planted, cfg["item_bits"], seed)
+    table, valid = params.client_table(client)
+    planes = params.codeword_planes(table, valid)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    sk = dev(W.secret_key(n, seed + 1))
+    a = torch.stack([torch.randint(0, q, (ell, n), generator=g, device="cuda", dtype=torch.int64)
+                     for q in params.q_primes], dim=1).contiguous()
+    e = torch.clamp(torch.round(torch.randn((ell, n), generator=g, device="cuda") * 3.2), -19, 19).to(torch.int32)
+    cts = torch.empty((ell, 2, L, n), dtype=torch.int64, device="cuda")
+    params.encrypt(sk, dev(planes), a, e, cts)
+    ka = torch.stack([torch.randint(0, q, (L, n), generator=g, device="cuda", dtype=torch.int64)
+                      for q in params.q_primes], dim=1).contiguous()
+    ke = torch.clamp(torch.round(torch.randn((L, n), generator=g, device="cuda") * 3.2), -19, 19).to(torch.int32)
+    rlk = torch.empty((L, 2, L, n), dtype=torch.int64, device="cuda")
+    params.keygen_relin(sk, ka, ke, rlk)
+    mask = dev(W.zero_sum_mask(n, 65537, seed + 2))
+    return dict(sk=sk, cts=cts, rlk=rlk, mask=mask, planted=planted, m=m)
+
+
+def batched_leg(params, server, server_items, cfg, nq, steps, seed, plain_value):
+    """Config 'batched': nq queries, m log-uniform in [64, 2048], 25% planted, one launch sequence."""
+    import torch
+    import workload as W
+    n, L = params.n, params.L
+    g = W.rng(seed, "batch-sizes")
+    sizes = np.rint(np.exp(g.uniform(np.log(64), np.log(2048), size=nq))).astype(int)
+    log(f"[bench] batched leg: {nq} queries, m in [{sizes.min()}, {sizes.max()}]")
+    qs = [make_query(params, server_items, cfg, int(m), int(round(0.25 * m)), seed + 100 * (i + 1))
+          for i, m in enumerate(sizes)]
+    outs = [torch.zeros((2, L, n), dtype=torch.int64, device="cuda") for _ in qs]
+    args = ([q["cts"] for q in qs], [q["rlk"] for q in qs], [q["mask"] for q in qs], outs)
+    server.eval_batch(*args)                      # warm-up (allocates the batched workspace)
+    torch.cuda.synchronize()
+    server.timing(enable=True, reset=True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        server.eval_batch(*args)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    tm = server.timing(enable=False)
+    bad = 0
+    for q, o in zip(qs, outs):
+        slots = torch.zeros((1, n), dtype=torch.int32, device="cuda")
+        params.decrypt(q["sk"], o.reshape(1, 2, L, n), slots)
+        torch.cuda.synchronize()
+        card = int(slots.cpu().numpy().view(np.uint32).astype(np.int64).sum() % 65537)
+        bad += card != q["planted"]
+    if bad:
+        log(f"[bench] WRONG RESULT in {bad} batched queries")
+        sys.exit(1)
+    value = nq * n * cfg["mu"] / t
+    return {
+        "queries": nq,
+        "m_range": [int(sizes.min()), int(sizes.max())],
+        "value": round(value, 1),
+        "unit": "slot-comparisons/s",
+        "ms_per_batch": round(1e3 * t, 2),
+        "ms_per_query": round(1e3 * t / nq, 3),
+        "speedup_vs_plain": round(value / plain_value, 3),
+        "select_sum_ms_per_batch": round(tm.select_sum_ms / steps, 2),
+        "checked_cardinalities": nq,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +174,8 @@ def main():
     ap.add_argument("--mode", choices=["cached", "generate"], default="cached",
                     help="server plaintexts resident in NTT form (cached) or regenerated each query")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", type=int, default=64, help="queries per batched launch (0: skip the batched leg)")
+    ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--seed", type=int, default=2024)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -228,6 +300,9 @@ def main():
         "server_max_load": server.max_load,
         "check": {"cardinality": card, "noise_budget_bits": budget},
     }
+    if args.batch > 0:
+        line["batched"] = batched_leg(params, server, server_items, cfg, args.batch, args.batch_steps,
+                                      args.seed + 7, value)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample)")
         line["cpu_baseline"] = cpu_baseline(cfg, params, server_items, args.seed)

@@ -206,6 +206,16 @@ int pepsi_server_eval_range(pepsi_server* server, const uint64_t* d_cts, const u
                             uint32_t batch_begin, uint32_t batch_end, uint32_t finalize,
                             const uint32_t* d_mask, uint64_t* d_out, void* stream);
 
+/* Batched server computation: nq queries (each with its own request, key and optional mask;
+ * arrays of nq device pointers given in host memory, masks may be NULL or hold NULL entries)
+ * are evaluated together, so that every streamed tile of server plaintexts serves all of
+ * them.  Each output equals what pepsi_server_eval gives for that query alone, bit for bit.
+ * nq <= PEPSI_MAX_BATCH.  Workspace grows with the largest nq seen and is kept. */
+#define PEPSI_MAX_BATCH 256
+int pepsi_server_eval_batch(pepsi_server* server, uint32_t nq, const uint64_t* const* d_cts,
+                            const uint64_t* const* d_rlk, const uint32_t* const* d_masks,
+                            uint64_t* const* d_out, void* stream);
+
 /* Event timing of a server's evaluations, for measurement.  While enabled,
  * every select-and-sum launch (the kernel that streams the server plaintexts)
  * and every whole evaluation is bracketed by HIP events on the evaluation's

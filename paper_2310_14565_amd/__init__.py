@@ -72,6 +72,8 @@ _SIGS = {
     "pepsi_server_destroy": (None, [C.c_void_p]),
     "pepsi_server_eval": (C.c_int, [C.c_void_p] * 6),
     "pepsi_server_timing": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(Timing)]),
+    "pepsi_server_eval_batch": (C.c_int, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                          C.c_void_p, C.c_void_p]),
     "pepsi_server_eval_range": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32,
                                           C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pepsi_ntt": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int,
@@ -254,6 +256,16 @@ class Server:
 
     def eval(self, cts, rlk, mask, out, stream=None):
         _check(lib().pepsi_server_eval(self._h, _dev(cts), _dev(rlk), _dev(mask), _dev(out), _stream(stream)))
+
+    def eval_batch(self, cts, rlks, masks, outs, stream=None):
+        """cts, rlks, outs: lists of device tensors (one per query); masks: list of tensors or None."""
+        nq = len(cts)
+        arr = C.c_void_p * nq
+        c_ = arr(*[t.data_ptr() for t in cts])
+        r_ = arr(*[t.data_ptr() for t in rlks])
+        o_ = arr(*[t.data_ptr() for t in outs])
+        m_ = None if masks is None else arr(*[0 if m is None else m.data_ptr() for m in masks])
+        _check(lib().pepsi_server_eval_batch(self._h, nq, c_, r_, m_, o_, _stream(stream)))
 
     def timing(self, enable: bool, reset: bool = False) -> Timing:
         t = Timing()

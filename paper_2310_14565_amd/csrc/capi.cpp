@@ -394,33 +394,23 @@ struct EventTimer {
 
 struct Operand { const uint64_t* q; const uint64_t* b; const uint64_t* alpha; };
 
-// Workspace for the equality product of up to TB server batches at once.
+// Workspace of the server computation for up to Qmax queries at once.  A tile is TBq server
+// batches of every query; the (batch b, query q) "pair" p = b * nq + q carries one
+// select-and-sum ciphertext through the product tree.  Pairs are batch-major, so a partial
+// tile of nb batches uses the first nb * nq pairs (and the first jobs of every tree level).
 struct Engine {
   pepsi_params* P = nullptr;
-  int TB = 0, levels = 0;
-  std::vector<int> jobs_at;            // jobs per batch at each tree level
-  DevBuf chat, rlkhat, acc;            // query-level
-  DevBuf sq, scoef, sb, alpha, e;      // per tile
-  DevBuf d, c3, c3h, D, rcoef;         // per multiply
+  int TBq = 0, Qmax = 0, levels = 0, jobs_nq = -1;
+  std::vector<int> jobs_at;            // tensor jobs per pair at each tree level
+  DevBuf chat, rlkhat, acc;            // per query: request and key in NTT form, running sum
+  DevBuf sq, scoef, sb, alpha, e;      // per pair
+  DevBuf d, c3, c3h, D, rcoef;         // per tensor job
   std::vector<DevBuf> rq, rb;          // per tree level outputs
   DevBuf jobs;                         // device TensorJob arrays, all levels
   std::vector<size_t> job_off;
   DevBuf gen_poly, gen_p;              // on-the-fly plaintext generation
   int GB = 0;
   EventTimer* timer = nullptr;
-
-  void timed_select_sum(const uint64_t* phat, int nb, uint64_t* Sx, hipStream_t s) {
-    const HostParams& H = P->H;
-    const size_t n = H.n, L = H.L;
-    hipEvent_t a = nullptr, b = nullptr;
-    if (timer && timer->on) { a = timer->get(); b = timer->get(); (void)hipEventRecord(a, s); }
-    select_sum(P->T, H.consts, chat.as<uint64_t>(), phat, H.ell, nb, Sx, (long)(2 * L * n), s);
-    if (a) {
-      (void)hipEventRecord(b, s);
-      const uint64_t bytes = 8ull * n * L * ((uint64_t)nb * H.ell + 2ull * H.ell + 2ull * nb);
-      timer->pending.push_back({a, b, 0, bytes});
-    }
-  }
 
   ~Engine() {
     for (DevBuf* b : {&chat, &rlkhat, &acc, &sq, &scoef, &sb, &alpha, &e, &d, &c3, &c3h, &D, &rcoef,
@@ -430,31 +420,32 @@ struct Engine {
     for (auto& b : rb) b.release();
   }
 
-  size_t N() const { return P->H.n; }
-  int L() const { return P->H.L; }
-  int K() const { return P->H.K; }
+  size_t cstride() const { return (size_t)P->H.ell * 2 * P->H.L * P->H.n; }
+  size_t rstride() const { return (size_t)P->H.L * 2 * P->H.L * P->H.n; }
+  size_t ctw() const { return (size_t)2 * P->H.L * P->H.n; }
 
-  // allocate for tiles of TB batches (h >= 2 tree buffers, generation buffers if needed)
-  int setup(pepsi_params* params, int tb, bool need_gen) {
+  int setup(pepsi_params* params, int tbq, int qmax, bool need_gen) {
     P = params;
     const HostParams& H = P->H;
     const size_t n = H.n, L = H.L, K = H.K, Pn = L + K;
-    TB = tb;
+    TBq = tbq;
+    Qmax = qmax;
+    jobs_nq = -1;
+    const size_t PC = (size_t)TBq * Qmax;          // pair capacity
     int rc;
-    if ((rc = chat.ensure((size_t)H.ell * 2 * L * n * 8))) return rc;
-    if ((rc = rlkhat.ensure(L * 2 * L * n * 8))) return rc;
-    if ((rc = acc.ensure(2 * L * n * 8))) return rc;
-    if ((rc = sq.ensure(TB * 2 * L * n * 8))) return rc;
-    if ((rc = e.ensure(TB * 2 * L * n * 8))) return rc;
-    // tree shape
+    if ((rc = chat.ensure(Qmax * cstride() * 8))) return rc;
+    if ((rc = rlkhat.ensure(Qmax * rstride() * 8))) return rc;
+    if ((rc = acc.ensure(Qmax * ctw() * 8))) return rc;
+    if ((rc = sq.ensure(PC * 2 * L * n * 8))) return rc;
+    if ((rc = e.ensure(PC * 2 * L * n * 8))) return rc;
     jobs_at.clear();
     for (int cnt = H.h; cnt > 1; cnt = cnt / 2 + cnt % 2) jobs_at.push_back(cnt / 2);
     levels = (int)jobs_at.size();
     if (levels > 0) {
-      const size_t J = (size_t)TB * jobs_at[0];
-      if ((rc = scoef.ensure(TB * 2 * L * n * 8))) return rc;
-      if ((rc = sb.ensure(TB * 2 * K * n * 8))) return rc;
-      if ((rc = alpha.ensure((size_t)TB * H.h * Pn * 8))) return rc;
+      const size_t J = PC * jobs_at[0];
+      if ((rc = scoef.ensure(PC * 2 * L * n * 8))) return rc;
+      if ((rc = sb.ensure(PC * 2 * K * n * 8))) return rc;
+      if ((rc = alpha.ensure(PC * H.h * Pn * 8))) return rc;
       if ((rc = d.ensure(J * 3 * Pn * n * 8))) return rc;
       if ((rc = c3.ensure(J * 3 * L * n * 8))) return rc;
       if ((rc = c3h.ensure(J * 3 * L * n * 8))) return rc;
@@ -463,63 +454,65 @@ struct Engine {
       rq.resize(levels);
       rb.resize(levels);
       for (int lv = 0; lv + 1 < levels; ++lv) {
-        const size_t Jl = (size_t)TB * jobs_at[lv];
+        const size_t Jl = PC * jobs_at[lv];
         if ((rc = rq[lv].ensure(Jl * 2 * L * n * 8))) return rc;
         if ((rc = rb[lv].ensure(Jl * 2 * K * n * 8))) return rc;
       }
-      if ((rc = build_jobs())) return rc;
     }
     if (need_gen) {
-      GB = std::min(TB, 8);
+      GB = std::min(TBq, 16);
       if ((rc = gen_poly.ensure((size_t)GB * H.ell * n * 4))) return rc;
       if ((rc = gen_p.ensure((size_t)GB * H.ell * L * n * 8))) return rc;
     }
     return 0;
   }
 
-  // Tensor jobs of every level for a full tile, batch-major (job = b * pairs + u), so a
-  // partial tile of nb batches uses the first nb * pairs jobs of each level.
-  int build_jobs() {
+  // Tensor jobs of every level for a full tile of nq queries (job = pair * pairs + u).
+  int build_jobs(int nq) {
+    if (levels == 0 || nq == jobs_nq) return 0;
     const HostParams& H = P->H;
     const size_t n = H.n, L = H.L, K = H.K, Pn = L + K;
+    const int npairs = TBq * nq;
     std::vector<TensorJob> all;
     job_off.clear();
-    std::vector<std::vector<Operand>> ops(TB);
-    for (int b = 0; b < TB; ++b)
+    std::vector<std::vector<Operand>> ops(npairs);
+    for (int p = 0; p < npairs; ++p)
       for (int r = 0; r < H.h; ++r)
-        ops[b].push_back(Operand{sq.as<uint64_t>((size_t)b * 2 * L * n), sb.as<uint64_t>((size_t)b * 2 * K * n),
-                                 alpha.as<uint64_t>(((size_t)b * H.h + r) * Pn)});
+        ops[p].push_back(Operand{sq.as<uint64_t>((size_t)p * 2 * L * n), sb.as<uint64_t>((size_t)p * 2 * K * n),
+                                 alpha.as<uint64_t>(((size_t)p * H.h + r) * Pn)});
     for (int lv = 0; lv < levels; ++lv) {
       const int pairs = jobs_at[lv];
       job_off.push_back(all.size());
-      for (int b = 0; b < TB; ++b)
+      for (int p = 0; p < npairs; ++p)
         for (int u = 0; u < pairs; ++u) {
-          const Operand& x = ops[b][2 * u];
-          const Operand& y = ops[b][2 * u + 1];
-          const size_t j = (size_t)b * pairs + u;
+          const Operand& x = ops[p][2 * u];
+          const Operand& y = ops[p][2 * u + 1];
+          const size_t j = (size_t)p * pairs + u;
           all.push_back(TensorJob{x.q, x.b, y.q, y.b, x.alpha, y.alpha, d.as<uint64_t>(j * 3 * Pn * n)});
         }
       if (lv + 1 < levels) {
-        for (int b = 0; b < TB; ++b) {
+        for (int p = 0; p < npairs; ++p) {
           std::vector<Operand> next;
           for (int u = 0; u < pairs; ++u) {
-            const size_t j = (size_t)b * pairs + u;
+            const size_t j = (size_t)p * pairs + u;
             next.push_back(Operand{rq[lv].as<uint64_t>(j * 2 * L * n), rb[lv].as<uint64_t>(j * 2 * K * n), nullptr});
           }
-          if (ops[b].size() % 2) next.push_back(ops[b].back());
-          ops[b] = next;
+          if (ops[p].size() % 2) next.push_back(ops[p].back());
+          ops[p] = next;
         }
       }
     }
+    HIPCHK(hipDeviceSynchronize());                  // the previous job arrays may still be in use
     int rc = jobs.ensure(all.size() * sizeof(TensorJob));
     if (rc) return rc;
     HIPCHK(hipMemcpy(jobs.p, all.data(), all.size() * sizeof(TensorJob), hipMemcpyHostToDevice));
+    jobs_nq = nq;
     return 0;
   }
 
-  // Ciphertext products + relinearisation of njobs jobs (device array), results in NTT form
-  // into out [njobs][2][L][N]; when ext_out is set also the Q -> B extension in NTT form.
-  void multiply_relin(const TensorJob* dev_jobs, int njobs, const uint64_t* rlk_hat, uint64_t* out,
+  // Products + relinearisation of njobs jobs (results NTT form into out [njobs][2][L][N]);
+  // with ext_out also the Q -> B extension of the results, NTT form.
+  void multiply_relin(const TensorJob* dev_jobs, int njobs, int jobs_per_pair, int nq, uint64_t* out,
                       uint64_t* ext_out, hipStream_t s) {
     const HostParams& H = P->H;
     const int L = H.L, K = H.K, Pn = L + K;
@@ -530,7 +523,8 @@ struct Engine {
     relin_digits(P->T, H.consts, c3.as<uint64_t>(), D.as<uint64_t>(), njobs, s);
     ntt_forward(P->T, H.logn, D.p, LOAD_U64, D.p, STORE_U64, njobs * L * L, L, 0, s);
     ntt_forward(P->T, H.logn, c3.p, LOAD_U64, c3h.p, STORE_U64, njobs * 3 * L, L, 0, s);
-    relin_inner(P->T, H.consts, c3h.as<uint64_t>(), D.as<uint64_t>(), rlk_hat, out, njobs, s);
+    relin_inner(P->T, H.consts, c3h.as<uint64_t>(), D.as<uint64_t>(), rlkhat.as<uint64_t>(), (long)rstride(),
+                jobs_per_pair, nq, out, njobs, s);
     if (ext_out) {
       ntt_inverse(P->T, H.logn, out, rcoef.as<uint64_t>(), njobs * 2 * L, L, 0, s);
       ext_q_to_b(P->T, H.consts, rcoef.as<uint64_t>(), ext_out, (long)K * H.n, njobs * 2,
@@ -539,56 +533,78 @@ struct Engine {
     }
   }
 
-  // Query preparation: client ciphertexts and relinearisation key to NTT form; acc = 0.
-  void begin_query(const uint64_t* cts, const uint64_t* rlk, hipStream_t s) {
+  // Requests and keys of nq queries to NTT form; running sums to zero.
+  void start_queries(int nq, const uint64_t* const* cts, const uint64_t* const* rlk, hipStream_t s) {
     const HostParams& H = P->H;
     const int L = H.L;
-    ntt_forward(P->T, H.logn, cts, LOAD_U64, chat.p, STORE_U64, H.ell * 2 * L, L, 0, s);
-    ntt_forward(P->T, H.logn, rlk, LOAD_U64, rlkhat.p, STORE_U64, L * 2 * L, L, 0, s);
-    (void)hipMemsetAsync(acc.p, 0, 2 * (size_t)L * H.n * 8, s);
+    for (int q = 0; q < nq; ++q) {
+      ntt_forward(P->T, H.logn, cts[q], LOAD_U64, chat.as<uint64_t>(q * cstride()), STORE_U64, H.ell * 2 * L,
+                  L, 0, s);
+      ntt_forward(P->T, H.logn, rlk[q], LOAD_U64, rlkhat.as<uint64_t>(q * rstride()), STORE_U64, L * 2 * L, L,
+                  0, s);
+    }
+    (void)hipMemsetAsync(acc.p, 0, (size_t)nq * ctw() * 8, s);
   }
 
-  // One tile of nb batches: P-hat given (cache) or generated from the codewords.
-  void run_tile(const uint16_t* cw, int b0, int nb, const uint64_t* phat, hipStream_t s) {
+  void timed_select_sum(const uint64_t* phat, int nb, int nq, uint64_t* Sx, hipStream_t s) {
+    const HostParams& H = P->H;
+    const size_t n = H.n, L = H.L;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (timer && timer->on) { a = timer->get(); b = timer->get(); (void)hipEventRecord(a, s); }
+    if (nq == 1)
+      select_sum(P->T, H.consts, chat.as<uint64_t>(), phat, H.ell, nb, Sx, (long)(2 * L * n), s);
+    else
+      select_sum_multi(P->T, H.consts, chat.as<uint64_t>(), (long)cstride(), nq, phat, H.ell, nb, Sx, s);
+    if (a) {
+      (void)hipEventRecord(b, s);
+      const uint64_t bytes =
+          8ull * n * L * ((uint64_t)nb * H.ell + 2ull * H.ell * nq + 2ull * nb * nq);
+      timer->pending.push_back({a, b, 0, bytes});
+    }
+  }
+
+  // One tile: batches [b0, b0 + nb) of nq queries; plaintexts from the cache (phat) or generated.
+  void run_tile(const uint16_t* cw, int b0, int nb, int nq, const uint64_t* phat, hipStream_t s) {
     const HostParams& H = P->H;
     const size_t n = H.n, L = H.L, K = H.K;
     uint64_t* Sq = sq.as<uint64_t>();
+    const int npairs = nb * nq;
     if (phat) {
-      timed_select_sum(phat, nb, Sq, s);
+      timed_select_sum(phat, nb, nq, Sq, s);
     } else {
       for (int g0 = 0; g0 < nb; g0 += GB) {
         const int g = std::min(GB, nb - g0);
         encode_server_planes(P->T, H.logn, cw, H.h, H.ell, b0 + g0, g, gen_poly.as<uint32_t>(), s);
         ntt_forward(P->T, H.logn, gen_poly.p, LOAD_LIFT_T, gen_p.p, STORE_SPLIT27, g * H.ell * (int)L,
                     (int)L, 0, s);
-        timed_select_sum(gen_p.as<uint64_t>(), g, Sq + (size_t)g0 * 2 * L * n, s);
+        timed_select_sum(gen_p.as<uint64_t>(), g, nq, Sq + (size_t)g0 * nq * 2 * L * n, s);
       }
     }
     if (levels == 0) {                                           // h = 1: e = S
-      accumulate(P->T, H.consts, Sq, (long)(2 * L * n), nb, acc.as<uint64_t>(), s);
+      accumulate(P->T, H.consts, Sq, (long)(2 * L * n), nb, nq, acc.as<uint64_t>(), s);
       return;
     }
-    ntt_inverse(P->T, H.logn, Sq, scoef.as<uint64_t>(), nb * 2 * (int)L, (int)L, 0, s);
-    ext_q_to_b(P->T, H.consts, scoef.as<uint64_t>(), sb.as<uint64_t>(), (long)(K * n), nb * 2,
+    ntt_inverse(P->T, H.logn, Sq, scoef.as<uint64_t>(), npairs * 2 * (int)L, (int)L, 0, s);
+    ext_q_to_b(P->T, H.consts, scoef.as<uint64_t>(), sb.as<uint64_t>(), (long)(K * n), npairs * 2,
                P->fallback.as<uint32_t>(), s);
-    ntt_forward(P->T, H.logn, sb.p, LOAD_U64, sb.p, STORE_U64, nb * 2 * (int)K, (int)K, (int)L, s);
-    factor_constants(P->T, H.consts, scoef.as<uint64_t>(), nb, H.h, alpha.as<uint64_t>(),
+    ntt_forward(P->T, H.logn, sb.p, LOAD_U64, sb.p, STORE_U64, npairs * 2 * (int)K, (int)K, (int)L, s);
+    factor_constants(P->T, H.consts, scoef.as<uint64_t>(), npairs, H.h, alpha.as<uint64_t>(),
                      P->fallback.as<uint32_t>(), s);
     for (int lv = 0; lv < levels; ++lv) {
-      const int njobs = nb * jobs_at[lv];
+      const int njobs = npairs * jobs_at[lv];
       const TensorJob* jl = jobs.as<TensorJob>() + job_off[lv];
       const bool last = lv + 1 == levels;
-      multiply_relin(jl, njobs, rlkhat.as<uint64_t>(), last ? e.as<uint64_t>() : rq[lv].as<uint64_t>(),
+      multiply_relin(jl, njobs, jobs_at[lv], nq, last ? e.as<uint64_t>() : rq[lv].as<uint64_t>(),
                      last ? nullptr : rb[lv].as<uint64_t>(), s);
     }
-    accumulate(P->T, H.consts, e.as<uint64_t>(), (long)(2 * L * n), nb, acc.as<uint64_t>(), s);
+    accumulate(P->T, H.consts, e.as<uint64_t>(), (long)(2 * L * n), nb, nq, acc.as<uint64_t>(), s);
   }
 
-  // out = coefficient form of acc, optionally times (h!)^-1 and plus Delta [encode(mask)]_t
-  void finish(bool finalize, const uint32_t* mask, uint64_t* out, hipStream_t s) {
+  // out = coefficient form of query q's sum, optionally times (h!)^-1 plus Delta [encode(mask)]_t
+  void finish(int q, bool finalize, const uint32_t* mask, uint64_t* out, hipStream_t s) {
     const HostParams& H = P->H;
     const int L = H.L;
-    uint64_t* a = acc.as<uint64_t>();
+    uint64_t* a = acc.as<uint64_t>(q * ctw());
     if (finalize) {
       uint64_t hf = 1;
       for (int r = 2; r <= H.h; ++r) hf = hf * r % PEPSI_T;
@@ -600,10 +616,24 @@ struct Engine {
     }
     ntt_inverse(P->T, H.logn, a, out, 2 * L, L, 0, s);
     if (finalize && mask) {
-      uint32_t* m = reinterpret_cast<uint32_t*>(sq.p);           // sq is free after the tiles
+      uint32_t* m = reinterpret_cast<uint32_t*>(e.p);            // e is free after the tiles
       encode_slots(P->T, H.logn, mask, m, 1, s);
       add_plain_poly(P->T, H.consts, out, m, s);
     }
+  }
+
+  // The whole computation for nq queries over batches [begin, stop).
+  int run(const uint16_t* cw, const uint64_t* cache, uint32_t begin, uint32_t stop, int nq,
+          const uint64_t* const* cts, const uint64_t* const* rlk, hipStream_t s) {
+    int rc = build_jobs(nq);
+    if (rc) return rc;
+    start_queries(nq, cts, rlk, s);
+    const size_t per = (size_t)P->H.ell * P->H.L * P->H.n;
+    for (uint32_t b0 = begin; b0 < stop; b0 += TBq) {
+      const int nb = (int)std::min<uint32_t>(TBq, stop - b0);
+      run_tile(cw, (int)b0, nb, nq, cache ? cache + per * b0 : nullptr, s);
+    }
+    return 0;
   }
 };
 
@@ -617,8 +647,10 @@ struct pepsi_server {
   DevBuf cw;            // [mu][N][h] uint16
   DevBuf cache;         // [max_load][ell][L][N] split-27 NTT form
   bool cached = false;
-  Engine eng;
+  Engine eng;            // one query at a time (plain path)
   bool ready = false;
+  Engine beng;           // many queries per launch (batched path)
+  int bqmax = 0;
 };
 
 extern "C" int pepsi_server_create(const pepsi_params* Pc, const uint32_t* items, uint64_t n,
@@ -709,7 +741,7 @@ extern "C" int pepsi_server_eval_range(pepsi_server* sv, const uint64_t* cts, co
   hipStream_t s = S(stream);
   if (!sv->ready) {
     const int tb = std::min<int>(128, std::max<int>(1, (int)sv->max_load));
-    int rc = sv->eng.setup(sv->P, tb, !sv->cached);
+    int rc = sv->eng.setup(sv->P, tb, 1, !sv->cached);
     if (rc) return rc;
     sv->eng.timer = &sv->timer;
     sv->ready = true;
@@ -717,15 +749,54 @@ extern "C" int pepsi_server_eval_range(pepsi_server* sv, const uint64_t* cts, co
   Engine& E = sv->eng;
   hipEvent_t ea = nullptr, eb = nullptr;
   if (sv->timer.on) { ea = sv->timer.get(); eb = sv->timer.get(); (void)hipEventRecord(ea, s); }
-  E.begin_query(cts, rlk, s);
   // batches at or above the fullest bin hold only dummies: their equality ciphertext is (0, 0)
   const uint32_t stop = std::min(end, sv->max_load);
-  const size_t per = (size_t)H.ell * H.L * H.n;
-  for (uint32_t b0 = begin; b0 < stop; b0 += E.TB) {
-    const int nb = (int)std::min<uint32_t>(E.TB, stop - b0);
-    E.run_tile(sv->cw.as<uint16_t>(), (int)b0, nb, sv->cached ? sv->cache.as<uint64_t>(per * b0) : nullptr, s);
+  const uint64_t* c1[1] = {cts};
+  const uint64_t* r1[1] = {rlk};
+  int rc = E.run(sv->cw.as<uint16_t>(), sv->cached ? sv->cache.as<uint64_t>() : nullptr, begin,
+                 std::max(begin, stop), 1, c1, r1, s);
+  if (rc) return rc;
+  E.finish(0, finalize != 0, mask, out, s);
+  if (ea) {
+    (void)hipEventRecord(eb, s);
+    sv->timer.pending.push_back({ea, eb, 1, 0});
   }
-  E.finish(finalize != 0, mask, out, s);
+  HIPCHK(hipGetLastError());
+  return PEPSI_OK;
+}
+
+extern "C" int pepsi_server_eval(pepsi_server* sv, const uint64_t* cts, const uint64_t* rlk,
+                                 const uint32_t* mask, uint64_t* out, void* stream) {
+  if (!sv) return fail(PEPSI_E_ARG, "null argument");
+  return pepsi_server_eval_range(sv, cts, rlk, 0, sv->P->H.mu, 1, mask, out, stream);
+}
+
+extern "C" int pepsi_server_eval_batch(pepsi_server* sv, uint32_t nq, const uint64_t* const* cts,
+                                       const uint64_t* const* rlk, const uint32_t* const* masks,
+                                       uint64_t* const* out, void* stream) {
+  if (!sv || !cts || !rlk || !out) return fail(PEPSI_E_ARG, "null argument");
+  if (nq == 0) return PEPSI_OK;
+  if (nq > PEPSI_MAX_BATCH) return fail(PEPSI_E_ARG, "at most %d queries per batch", PEPSI_MAX_BATCH);
+  for (uint32_t q = 0; q < nq; ++q)
+    if (!cts[q] || !rlk[q] || !out[q]) return fail(PEPSI_E_ARG, "null query pointer %u", q);
+  const HostParams& H = sv->P->H;
+  hipStream_t s = S(stream);
+  if ((int)nq > sv->bqmax) {
+    // batches per tile: one batch group of the multi-query select-and-sum (16)
+    int rc = sv->beng.setup(sv->P, std::min<int>(16, std::max<int>(1, (int)sv->max_load)), (int)nq,
+                            !sv->cached);
+    if (rc) return rc;
+    sv->beng.timer = &sv->timer;
+    sv->bqmax = (int)nq;
+  }
+  Engine& E = sv->beng;
+  hipEvent_t ea = nullptr, eb = nullptr;
+  if (sv->timer.on) { ea = sv->timer.get(); eb = sv->timer.get(); (void)hipEventRecord(ea, s); }
+  const uint32_t stop = std::min<uint32_t>(H.mu, sv->max_load);
+  int rc = E.run(sv->cw.as<uint16_t>(), sv->cached ? sv->cache.as<uint64_t>() : nullptr, 0, stop, (int)nq,
+                 cts, rlk, s);
+  if (rc) return rc;
+  for (uint32_t q = 0; q < nq; ++q) E.finish((int)q, true, masks ? masks[q] : nullptr, out[q], s);
   if (ea) {
     (void)hipEventRecord(eb, s);
     sv->timer.pending.push_back({ea, eb, 1, 0});
@@ -744,11 +815,6 @@ extern "C" int pepsi_server_timing(pepsi_server* sv, int enable, int reset, peps
   return PEPSI_OK;
 }
 
-extern "C" int pepsi_server_eval(pepsi_server* sv, const uint64_t* cts, const uint64_t* rlk,
-                                 const uint32_t* mask, uint64_t* out, void* stream) {
-  if (!sv) return fail(PEPSI_E_ARG, "null argument");
-  return pepsi_server_eval_range(sv, cts, rlk, 0, sv->P->H.mu, 1, mask, out, stream);
-}
 
 // ------------------------------------------------------------------ single steps
 extern "C" int pepsi_ntt(const pepsi_params* P, uint64_t* data, uint32_t rows, uint32_t first,
@@ -855,7 +921,7 @@ extern "C" int pepsi_relin(const pepsi_params* Pc, const uint64_t* ct3, const ui
   ntt_forward(P->T, H.logn, Dd, LOAD_U64, Dd, STORE_U64, (int)(L * L), (int)L, 0, s);
   ntt_forward(P->T, H.logn, ct3, LOAD_U64, c3h, STORE_U64, (int)(3 * L), (int)L, 0, s);
   ntt_forward(P->T, H.logn, rlk, LOAD_U64, rh, STORE_U64, (int)(2 * L * L), (int)L, 0, s);
-  relin_inner(P->T, H.consts, c3h, Dd, rh, o, 1, s);
+  relin_inner(P->T, H.consts, c3h, Dd, rh, 0, 1, 1, o, 1, s);
   ntt_inverse(P->T, H.logn, o, out, (int)(2 * L), (int)L, 0, s);
   HIPCHK(hipGetLastError());
   return PEPSI_OK;

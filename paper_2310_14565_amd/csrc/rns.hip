@@ -272,7 +272,8 @@ __global__ void __launch_bounds__(TPB) k_relin_digits(Tables T, const uint64_t* 
 template <int L>
 __global__ void __launch_bounds__(TPB) k_relin_inner(Tables T, const uint64_t* __restrict__ dhat,
                                                     const uint64_t* __restrict__ Dhat,
-                                                    const uint64_t* __restrict__ rlk,
+                                                    const uint64_t* __restrict__ rlk_base, long rlk_stride,
+                                                    int jobs_per_pair, int nq,
                                                     uint64_t* __restrict__ out) {
   const Consts& C = *T.c;
   const int N = C.n;
@@ -281,6 +282,8 @@ __global__ void __launch_bounds__(TPB) k_relin_inner(Tables T, const uint64_t* _
   const size_t row = blockIdx.z;
   if (k >= N) return;
   const Prime& pr = C.prm[j];
+  // pair = b * nq + q: the key of the job's query
+  const uint64_t* rlk = rlk_base + (size_t)((row / jobs_per_pair) % nq) * rlk_stride;
   u128 a0 = dhat[((row * 3 + 0) * L + j) * N + k];
   u128 a1 = dhat[((row * 3 + 1) * L + j) * N + k];
 #pragma unroll
@@ -293,23 +296,26 @@ __global__ void __launch_bounds__(TPB) k_relin_inner(Tables T, const uint64_t* _
   out[(row * 2 + 1) * L * N + (size_t)j * N + k] = reduce116((uint64_t)a1, (uint64_t)(a1 >> 64), pr);
 }
 
+// acc[q] += sum over batches b of x[b * nq + q]  (each entry [2][L][N], xstride words apart)
 __global__ void __launch_bounds__(TPB) k_accumulate(Tables T, const uint64_t* __restrict__ x,
-                                                   long xstride, int rows, uint64_t* __restrict__ acc) {
+                                                   long xstride, int nb, int nq, uint64_t* __restrict__ acc) {
   const Consts& C = *T.c;
   const int N = C.n, L = C.L;
   const int k = blockIdx.x * TPB + threadIdx.x;
   const int cl = blockIdx.y;                       // component * L + limb
+  const int q = blockIdx.z;
   if (k >= N) return;
   const Prime& pr = C.prm[cl % L];
-  uint64_t s = acc[(size_t)cl * N + k];
-  int r = 0;
-  while (r < rows) {
+  uint64_t* a = acc + (size_t)q * 2 * L * N;
+  uint64_t s = a[(size_t)cl * N + k];
+  int b = 0;
+  while (b < nb) {
     u128 t = s;
-    const int end = min(rows, r + 1000);           // 1000 * 2^54 stays below 2^116
-    for (; r < end; ++r) t += x[(size_t)r * xstride + (size_t)cl * N + k];
+    const int end = min(nb, b + 1000);             // 1000 * 2^54 stays below 2^116
+    for (; b < end; ++b) t += x[((size_t)b * nq + q) * xstride + (size_t)cl * N + k];
     s = reduce116((uint64_t)t, (uint64_t)(t >> 64), pr);
   }
-  acc[(size_t)cl * N + k] = s;
+  a[(size_t)cl * N + k] = s;
 }
 
 // Select-and-sum.  Thread = one slot position k of one limb, IB server batches at a time (the
@@ -385,6 +391,113 @@ __global__ void __launch_bounds__(TPB) k_select_sum(Tables T, const uint64_t* __
 #pragma unroll
       for (int c = 0; c < 2; ++c)
         S[(size_t)(b0 + b) * sstride + ((size_t)c * L + l) * N + k] = fold3(lo[c][b], mid[c][b], hi[c][b], pr);
+}
+
+// Select-and-sum of several queries against one tile of server plaintexts.
+// A workgroup of 4 waves owns 64 slot positions (one per lane) of one limb, MQ = 2 queries and
+// MB = 16 batches; wave w computes both queries x batches 4 w + {0..3} (16 outputs per lane,
+// three accumulators each as in k_select_sum), loading the next code position's values while
+// it multiplies the current ones.  The waves of a workgroup read the same client values (L1),
+// and blocks are numbered so that all query groups of one (positions, limb, batch group)
+// region are dispatched consecutively to the same XCD and share its L2 for the plaintexts.
+constexpr int MQ = 2, MB = 16, MBB = 4, MTPB = 64 * (MB / MBB);
+__global__ void __launch_bounds__(MTPB) k_select_sum_multi(Tables T, const uint64_t* __restrict__ Cq,
+                                                          long cq_stride, int nq,
+                                                          const uint64_t* __restrict__ Pc, int ell, int nb,
+                                                          uint64_t* __restrict__ S, int regions, int qgroups) {
+  const Consts& C = *T.c;
+  const int N = C.n, L = C.L;
+  const int bid = blockIdx.x, xcd = bid & 7, w8 = bid >> 3;
+  const int qg = w8 % qgroups, region = (w8 / qgroups) * 8 + xcd;
+  if (region >= regions) return;
+  const int kchunks = N / 64;
+  const int kc = region % kchunks, l = (region / kchunks) % L, bg = region / (kchunks * L);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int kbase = kc * 64, q0 = qg * MQ, b0 = bg * MB + wave * MBB;
+  const int nql = min(MQ, nq - q0), nbl = min(MBB, nb - b0);
+  if (nbl <= 0) return;
+  const Prime& pr = C.prm[l];
+  constexpr uint64_t M27 = (1ull << 27) - 1;
+  const size_t cjs = (size_t)2 * L * N, pjs = (size_t)L * N;
+  const uint64_t* cp[MQ][2];
+  const uint64_t* pp[MBB];
+#pragma unroll
+  for (int a = 0; a < MQ; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+      cp[a][c] = Cq + (size_t)(q0 + min(a, nql - 1)) * cq_stride + ((size_t)c * L + l) * N + kbase + lane;
+#pragma unroll
+  for (int b = 0; b < MBB; ++b)
+    pp[b] = Pc + ((size_t)(b0 + min(b, nbl - 1)) * ell * L + l) * N + kbase + lane;
+  uint64_t lo[MQ][2][MBB], mid[MQ][2][MBB], hi[MQ][2][MBB];
+#pragma unroll
+  for (int a = 0; a < MQ; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int b = 0; b < MBB; ++b) lo[a][c][b] = mid[a][c][b] = hi[a][c][b] = 0;
+  uint64_t nc[MQ][2], np[MBB];
+#pragma unroll
+  for (int a = 0; a < MQ; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) nc[a][c] = cp[a][c][0];
+#pragma unroll
+  for (int b = 0; b < MBB; ++b) np[b] = pp[b][0];
+  int fold = 0;
+  for (int j = 0; j < ell; ++j) {
+    const int jn = min(j + 1, ell - 1);
+    uint32_t a0[MQ][2], a1[MQ][2];
+#pragma unroll
+    for (int a = 0; a < MQ; ++a)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const uint64_t v = nc[a][c];
+        nc[a][c] = cp[a][c][jn * cjs];
+        a0[a][c] = (uint32_t)(v & M27);
+        a1[a][c] = (uint32_t)(v >> 27);
+      }
+    uint64_t pv[MBB];
+#pragma unroll
+    for (int b = 0; b < MBB; ++b) {
+      pv[b] = np[b];
+      np[b] = pp[b][jn * pjs];
+    }
+#pragma unroll
+    for (int b = 0; b < MBB; ++b) {
+      const uint32_t blo = (uint32_t)pv[b], bhi = (uint32_t)(pv[b] >> 32);
+#pragma unroll
+      for (int a = 0; a < MQ; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          lo[a][c][b] += (uint64_t)a0[a][c] * blo;
+          mid[a][c][b] += (uint64_t)a0[a][c] * bhi;
+          mid[a][c][b] += (uint64_t)a1[a][c] * blo;
+          hi[a][c][b] += (uint64_t)a1[a][c] * bhi;
+        }
+    }
+    if (++fold == FOLD) {
+      fold = 0;
+#pragma unroll
+      for (int a = 0; a < MQ; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+          for (int b = 0; b < MBB; ++b) {
+            lo[a][c][b] = fold3(lo[a][c][b], mid[a][c][b], hi[a][c][b], pr);
+            mid[a][c][b] = hi[a][c][b] = 0;
+          }
+    }
+  }
+  const int k = kbase + lane;
+#pragma unroll
+  for (int a = 0; a < MQ; ++a)
+#pragma unroll
+    for (int b = 0; b < MBB; ++b)
+      if (a < nql && b < nbl)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+          S[((size_t)(b0 + b) * nq + q0 + a) * 2 * L * N + ((size_t)c * L + l) * N + k] =
+              fold3(lo[a][c][b], mid[a][c][b], hi[a][c][b], pr);
 }
 
 __global__ void __launch_bounds__(TPB) k_pointwise(Tables T, const uint64_t* __restrict__ a,
@@ -600,20 +713,31 @@ void relin_digits(const Tables& T, const Consts& hc, const uint64_t* c3, uint64_
   PEPSI_L_LAUNCH(k_relin_digits, hc.L, grid_for(hc.n, rows), dim3(TPB), s, T, c3, D);
 }
 void relin_inner(const Tables& T, const Consts& hc, const uint64_t* dhat, const uint64_t* Dhat,
-                 const uint64_t* rlk, uint64_t* out, int rows, hipStream_t s) {
+                 const uint64_t* rlk, long rlk_stride, int jobs_per_pair, int nq, uint64_t* out, int rows,
+                 hipStream_t s) {
   if (rows <= 0) return;
-  PEPSI_L_LAUNCH(k_relin_inner, hc.L, grid_for(hc.n, hc.L, rows), dim3(TPB), s, T, dhat, Dhat, rlk, out);
+  PEPSI_L_LAUNCH(k_relin_inner, hc.L, grid_for(hc.n, hc.L, rows), dim3(TPB), s, T, dhat, Dhat, rlk,
+                 rlk_stride, jobs_per_pair, nq, out);
 }
-void accumulate(const Tables& T, const Consts& hc, const uint64_t* x, long xstride, int rows,
+void accumulate(const Tables& T, const Consts& hc, const uint64_t* x, long xstride, int nb, int nq,
                 uint64_t* acc, hipStream_t s) {
-  if (rows <= 0) return;
-  hipLaunchKernelGGL(k_accumulate, grid_for(hc.n, 2 * hc.L), dim3(TPB), 0, s, T, x, xstride, rows, acc);
+  if (nb <= 0 || nq <= 0) return;
+  hipLaunchKernelGGL(k_accumulate, grid_for(hc.n, 2 * hc.L, nq), dim3(TPB), 0, s, T, x, xstride, nb, nq, acc);
 }
 void select_sum(const Tables& T, const Consts& hc, const uint64_t* Cn, const uint64_t* P, int ell,
                 int nb, uint64_t* S, long sstride, hipStream_t s) {
   if (nb <= 0) return;
   hipLaunchKernelGGL(k_select_sum, grid_for(hc.n, hc.L, (nb + IB - 1) / IB), dim3(TPB), 0, s, T, Cn,
                      P, ell, nb, S, sstride);
+}
+void select_sum_multi(const Tables& T, const Consts& hc, const uint64_t* Cq, long cq_stride, int nq,
+                      const uint64_t* P, int ell, int nb, uint64_t* S, hipStream_t s) {
+  if (nb <= 0 || nq <= 0) return;
+  const int regions = (hc.n / 64) * hc.L * ((nb + MB - 1) / MB);
+  const int qgroups = (nq + MQ - 1) / MQ;
+  const int blocks = ((regions + 7) / 8) * 8 * qgroups;
+  hipLaunchKernelGGL(k_select_sum_multi, dim3(blocks), dim3(MTPB), 0, s, T, Cq, cq_stride, nq, P, ell, nb,
+                     S, regions, qgroups);
 }
 void pointwise_mul(const Tables& T, const Consts& hc, const uint64_t* a, const uint64_t* b,
                    uint64_t* out, int rows, int nprimes, bool bcast, hipStream_t s) {

@@ -167,8 +167,8 @@ typedef struct pepsi_server pepsi_server;
 typedef struct {
   uint32_t mu;             /* batches of the table                                     */
   uint32_t max_load;       /* fullest bin; batches at or above it hold only dummies    */
-  uint32_t cached;         /* 1 if the plaintext cache is resident                     */
-  uint32_t reserved;
+  uint32_t cached;         /* 1 if a plaintext cache is resident                       */
+  uint32_t cached_batches; /* server batches whose plaintexts are cached (the first ones) */
   uint64_t device_bytes;   /* device memory held by the handle                         */
 } pepsi_server_info;
 
@@ -176,9 +176,11 @@ typedef struct {
  * each distinct bin among H_1..H_k (input order inside a bin), bins are padded to
  * mu with dummies, every entry is constant-weight encoded, and the codeword
  * positions uint16 [mu][N][h] (0xFFFF for dummies) are copied to device memory
- * owned by the handle.  With PEPSI_SERVER_CACHE_PLAINTEXTS every server plaintext
- * pt_s[i'][j] is also batch-encoded and transformed into NTT form once, here
- * (mu * ell * L * N * 8 bytes of HBM); otherwise each evaluation regenerates them.
+ * owned by the handle.  With PEPSI_SERVER_CACHE_PLAINTEXTS the server plaintexts
+ * pt_s[i'][j] are also batch-encoded and transformed into NTT form once, here
+ * (ell * L * N * 8 bytes of HBM per server batch), for the first batches that fit
+ * beside a 48 GiB working reserve (whole 16-batch tiles unless all fit; batches
+ * holding only dummies are never stored); every evaluation regenerates the rest.
  * Synchronises the stream.  Errors: PEPSI_E_RANGE, PEPSI_E_BIN_OVERFLOW,
  * PEPSI_E_NOMEM. */
 int pepsi_server_create(const pepsi_params* params, const uint32_t* items, uint64_t n,
@@ -215,6 +217,40 @@ int pepsi_server_eval_range(pepsi_server* server, const uint64_t* d_cts, const u
 int pepsi_server_eval_batch(pepsi_server* server, uint32_t nq, const uint64_t* const* d_cts,
                             const uint64_t* const* d_rlk, const uint32_t* const* d_masks,
                             uint64_t* const* d_out, void* stream);
+
+/* ------------------------------------------------------------------ */
+/* Serving: continuous batching over one prepared server               */
+/* ------------------------------------------------------------------ */
+/* A serving handle runs a worker thread with its own HIP stream.  The server
+ * batches are walked as a circular sequence of 16-batch tiles; every step runs one
+ * tile for all admitted queries, so each streamed plaintext tile serves all of
+ * them.  A submitted request waits in a queue until a query slot is free, is
+ * admitted at the next step boundary, and completes after one full cycle of tiles
+ * (its result is bit-identical to pepsi_server_eval on the same inputs).  The
+ * number of slots is max_active, capped by hbm_budget / (device bytes per slot)
+ * when hbm_budget is non-zero; the handle's workspace is allocated at creation.
+ * Device buffers of a request must be ready (their producing work synchronised)
+ * at submission and stay valid until it completes.  submit / poll / wait /
+ * get_info are thread-safe.  Times are seconds on pepsi_clock(), a monotonic
+ * clock. */
+typedef struct pepsi_serve pepsi_serve;
+typedef struct {
+  double submit_s, admit_s, done_s;
+  uint32_t slot, done;
+} pepsi_req_stats;
+typedef struct {
+  uint32_t slots, tiles, active, queued;
+  uint64_t steps, completed;
+} pepsi_serve_info;
+double pepsi_clock(void);
+int pepsi_serve_create(pepsi_server* server, uint32_t max_active, uint64_t hbm_budget, pepsi_serve** out);
+int pepsi_serve_submit(pepsi_serve* serve, const uint64_t* d_cts, const uint64_t* d_rlk,
+                       const uint32_t* d_mask, uint64_t* d_out, uint64_t* req_id);
+int pepsi_serve_poll(pepsi_serve* serve, uint64_t req_id, int* done, pepsi_req_stats* stats);
+int pepsi_serve_wait(pepsi_serve* serve, uint64_t req_id, pepsi_req_stats* stats);
+int pepsi_serve_get_info(pepsi_serve* serve, pepsi_serve_info* out);
+/* Waits for every submitted request, then stops the worker and frees the handle. */
+void pepsi_serve_destroy(pepsi_serve* serve);
 
 /* Event timing of a server's evaluations, for measurement.  While enabled,
  * every select-and-sum launch (the kernel that streams the server plaintexts)

@@ -45,7 +45,17 @@ class ParamsInfo(C.Structure):
 
 class ServerInfo(C.Structure):
     _fields_ = [("mu", C.c_uint32), ("max_load", C.c_uint32), ("cached", C.c_uint32),
-                ("reserved", C.c_uint32), ("device_bytes", C.c_uint64)]
+                ("cached_batches", C.c_uint32), ("device_bytes", C.c_uint64)]
+
+
+class ReqStats(C.Structure):
+    _fields_ = [("submit_s", C.c_double), ("admit_s", C.c_double), ("done_s", C.c_double),
+                ("slot", C.c_uint32), ("done", C.c_uint32)]
+
+
+class ServeInfo(C.Structure):
+    _fields_ = [("slots", C.c_uint32), ("tiles", C.c_uint32), ("active", C.c_uint32), ("queued", C.c_uint32),
+                ("steps", C.c_uint64), ("completed", C.c_uint64)]
 
 
 class Timing(C.Structure):
@@ -74,6 +84,13 @@ _SIGS = {
     "pepsi_server_timing": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(Timing)]),
     "pepsi_server_eval_batch": (C.c_int, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p,
                                           C.c_void_p, C.c_void_p]),
+    "pepsi_clock": (C.c_double, []),
+    "pepsi_serve_create": (C.c_int, [C.c_void_p, C.c_uint32, C.c_uint64, C.POINTER(C.c_void_p)]),
+    "pepsi_serve_submit": (C.c_int, [C.c_void_p] * 5 + [C.POINTER(C.c_uint64)]),
+    "pepsi_serve_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_int), C.POINTER(ReqStats)]),
+    "pepsi_serve_wait": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(ReqStats)]),
+    "pepsi_serve_get_info": (C.c_int, [C.c_void_p, C.POINTER(ServeInfo)]),
+    "pepsi_serve_destroy": (None, [C.c_void_p]),
     "pepsi_server_eval_range": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32,
                                           C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pepsi_ntt": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int,
@@ -236,6 +253,7 @@ class Server:
         info = ServerInfo()
         _check(lib().pepsi_server_get_info(self._h, C.byref(info)))
         self.max_load, self.cached, self.device_bytes = info.max_load, bool(info.cached), info.device_bytes
+        self.cached_batches = info.cached_batches
 
     def close(self):
         if getattr(self, "_h", None):
@@ -275,3 +293,53 @@ class Server:
     def eval_range(self, cts, rlk, begin: int, end: int, finalize: bool, mask, out, stream=None):
         _check(lib().pepsi_server_eval_range(self._h, _dev(cts), _dev(rlk), begin, end,
                                              1 if finalize else 0, _dev(mask), _dev(out), _stream(stream)))
+
+
+def clock() -> float:
+    return float(lib().pepsi_clock())
+
+
+class Serve:
+    """Continuous-batching serving loop over a prepared server (pepsi_serve_*)."""
+
+    def __init__(self, server: Server, max_active: int = 0, hbm_budget: int = 0):
+        h_ = C.c_void_p()
+        _check(lib().pepsi_serve_create(server._h, max_active, hbm_budget, C.byref(h_)))
+        self._h = h_
+        self.server = server
+        self._keep = {}
+
+    def submit(self, cts, rlk, mask, out) -> int:
+        rid = C.c_uint64()
+        _check(lib().pepsi_serve_submit(self._h, _dev(cts), _dev(rlk), _dev(mask), _dev(out), C.byref(rid)))
+        self._keep[rid.value] = (cts, rlk, mask, out)       # buffers must outlive the request
+        return int(rid.value)
+
+    def poll(self, rid: int):
+        done = C.c_int()
+        st = ReqStats()
+        _check(lib().pepsi_serve_poll(self._h, rid, C.byref(done), C.byref(st)))
+        return bool(done.value), st
+
+    def wait(self, rid: int) -> ReqStats:
+        st = ReqStats()
+        _check(lib().pepsi_serve_wait(self._h, rid, C.byref(st)))
+        self._keep.pop(rid, None)
+        return st
+
+    def info(self) -> ServeInfo:
+        i = ServeInfo()
+        _check(lib().pepsi_serve_get_info(self._h, C.byref(i)))
+        return i
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pepsi_serve_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

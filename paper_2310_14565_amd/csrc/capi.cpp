@@ -7,7 +7,13 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
 #include <string>
+#include <thread>
+#include <unordered_map>
 #include <unordered_set>
 #include <vector>
 
@@ -400,14 +406,13 @@ struct Operand { const uint64_t* q; const uint64_t* b; const uint64_t* alpha; };
 // tile of nb batches uses the first nb * nq pairs (and the first jobs of every tree level).
 struct Engine {
   pepsi_params* P = nullptr;
-  int TBq = 0, Qmax = 0, levels = 0, jobs_nq = -1;
+  int TBq = 0, Qmax = 0, levels = 0;
   std::vector<int> jobs_at;            // tensor jobs per pair at each tree level
   DevBuf chat, rlkhat, acc;            // per query: request and key in NTT form, running sum
   DevBuf sq, scoef, sb, alpha, e;      // per pair
   DevBuf d, c3, c3h, D, rcoef;         // per tensor job
   std::vector<DevBuf> rq, rb;          // per tree level outputs
   DevBuf jobs;                         // device TensorJob arrays, all levels
-  std::vector<size_t> job_off;
   DevBuf gen_poly, gen_p;              // on-the-fly plaintext generation
   int GB = 0;
   EventTimer* timer = nullptr;
@@ -430,7 +435,6 @@ struct Engine {
     const size_t n = H.n, L = H.L, K = H.K, Pn = L + K;
     TBq = tbq;
     Qmax = qmax;
-    jobs_nq = -1;
     const size_t PC = (size_t)TBq * Qmax;          // pair capacity
     int rc;
     if ((rc = chat.ensure(Qmax * cstride() * 8))) return rc;
@@ -464,56 +468,58 @@ struct Engine {
       if ((rc = gen_poly.ensure((size_t)GB * H.ell * n * 4))) return rc;
       if ((rc = gen_p.ensure((size_t)GB * H.ell * L * n * 8))) return rc;
     }
-    return 0;
+    return build_all_jobs();
   }
 
-  // Tensor jobs of every level for a full tile of nq queries (job = pair * pairs + u).
-  int build_jobs(int nq) {
-    if (levels == 0 || nq == jobs_nq) return 0;
+  // Tensor jobs of every level for a full tile of na active queries (job = pair * pairs + u),
+  // for every na in [1, Qmax]; job_off[na][lv] locates them in one device array.
+  std::vector<std::vector<size_t>> job_off_na;
+  int build_all_jobs() {
+    if (levels == 0) return 0;
     const HostParams& H = P->H;
     const size_t n = H.n, L = H.L, K = H.K, Pn = L + K;
-    const int npairs = TBq * nq;
     std::vector<TensorJob> all;
-    job_off.clear();
-    std::vector<std::vector<Operand>> ops(npairs);
-    for (int p = 0; p < npairs; ++p)
-      for (int r = 0; r < H.h; ++r)
-        ops[p].push_back(Operand{sq.as<uint64_t>((size_t)p * 2 * L * n), sb.as<uint64_t>((size_t)p * 2 * K * n),
-                                 alpha.as<uint64_t>(((size_t)p * H.h + r) * Pn)});
-    for (int lv = 0; lv < levels; ++lv) {
-      const int pairs = jobs_at[lv];
-      job_off.push_back(all.size());
+    job_off_na.assign(Qmax + 1, std::vector<size_t>(levels, 0));
+    for (int na = 1; na <= Qmax; ++na) {
+      const int npairs = TBq * na;
+      std::vector<std::vector<Operand>> ops(npairs);
       for (int p = 0; p < npairs; ++p)
-        for (int u = 0; u < pairs; ++u) {
-          const Operand& x = ops[p][2 * u];
-          const Operand& y = ops[p][2 * u + 1];
-          const size_t j = (size_t)p * pairs + u;
-          all.push_back(TensorJob{x.q, x.b, y.q, y.b, x.alpha, y.alpha, d.as<uint64_t>(j * 3 * Pn * n)});
-        }
-      if (lv + 1 < levels) {
-        for (int p = 0; p < npairs; ++p) {
-          std::vector<Operand> next;
+        for (int r = 0; r < H.h; ++r)
+          ops[p].push_back(Operand{sq.as<uint64_t>((size_t)p * 2 * L * n), sb.as<uint64_t>((size_t)p * 2 * K * n),
+                                   alpha.as<uint64_t>(((size_t)p * H.h + r) * Pn)});
+      for (int lv = 0; lv < levels; ++lv) {
+        const int pairs = jobs_at[lv];
+        job_off_na[na][lv] = all.size();
+        for (int p = 0; p < npairs; ++p)
           for (int u = 0; u < pairs; ++u) {
+            const Operand& x = ops[p][2 * u];
+            const Operand& y = ops[p][2 * u + 1];
             const size_t j = (size_t)p * pairs + u;
-            next.push_back(Operand{rq[lv].as<uint64_t>(j * 2 * L * n), rb[lv].as<uint64_t>(j * 2 * K * n), nullptr});
+            all.push_back(TensorJob{x.q, x.b, y.q, y.b, x.alpha, y.alpha, d.as<uint64_t>(j * 3 * Pn * n)});
           }
-          if (ops[p].size() % 2) next.push_back(ops[p].back());
-          ops[p] = next;
+        if (lv + 1 < levels) {
+          for (int p = 0; p < npairs; ++p) {
+            std::vector<Operand> next;
+            for (int u = 0; u < pairs; ++u) {
+              const size_t j = (size_t)p * pairs + u;
+              next.push_back(Operand{rq[lv].as<uint64_t>(j * 2 * L * n), rb[lv].as<uint64_t>(j * 2 * K * n), nullptr});
+            }
+            if (ops[p].size() % 2) next.push_back(ops[p].back());
+            ops[p] = next;
+          }
         }
       }
     }
-    HIPCHK(hipDeviceSynchronize());                  // the previous job arrays may still be in use
     int rc = jobs.ensure(all.size() * sizeof(TensorJob));
     if (rc) return rc;
     HIPCHK(hipMemcpy(jobs.p, all.data(), all.size() * sizeof(TensorJob), hipMemcpyHostToDevice));
-    jobs_nq = nq;
     return 0;
   }
 
   // Products + relinearisation of njobs jobs (results NTT form into out [njobs][2][L][N]);
   // with ext_out also the Q -> B extension of the results, NTT form.
-  void multiply_relin(const TensorJob* dev_jobs, int njobs, int jobs_per_pair, int nq, uint64_t* out,
-                      uint64_t* ext_out, hipStream_t s) {
+  void multiply_relin(const TensorJob* dev_jobs, int njobs, int jobs_per_pair, int nq, const int* qslot,
+                      uint64_t* out, uint64_t* ext_out, hipStream_t s, int key_slot = 0) {
     const HostParams& H = P->H;
     const int L = H.L, K = H.K, Pn = L + K;
     uint64_t* dd = d.as<uint64_t>();
@@ -523,8 +529,9 @@ struct Engine {
     relin_digits(P->T, H.consts, c3.as<uint64_t>(), D.as<uint64_t>(), njobs, s);
     ntt_forward(P->T, H.logn, D.p, LOAD_U64, D.p, STORE_U64, njobs * L * L, L, 0, s);
     ntt_forward(P->T, H.logn, c3.p, LOAD_U64, c3h.p, STORE_U64, njobs * 3 * L, L, 0, s);
-    relin_inner(P->T, H.consts, c3h.as<uint64_t>(), D.as<uint64_t>(), rlkhat.as<uint64_t>(), (long)rstride(),
-                jobs_per_pair, nq, out, njobs, s);
+    relin_inner(P->T, H.consts, c3h.as<uint64_t>(), D.as<uint64_t>(),
+                rlkhat.as<uint64_t>((size_t)key_slot * rstride()), (long)rstride(), qslot, jobs_per_pair, nq, out,
+                njobs, s);
     if (ext_out) {
       ntt_inverse(P->T, H.logn, out, rcoef.as<uint64_t>(), njobs * 2 * L, L, 0, s);
       ext_q_to_b(P->T, H.consts, rcoef.as<uint64_t>(), ext_out, (long)K * H.n, njobs * 2,
@@ -533,28 +540,27 @@ struct Engine {
     }
   }
 
-  // Requests and keys of nq queries to NTT form; running sums to zero.
-  void start_queries(int nq, const uint64_t* const* cts, const uint64_t* const* rlk, hipStream_t s) {
+  // A query enters slot `slot`: request and key to NTT form, running sum to zero.
+  void admit(int slot, const uint64_t* cts, const uint64_t* rlk, hipStream_t s) {
     const HostParams& H = P->H;
     const int L = H.L;
-    for (int q = 0; q < nq; ++q) {
-      ntt_forward(P->T, H.logn, cts[q], LOAD_U64, chat.as<uint64_t>(q * cstride()), STORE_U64, H.ell * 2 * L,
-                  L, 0, s);
-      ntt_forward(P->T, H.logn, rlk[q], LOAD_U64, rlkhat.as<uint64_t>(q * rstride()), STORE_U64, L * 2 * L, L,
-                  0, s);
-    }
-    (void)hipMemsetAsync(acc.p, 0, (size_t)nq * ctw() * 8, s);
+    ntt_forward(P->T, H.logn, cts, LOAD_U64, chat.as<uint64_t>(slot * cstride()), STORE_U64, H.ell * 2 * L, L,
+                0, s);
+    ntt_forward(P->T, H.logn, rlk, LOAD_U64, rlkhat.as<uint64_t>(slot * rstride()), STORE_U64, L * 2 * L, L, 0, s);
+    (void)hipMemsetAsync(acc.as<uint64_t>(slot * ctw()), 0, ctw() * 8, s);
   }
 
-  void timed_select_sum(const uint64_t* phat, int nb, int nq, uint64_t* Sx, hipStream_t s) {
+  void timed_select_sum(const uint64_t* phat, int nb, int nq, const int* qslot, int single_slot, uint64_t* Sx,
+                        hipStream_t s) {
     const HostParams& H = P->H;
     const size_t n = H.n, L = H.L;
     hipEvent_t a = nullptr, b = nullptr;
     if (timer && timer->on) { a = timer->get(); b = timer->get(); (void)hipEventRecord(a, s); }
     if (nq == 1)
-      select_sum(P->T, H.consts, chat.as<uint64_t>(), phat, H.ell, nb, Sx, (long)(2 * L * n), s);
+      select_sum(P->T, H.consts, chat.as<uint64_t>((size_t)single_slot * cstride()), phat, H.ell, nb, Sx,
+                 (long)(2 * L * n), s);
     else
-      select_sum_multi(P->T, H.consts, chat.as<uint64_t>(), (long)cstride(), nq, phat, H.ell, nb, Sx, s);
+      select_sum_multi(P->T, H.consts, chat.as<uint64_t>(), (long)cstride(), qslot, nq, phat, H.ell, nb, Sx, s);
     if (a) {
       (void)hipEventRecord(b, s);
       const uint64_t bytes =
@@ -563,25 +569,29 @@ struct Engine {
     }
   }
 
-  // One tile: batches [b0, b0 + nb) of nq queries; plaintexts from the cache (phat) or generated.
-  void run_tile(const uint16_t* cw, int b0, int nb, int nq, const uint64_t* phat, hipStream_t s) {
+  // One tile: batches [b0, b0 + nb) of nq active queries (slots qslot[0..nq), or single_slot when
+  // nq == 1); plaintexts from the cache (phat) or generated.
+  void run_tile(const uint16_t* cw, int b0, int nb, int nq, const int* qslot, int single_slot,
+                const uint64_t* phat, hipStream_t s) {
     const HostParams& H = P->H;
     const size_t n = H.n, L = H.L, K = H.K;
     uint64_t* Sq = sq.as<uint64_t>();
     const int npairs = nb * nq;
     if (phat) {
-      timed_select_sum(phat, nb, nq, Sq, s);
+      timed_select_sum(phat, nb, nq, qslot, single_slot, Sq, s);
     } else {
       for (int g0 = 0; g0 < nb; g0 += GB) {
         const int g = std::min(GB, nb - g0);
         encode_server_planes(P->T, H.logn, cw, H.h, H.ell, b0 + g0, g, gen_poly.as<uint32_t>(), s);
         ntt_forward(P->T, H.logn, gen_poly.p, LOAD_LIFT_T, gen_p.p, STORE_SPLIT27, g * H.ell * (int)L,
                     (int)L, 0, s);
-        timed_select_sum(gen_p.as<uint64_t>(), g, nq, Sq + (size_t)g0 * nq * 2 * L * n, s);
+        timed_select_sum(gen_p.as<uint64_t>(), g, nq, qslot, single_slot, Sq + (size_t)g0 * nq * 2 * L * n, s);
       }
     }
+    const int* acc_slot = nq == 1 ? nullptr : qslot;
+    uint64_t* acc_base = nq == 1 ? acc.as<uint64_t>((size_t)single_slot * ctw()) : acc.as<uint64_t>();
     if (levels == 0) {                                           // h = 1: e = S
-      accumulate(P->T, H.consts, Sq, (long)(2 * L * n), nb, nq, acc.as<uint64_t>(), s);
+      accumulate(P->T, H.consts, Sq, (long)(2 * L * n), nb, nq, acc_slot, acc_base, s);
       return;
     }
     ntt_inverse(P->T, H.logn, Sq, scoef.as<uint64_t>(), npairs * 2 * (int)L, (int)L, 0, s);
@@ -590,14 +600,16 @@ struct Engine {
     ntt_forward(P->T, H.logn, sb.p, LOAD_U64, sb.p, STORE_U64, npairs * 2 * (int)K, (int)K, (int)L, s);
     factor_constants(P->T, H.consts, scoef.as<uint64_t>(), npairs, H.h, alpha.as<uint64_t>(),
                      P->fallback.as<uint32_t>(), s);
+    // the key of a single active query: shift the key base to its slot
+    const int* rslot = nq == 1 ? nullptr : qslot;
     for (int lv = 0; lv < levels; ++lv) {
       const int njobs = npairs * jobs_at[lv];
-      const TensorJob* jl = jobs.as<TensorJob>() + job_off[lv];
+      const TensorJob* jl = jobs.as<TensorJob>() + job_off_na[nq][lv];
       const bool last = lv + 1 == levels;
-      multiply_relin(jl, njobs, jobs_at[lv], nq, last ? e.as<uint64_t>() : rq[lv].as<uint64_t>(),
-                     last ? nullptr : rb[lv].as<uint64_t>(), s);
+      multiply_relin(jl, njobs, jobs_at[lv], nq, rslot, last ? e.as<uint64_t>() : rq[lv].as<uint64_t>(),
+                     last ? nullptr : rb[lv].as<uint64_t>(), s, nq == 1 ? single_slot : 0);
     }
-    accumulate(P->T, H.consts, e.as<uint64_t>(), (long)(2 * L * n), nb, nq, acc.as<uint64_t>(), s);
+    accumulate(P->T, H.consts, e.as<uint64_t>(), (long)(2 * L * n), nb, nq, acc_slot, acc_base, s);
   }
 
   // out = coefficient form of query q's sum, optionally times (h!)^-1 plus Delta [encode(mask)]_t
@@ -622,16 +634,19 @@ struct Engine {
     }
   }
 
-  // The whole computation for nq queries over batches [begin, stop).
-  int run(const uint16_t* cw, const uint64_t* cache, uint32_t begin, uint32_t stop, int nq,
+  // Plaintexts of tile [b0, b0 + nb): the cache when it covers the tile, else generated.
+  static const uint64_t* cached_tile(const uint64_t* cache, uint32_t cached, uint32_t b0, int nb, size_t per) {
+    return (cache && b0 + (uint32_t)nb <= cached) ? cache + per * b0 : nullptr;
+  }
+
+  // The whole computation for nq queries in slots 0..nq-1 over batches [begin, stop).
+  int run(const uint16_t* cw, const uint64_t* cache, uint32_t cached, uint32_t begin, uint32_t stop, int nq,
           const uint64_t* const* cts, const uint64_t* const* rlk, hipStream_t s) {
-    int rc = build_jobs(nq);
-    if (rc) return rc;
-    start_queries(nq, cts, rlk, s);
+    for (int q = 0; q < nq; ++q) admit(q, cts[q], rlk[q], s);
     const size_t per = (size_t)P->H.ell * P->H.L * P->H.n;
     for (uint32_t b0 = begin; b0 < stop; b0 += TBq) {
       const int nb = (int)std::min<uint32_t>(TBq, stop - b0);
-      run_tile(cw, (int)b0, nb, nq, cache ? cache + per * b0 : nullptr, s);
+      run_tile(cw, (int)b0, nb, nq, nullptr, 0, cached_tile(cache, cached, b0, nb, per), s);
     }
     return 0;
   }
@@ -645,8 +660,9 @@ struct pepsi_server {
   EventTimer timer;
   uint32_t max_load = 0;
   DevBuf cw;            // [mu][N][h] uint16
-  DevBuf cache;         // [max_load][ell][L][N] split-27 NTT form
+  DevBuf cache;         // [cached][ell][L][N] split-27 NTT form
   bool cached = false;
+  uint32_t cached_batches = 0;
   Engine eng;            // one query at a time (plain path)
   bool ready = false;
   Engine beng;           // many queries per launch (batched path)
@@ -686,22 +702,31 @@ extern "C" int pepsi_server_create(const pepsi_params* Pc, const uint32_t* items
     return fail(PEPSI_E_DEVICE, "codeword upload failed");
   }
   if ((flags & PEPSI_SERVER_CACHE_PLAINTEXTS) && max_load > 0) {
+    // as many batches as fit beside a working reserve, in whole 16-batch tiles unless all fit
     const size_t per = (size_t)H.ell * H.L * H.n;
-    if ((rc = sv->cache.ensure(per * max_load * 8))) { delete sv; return rc; }
-    // generation buffers: 8 batches at a time
-    DevBuf poly;
-    const int G = 8;
-    if ((rc = poly.ensure((size_t)G * H.ell * H.n * 4))) { delete sv; return rc; }
-    hipStream_t s = S(stream);
-    for (uint32_t b0 = 0; b0 < max_load; b0 += G) {
-      const int g = (int)std::min<uint32_t>(G, max_load - b0);
-      encode_server_planes(P->T, H.logn, sv->cw.as<uint16_t>(), H.h, H.ell, (int)b0, g, poly.as<uint32_t>(), s);
-      ntt_forward(P->T, H.logn, poly.p, LOAD_LIFT_T, sv->cache.as<uint64_t>(per * b0), STORE_SPLIT27,
-                  g * H.ell * H.L, H.L, 0, s);
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) { delete sv; return fail(PEPSI_E_DEVICE, "hipMemGetInfo failed"); }
+    const size_t reserve = (size_t)48 << 30;
+    size_t fit = free_b > reserve ? (free_b - reserve) / (per * 8) : 0;
+    uint32_t nc = (uint32_t)std::min<size_t>(fit, max_load);
+    if (nc < max_load) nc -= nc % 16;
+    if (nc > 0) {
+      if ((rc = sv->cache.ensure(per * nc * 8))) { delete sv; return rc; }
+      DevBuf poly;
+      const int G = 8;
+      if ((rc = poly.ensure((size_t)G * H.ell * H.n * 4))) { delete sv; return rc; }
+      hipStream_t s = S(stream);
+      for (uint32_t b0 = 0; b0 < nc; b0 += G) {
+        const int g = (int)std::min<uint32_t>(G, nc - b0);
+        encode_server_planes(P->T, H.logn, sv->cw.as<uint16_t>(), H.h, H.ell, (int)b0, g, poly.as<uint32_t>(), s);
+        ntt_forward(P->T, H.logn, poly.p, LOAD_LIFT_T, sv->cache.as<uint64_t>(per * b0), STORE_SPLIT27,
+                    g * H.ell * H.L, H.L, 0, s);
+      }
+      if (hipStreamSynchronize(s) != hipSuccess) { poly.release(); delete sv; return fail(PEPSI_E_DEVICE, "cache build failed"); }
+      poly.release();
+      sv->cached = true;
+      sv->cached_batches = nc;
     }
-    if (hipStreamSynchronize(s) != hipSuccess) { poly.release(); delete sv; return fail(PEPSI_E_DEVICE, "cache build failed"); }
-    poly.release();
-    sv->cached = true;
   }
   *out = sv;
   return PEPSI_OK;
@@ -713,6 +738,7 @@ extern "C" int pepsi_server_get_info(const pepsi_server* sv, pepsi_server_info* 
   o->mu = sv->P->H.mu;
   o->max_load = sv->max_load;
   o->cached = sv->cached ? 1 : 0;
+  o->cached_batches = sv->cached_batches;
   o->device_bytes = sv->cw.cap + sv->cache.cap;
   return PEPSI_OK;
 }
@@ -741,7 +767,7 @@ extern "C" int pepsi_server_eval_range(pepsi_server* sv, const uint64_t* cts, co
   hipStream_t s = S(stream);
   if (!sv->ready) {
     const int tb = std::min<int>(128, std::max<int>(1, (int)sv->max_load));
-    int rc = sv->eng.setup(sv->P, tb, 1, !sv->cached);
+    int rc = sv->eng.setup(sv->P, tb, 1, sv->cached_batches < sv->max_load);
     if (rc) return rc;
     sv->eng.timer = &sv->timer;
     sv->ready = true;
@@ -753,7 +779,7 @@ extern "C" int pepsi_server_eval_range(pepsi_server* sv, const uint64_t* cts, co
   const uint32_t stop = std::min(end, sv->max_load);
   const uint64_t* c1[1] = {cts};
   const uint64_t* r1[1] = {rlk};
-  int rc = E.run(sv->cw.as<uint16_t>(), sv->cached ? sv->cache.as<uint64_t>() : nullptr, begin,
+  int rc = E.run(sv->cw.as<uint16_t>(), sv->cached ? sv->cache.as<uint64_t>() : nullptr, sv->cached_batches, begin,
                  std::max(begin, stop), 1, c1, r1, s);
   if (rc) return rc;
   E.finish(0, finalize != 0, mask, out, s);
@@ -784,7 +810,7 @@ extern "C" int pepsi_server_eval_batch(pepsi_server* sv, uint32_t nq, const uint
   if ((int)nq > sv->bqmax) {
     // batches per tile: one batch group of the multi-query select-and-sum (16)
     int rc = sv->beng.setup(sv->P, std::min<int>(16, std::max<int>(1, (int)sv->max_load)), (int)nq,
-                            !sv->cached);
+                            sv->cached_batches < sv->max_load);
     if (rc) return rc;
     sv->beng.timer = &sv->timer;
     sv->bqmax = (int)nq;
@@ -793,7 +819,8 @@ extern "C" int pepsi_server_eval_batch(pepsi_server* sv, uint32_t nq, const uint
   hipEvent_t ea = nullptr, eb = nullptr;
   if (sv->timer.on) { ea = sv->timer.get(); eb = sv->timer.get(); (void)hipEventRecord(ea, s); }
   const uint32_t stop = std::min<uint32_t>(H.mu, sv->max_load);
-  int rc = E.run(sv->cw.as<uint16_t>(), sv->cached ? sv->cache.as<uint64_t>() : nullptr, 0, stop, (int)nq,
+  int rc = E.run(sv->cw.as<uint16_t>(), sv->cached ? sv->cache.as<uint64_t>() : nullptr, sv->cached_batches, 0,
+                 stop, (int)nq,
                  cts, rlk, s);
   if (rc) return rc;
   for (uint32_t q = 0; q < nq; ++q) E.finish((int)q, true, masks ? masks[q] : nullptr, out[q], s);
@@ -815,6 +842,240 @@ extern "C" int pepsi_server_timing(pepsi_server* sv, int enable, int reset, peps
   return PEPSI_OK;
 }
 
+
+// ------------------------------------------------------------------ serving
+// Continuous batching.  The worker walks the server batches as a circular sequence of tiles of
+// TBq batches; every step runs one tile for all active queries.  A request is admitted into a
+// free slot at a step boundary and is finished after it has seen every tile once (it joins at
+// whatever tile the cursor is on; sums mod Q do not depend on the order).  Requests beyond the
+// slots wait in the queue.
+namespace {
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+}  // namespace
+
+extern "C" double pepsi_clock(void) { return now_s(); }
+
+struct pepsi_serve {
+  struct Req {
+    uint64_t id = 0;
+    const uint64_t* cts = nullptr;
+    const uint64_t* rlk = nullptr;
+    const uint32_t* mask = nullptr;
+    uint64_t* out = nullptr;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    int slot = -1, tiles = 0, done = 0;
+  };
+  pepsi_server* sv = nullptr;
+  Engine eng;
+  hipStream_t stream = nullptr;
+  int slots = 0, T = 0, cursor = 0;
+  uint32_t stop_b = 0;
+  std::thread worker;
+  std::mutex mu;
+  std::condition_variable cv, cv_done;
+  bool stop = false;
+  int err = 0;
+  std::string err_msg;
+  std::deque<Req*> queue;
+  std::unordered_map<uint64_t, Req*> reqs;
+  std::vector<Req*> active;
+  uint64_t next_id = 1, steps = 0, completed = 0;
+  int* qslot_host = nullptr;
+  DevBuf qslot_dev;
+
+  void fail_all(const char* what) {
+    std::lock_guard<std::mutex> lk(mu);
+    err = PEPSI_E_DEVICE;
+    err_msg = what;
+    cv_done.notify_all();
+  }
+
+  void loop() {
+    (void)hipSetDevice(sv->P->device);
+    const size_t per = (size_t)sv->P->H.ell * sv->P->H.L * sv->P->H.n;
+    for (;;) {
+      std::vector<Req*> admitted;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv.wait(lk, [&] {
+          if (stop) return true;
+          if (!queue.empty()) return true;
+          for (Req* r : active) if (r) return true;
+          return false;
+        });
+        bool any = false;
+        for (Req* r : active) any |= r != nullptr;
+        if (stop && queue.empty() && !any) break;
+        for (int s = 0; s < slots && !queue.empty(); ++s) {
+          if (active[s]) continue;
+          Req* r = queue.front();
+          queue.pop_front();
+          r->slot = s;
+          r->t_admit = now_s();
+          active[s] = r;
+          admitted.push_back(r);
+        }
+      }
+      for (Req* r : admitted) eng.admit(r->slot, r->cts, r->rlk, stream);
+      std::vector<int> live;
+      for (int s = 0; s < slots; ++s) if (active[s]) live.push_back(s);
+      std::vector<Req*> finished;
+      const int na = (int)live.size();
+      if (T > 0 && na > 0) {
+        for (int i = 0; i < na; ++i) qslot_host[i] = live[i];
+        if (hipMemcpyAsync(qslot_dev.p, qslot_host, sizeof(int) * na, hipMemcpyHostToDevice, stream) != hipSuccess) {
+          fail_all("slot upload failed");
+          return;
+        }
+        const uint32_t b0 = (uint32_t)cursor * eng.TBq;
+        const int nb = (int)std::min<uint32_t>(eng.TBq, stop_b - b0);
+        eng.run_tile(sv->cw.as<uint16_t>(), (int)b0, nb, na, qslot_dev.as<int>(), live[0],
+                     Engine::cached_tile(sv->cached ? sv->cache.as<uint64_t>() : nullptr, sv->cached_batches, b0,
+                                         nb, per),
+                     stream);
+        cursor = (cursor + 1) % T;
+        ++steps;
+      }
+      for (int s : live) {
+        Req* r = active[s];
+        if (++r->tiles >= T) {
+          eng.finish(s, true, r->mask, r->out, stream);
+          finished.push_back(r);
+        }
+      }
+      if (hipStreamSynchronize(stream) != hipSuccess) {
+        fail_all("device error in a serving step");
+        return;
+      }
+      if (!finished.empty()) {
+        std::lock_guard<std::mutex> lk(mu);
+        const double t = now_s();
+        for (Req* r : finished) {
+          r->t_done = t;
+          r->done = 1;
+          active[r->slot] = nullptr;
+          ++completed;
+        }
+        cv_done.notify_all();
+      }
+    }
+  }
+};
+
+extern "C" int pepsi_serve_create(pepsi_server* sv, uint32_t max_active, uint64_t hbm_budget, pepsi_serve** out) {
+  if (!sv || !out) return fail(PEPSI_E_ARG, "null argument");
+  *out = nullptr;
+  const HostParams& H = sv->P->H;
+  const int tbq = std::min<int>(16, std::max<int>(1, (int)sv->max_load));
+  // device memory per slot: request + key + sum in NTT form, and tbq pairs of tile buffers
+  const size_t n = H.n, L = H.L, K = H.K, Pn = L + K;
+  const size_t jobs0 = (size_t)(H.h / 2 > 0 ? H.h / 2 : 1);
+  const size_t per_pair = 8 * n * (2 * L * 3 + 2 * K + jobs0 * (3 * Pn + 6 * L + L * L + 2 * L + 2 * L + 2 * K));
+  const size_t per_slot = 8 * ((size_t)H.ell * 2 * L * n + L * 2 * L * n + 2 * L * n) + tbq * per_pair;
+  uint32_t slots = max_active ? max_active : PEPSI_MAX_BATCH;
+  if (hbm_budget) slots = (uint32_t)std::min<uint64_t>(slots, hbm_budget / per_slot);
+  slots = std::min<uint32_t>(slots, PEPSI_MAX_BATCH);
+  if (slots == 0) return fail(PEPSI_E_NOMEM, "HBM budget below one query slot (%zu bytes)", per_slot);
+  pepsi_serve* sr = new pepsi_serve();
+  sr->sv = sv;
+  sr->slots = (int)slots;
+  sr->stop_b = std::min<uint32_t>(H.mu, sv->max_load);
+  sr->T = (int)((sr->stop_b + tbq - 1) / tbq);
+  int rc = sr->eng.setup(sv->P, tbq, (int)slots, sv->cached_batches < sv->max_load);
+  if (!rc) rc = sr->qslot_dev.ensure(sizeof(int) * slots);
+  if (!rc && hipHostMalloc((void**)&sr->qslot_host, sizeof(int) * slots, hipHostMallocDefault) != hipSuccess)
+    rc = fail(PEPSI_E_NOMEM, "pinned slot buffer");
+  if (!rc && hipStreamCreateWithFlags(&sr->stream, hipStreamNonBlocking) != hipSuccess)
+    rc = fail(PEPSI_E_DEVICE, "stream creation failed");
+  if (rc) {
+    if (sr->qslot_host) (void)hipHostFree(sr->qslot_host);
+    delete sr;
+    return rc;
+  }
+  sr->eng.timer = nullptr;            // the server timer belongs to the calling thread
+  sr->active.assign(slots, nullptr);
+  sr->worker = std::thread([sr] { sr->loop(); });
+  *out = sr;
+  return PEPSI_OK;
+}
+
+extern "C" int pepsi_serve_submit(pepsi_serve* sr, const uint64_t* cts, const uint64_t* rlk, const uint32_t* mask,
+                                  uint64_t* out, uint64_t* req_id) {
+  if (!sr || !cts || !rlk || !out || !req_id) return fail(PEPSI_E_ARG, "null argument");
+  std::lock_guard<std::mutex> lk(sr->mu);
+  if (sr->err) return fail(sr->err, "%s", sr->err_msg.c_str());
+  auto* r = new pepsi_serve::Req();
+  r->id = sr->next_id++;
+  r->cts = cts; r->rlk = rlk; r->mask = mask; r->out = out;
+  r->t_submit = now_s();
+  sr->reqs[r->id] = r;
+  sr->queue.push_back(r);
+  *req_id = r->id;
+  sr->cv.notify_all();
+  return PEPSI_OK;
+}
+
+static void fill_stats(const pepsi_serve::Req* r, pepsi_req_stats* st) {
+  if (!st) return;
+  st->submit_s = r->t_submit;
+  st->admit_s = r->t_admit;
+  st->done_s = r->t_done;
+  st->slot = (uint32_t)r->slot;
+  st->done = (uint32_t)r->done;
+}
+
+extern "C" int pepsi_serve_poll(pepsi_serve* sr, uint64_t id, int* done, pepsi_req_stats* st) {
+  if (!sr || !done) return fail(PEPSI_E_ARG, "null argument");
+  std::lock_guard<std::mutex> lk(sr->mu);
+  auto it = sr->reqs.find(id);
+  if (it == sr->reqs.end()) return fail(PEPSI_E_ARG, "unknown request %llu", (unsigned long long)id);
+  *done = it->second->done;
+  fill_stats(it->second, st);
+  if (sr->err) return fail(sr->err, "%s", sr->err_msg.c_str());
+  return PEPSI_OK;
+}
+
+extern "C" int pepsi_serve_wait(pepsi_serve* sr, uint64_t id, pepsi_req_stats* st) {
+  if (!sr) return fail(PEPSI_E_ARG, "null argument");
+  std::unique_lock<std::mutex> lk(sr->mu);
+  auto it = sr->reqs.find(id);
+  if (it == sr->reqs.end()) return fail(PEPSI_E_ARG, "unknown request %llu", (unsigned long long)id);
+  pepsi_serve::Req* r = it->second;
+  sr->cv_done.wait(lk, [&] { return r->done || sr->err; });
+  fill_stats(r, st);
+  if (sr->err) return fail(sr->err, "%s", sr->err_msg.c_str());
+  return PEPSI_OK;
+}
+
+extern "C" int pepsi_serve_get_info(pepsi_serve* sr, pepsi_serve_info* o) {
+  if (!sr || !o) return fail(PEPSI_E_ARG, "null argument");
+  std::lock_guard<std::mutex> lk(sr->mu);
+  memset(o, 0, sizeof(*o));
+  o->slots = (uint32_t)sr->slots;
+  o->tiles = (uint32_t)sr->T;
+  o->queued = (uint32_t)sr->queue.size();
+  for (auto* r : sr->active) o->active += r != nullptr;
+  o->steps = sr->steps;
+  o->completed = sr->completed;
+  return PEPSI_OK;
+}
+
+extern "C" void pepsi_serve_destroy(pepsi_serve* sr) {
+  if (!sr) return;
+  {
+    std::lock_guard<std::mutex> lk(sr->mu);
+    sr->stop = true;
+    sr->cv.notify_all();
+  }
+  if (sr->worker.joinable()) sr->worker.join();
+  if (sr->stream) (void)hipStreamDestroy(sr->stream);
+  if (sr->qslot_host) (void)hipHostFree(sr->qslot_host);
+  for (auto& kv : sr->reqs) delete kv.second;
+  delete sr;
+}
 
 // ------------------------------------------------------------------ single steps
 extern "C" int pepsi_ntt(const pepsi_params* P, uint64_t* data, uint32_t rows, uint32_t first,
@@ -921,7 +1182,7 @@ extern "C" int pepsi_relin(const pepsi_params* Pc, const uint64_t* ct3, const ui
   ntt_forward(P->T, H.logn, Dd, LOAD_U64, Dd, STORE_U64, (int)(L * L), (int)L, 0, s);
   ntt_forward(P->T, H.logn, ct3, LOAD_U64, c3h, STORE_U64, (int)(3 * L), (int)L, 0, s);
   ntt_forward(P->T, H.logn, rlk, LOAD_U64, rh, STORE_U64, (int)(2 * L * L), (int)L, 0, s);
-  relin_inner(P->T, H.consts, c3h, Dd, rh, 0, 1, 1, o, 1, s);
+  relin_inner(P->T, H.consts, c3h, Dd, rh, 0, nullptr, 1, 1, o, 1, s);
   ntt_inverse(P->T, H.logn, o, out, (int)(2 * L), (int)L, 0, s);
   HIPCHK(hipGetLastError());
   return PEPSI_OK;

@@ -58,13 +58,15 @@ void relin_digits(const Tables& T, const Consts& hc, const uint64_t* c3, uint64_
                   hipStream_t s);
 // out[r][c] = dhat_c + sum_i Dhat_i * rlk_i,c  (all NTT form); dhat: [rows][3][L][N] (first 2
 // polys used), Dhat [rows][L][L][N]; out [rows][2][L][N].  Row r belongs to pair r / jobs_per_pair,
-// pair = b * nq + q, and uses the key rlk + q * rlk_stride ([L][2][L][N] each).
+// pair = b * nq + q, and uses the key rlk + slot(q) * rlk_stride ([L][2][L][N] each), where
+// slot(q) = qslot[q] (device array) or q when qslot is null; likewise for the other
+// per-query arrays below.
 void relin_inner(const Tables& T, const Consts& hc, const uint64_t* dhat, const uint64_t* Dhat,
-                 const uint64_t* rlk, long rlk_stride, int jobs_per_pair, int nq, uint64_t* out, int rows,
-                 hipStream_t s);
+                 const uint64_t* rlk, long rlk_stride, const int* qslot, int jobs_per_pair, int nq, uint64_t* out,
+                 int rows, hipStream_t s);
 // acc[q][2][L][N] += sum over b < nb of x[b * nq + q] (entries xstride words apart)
 void accumulate(const Tables& T, const Consts& hc, const uint64_t* x, long xstride, int nb, int nq,
-                uint64_t* acc, hipStream_t s);
+                const int* qslot, uint64_t* acc, hipStream_t s);
 // select-and-sum: S[b][c][l][k] = sum_j C[j][c][l][k] * P[b][j][l][k] mod q_l.
 // C: NTT form [ell][2][L][N]; P: split-27 NTT form [nb][ell][L][N]; S rows of stride sstride.
 void select_sum(const Tables& T, const Consts& hc, const uint64_t* C, const uint64_t* P, int ell,
@@ -72,8 +74,8 @@ void select_sum(const Tables& T, const Consts& hc, const uint64_t* C, const uint
 
 // select-and-sum of nq queries (client values Cq + q * cq_stride, NTT form [ell][2][L][N]) against
 // nb plaintext batches; S entry of (batch b, query q) at (b * nq + q) * 2 L N.
-void select_sum_multi(const Tables& T, const Consts& hc, const uint64_t* Cq, long cq_stride, int nq,
-                      const uint64_t* P, int ell, int nb, uint64_t* S, hipStream_t s);
+void select_sum_multi(const Tables& T, const Consts& hc, const uint64_t* Cq, long cq_stride, const int* qslot,
+                      int nq, const uint64_t* P, int ell, int nb, uint64_t* S, hipStream_t s);
 
 // ---------------- elementwise helpers ----------------
 // out = a * b pointwise (both [rows][L][N] NTT form, b broadcast over rows if bcast)

@@ -273,7 +273,7 @@ template <int L>
 __global__ void __launch_bounds__(TPB) k_relin_inner(Tables T, const uint64_t* __restrict__ dhat,
                                                     const uint64_t* __restrict__ Dhat,
                                                     const uint64_t* __restrict__ rlk_base, long rlk_stride,
-                                                    int jobs_per_pair, int nq,
+                                                    const int* __restrict__ qslot, int jobs_per_pair, int nq,
                                                     uint64_t* __restrict__ out) {
   const Consts& C = *T.c;
   const int N = C.n;
@@ -283,7 +283,8 @@ __global__ void __launch_bounds__(TPB) k_relin_inner(Tables T, const uint64_t* _
   if (k >= N) return;
   const Prime& pr = C.prm[j];
   // pair = b * nq + q: the key of the job's query
-  const uint64_t* rlk = rlk_base + (size_t)((row / jobs_per_pair) % nq) * rlk_stride;
+  const int q = (int)((row / jobs_per_pair) % nq);
+  const uint64_t* rlk = rlk_base + (size_t)(qslot ? qslot[q] : q) * rlk_stride;
   u128 a0 = dhat[((row * 3 + 0) * L + j) * N + k];
   u128 a1 = dhat[((row * 3 + 1) * L + j) * N + k];
 #pragma unroll
@@ -298,7 +299,8 @@ __global__ void __launch_bounds__(TPB) k_relin_inner(Tables T, const uint64_t* _
 
 // acc[q] += sum over batches b of x[b * nq + q]  (each entry [2][L][N], xstride words apart)
 __global__ void __launch_bounds__(TPB) k_accumulate(Tables T, const uint64_t* __restrict__ x,
-                                                   long xstride, int nb, int nq, uint64_t* __restrict__ acc) {
+                                                   long xstride, int nb, int nq, const int* __restrict__ qslot,
+                                                   uint64_t* __restrict__ acc) {
   const Consts& C = *T.c;
   const int N = C.n, L = C.L;
   const int k = blockIdx.x * TPB + threadIdx.x;
@@ -306,7 +308,7 @@ __global__ void __launch_bounds__(TPB) k_accumulate(Tables T, const uint64_t* __
   const int q = blockIdx.z;
   if (k >= N) return;
   const Prime& pr = C.prm[cl % L];
-  uint64_t* a = acc + (size_t)q * 2 * L * N;
+  uint64_t* a = acc + (size_t)(qslot ? qslot[q] : q) * 2 * L * N;
   uint64_t s = a[(size_t)cl * N + k];
   int b = 0;
   while (b < nb) {
@@ -402,7 +404,7 @@ __global__ void __launch_bounds__(TPB) k_select_sum(Tables T, const uint64_t* __
 // region are dispatched consecutively to the same XCD and share its L2 for the plaintexts.
 constexpr int MQ = 2, MB = 16, MBB = 4, MTPB = 64 * (MB / MBB);
 __global__ void __launch_bounds__(MTPB) k_select_sum_multi(Tables T, const uint64_t* __restrict__ Cq,
-                                                          long cq_stride, int nq,
+                                                          long cq_stride, const int* __restrict__ qslot, int nq,
                                                           const uint64_t* __restrict__ Pc, int ell, int nb,
                                                           uint64_t* __restrict__ S, int regions, int qgroups) {
   const Consts& C = *T.c;
@@ -425,7 +427,8 @@ __global__ void __launch_bounds__(MTPB) k_select_sum_multi(Tables T, const uint6
   for (int a = 0; a < MQ; ++a)
 #pragma unroll
     for (int c = 0; c < 2; ++c)
-      cp[a][c] = Cq + (size_t)(q0 + min(a, nql - 1)) * cq_stride + ((size_t)c * L + l) * N + kbase + lane;
+      cp[a][c] = Cq + (size_t)(qslot ? qslot[q0 + min(a, nql - 1)] : q0 + min(a, nql - 1)) * cq_stride +
+                 ((size_t)c * L + l) * N + kbase + lane;
 #pragma unroll
   for (int b = 0; b < MBB; ++b)
     pp[b] = Pc + ((size_t)(b0 + min(b, nbl - 1)) * ell * L + l) * N + kbase + lane;
@@ -713,16 +716,17 @@ void relin_digits(const Tables& T, const Consts& hc, const uint64_t* c3, uint64_
   PEPSI_L_LAUNCH(k_relin_digits, hc.L, grid_for(hc.n, rows), dim3(TPB), s, T, c3, D);
 }
 void relin_inner(const Tables& T, const Consts& hc, const uint64_t* dhat, const uint64_t* Dhat,
-                 const uint64_t* rlk, long rlk_stride, int jobs_per_pair, int nq, uint64_t* out, int rows,
-                 hipStream_t s) {
+                 const uint64_t* rlk, long rlk_stride, const int* qslot, int jobs_per_pair, int nq, uint64_t* out,
+                 int rows, hipStream_t s) {
   if (rows <= 0) return;
   PEPSI_L_LAUNCH(k_relin_inner, hc.L, grid_for(hc.n, hc.L, rows), dim3(TPB), s, T, dhat, Dhat, rlk,
-                 rlk_stride, jobs_per_pair, nq, out);
+                 rlk_stride, qslot, jobs_per_pair, nq, out);
 }
 void accumulate(const Tables& T, const Consts& hc, const uint64_t* x, long xstride, int nb, int nq,
-                uint64_t* acc, hipStream_t s) {
+                const int* qslot, uint64_t* acc, hipStream_t s) {
   if (nb <= 0 || nq <= 0) return;
-  hipLaunchKernelGGL(k_accumulate, grid_for(hc.n, 2 * hc.L, nq), dim3(TPB), 0, s, T, x, xstride, nb, nq, acc);
+  hipLaunchKernelGGL(k_accumulate, grid_for(hc.n, 2 * hc.L, nq), dim3(TPB), 0, s, T, x, xstride, nb, nq, qslot,
+                     acc);
 }
 void select_sum(const Tables& T, const Consts& hc, const uint64_t* Cn, const uint64_t* P, int ell,
                 int nb, uint64_t* S, long sstride, hipStream_t s) {
@@ -730,14 +734,14 @@ void select_sum(const Tables& T, const Consts& hc, const uint64_t* Cn, const uin
   hipLaunchKernelGGL(k_select_sum, grid_for(hc.n, hc.L, (nb + IB - 1) / IB), dim3(TPB), 0, s, T, Cn,
                      P, ell, nb, S, sstride);
 }
-void select_sum_multi(const Tables& T, const Consts& hc, const uint64_t* Cq, long cq_stride, int nq,
-                      const uint64_t* P, int ell, int nb, uint64_t* S, hipStream_t s) {
+void select_sum_multi(const Tables& T, const Consts& hc, const uint64_t* Cq, long cq_stride, const int* qslot,
+                      int nq, const uint64_t* P, int ell, int nb, uint64_t* S, hipStream_t s) {
   if (nb <= 0 || nq <= 0) return;
   const int regions = (hc.n / 64) * hc.L * ((nb + MB - 1) / MB);
   const int qgroups = (nq + MQ - 1) / MQ;
   const int blocks = ((regions + 7) / 8) * 8 * qgroups;
-  hipLaunchKernelGGL(k_select_sum_multi, dim3(blocks), dim3(MTPB), 0, s, T, Cq, cq_stride, nq, P, ell, nb,
-                     S, regions, qgroups);
+  hipLaunchKernelGGL(k_select_sum_multi, dim3(blocks), dim3(MTPB), 0, s, T, Cq, cq_stride, qslot, nq, P, ell,
+                     nb, S, regions, qgroups);
 }
 void pointwise_mul(const Tables& T, const Consts& hc, const uint64_t* a, const uint64_t* b,
                    uint64_t* out, int rows, int nprimes, bool bcast, hipStream_t s) {

@@ -36,6 +36,10 @@ CONFIGS = {
     "paper": dict(log_n=13, L=4, h=4, item_bits=32, mu=526, n_server=1 << 20, m_client=1024, planted=256),
     "toy": dict(log_n=12, L=2, h=2, item_bits=16, mu=11, n_server=256, m_client=16, planted=4),
 }
+# Serving workload: a resident n = 2^22 set at N = 8192, mu = 1870 (the least mu with
+# b * P[Bin(3n, 1/b) >= mu] <= 2^-40), requests with m log-uniform in [128, 4096], 25% planted,
+# Poisson arrivals at 0.8 x the measured saturated capacity.
+SERVE = dict(log_n=13, L=4, h=4, item_bits=32, mu=1870, n_server=1 << 22, m_lo=128, m_hi=4096)
 HBM_PEAK_GBS = 8000.0
 
 
@@ -120,6 +124,99 @@ def make_query(params, server_items, cfg, m, planted, seed):
     return dict(sk=sk, cts=cts, rlk=rlk, mask=mask, planted=planted, m=m)
 
 
+def serving_leg(pk, requests, pool, slots, load, seed):
+    """Continuous batching: `requests` requests over a pool of distinct client queries, Poisson arrivals
+    at `load` x the saturated capacity measured first on the same handle; latency = completion minus
+    scheduled arrival."""
+    import torch
+    import workload as W
+    sc = SERVE
+    n, L = 1 << sc["log_n"], sc["L"]
+    params = pk.Params(sc["log_n"], L, sc["h"], sc["item_bits"], sc["mu"])
+    server_items = W.server_items(sc["n_server"], sc["item_bits"], seed)
+    g = W.rng(seed, "serve-sizes")
+    sizes = np.rint(np.exp(g.uniform(np.log(sc["m_lo"]), np.log(sc["m_hi"]), size=pool))).astype(int)
+    log(f"[bench] serving leg: n={sc['n_server']} mu={sc['mu']}, pool of {pool} queries, m in "
+        f"[{sizes.min()}, {sizes.max()}]")
+    qs = [make_query(params, server_items, sc, int(m), int(round(0.25 * m)), seed + 100 * (i + 1))
+          for i, m in enumerate(sizes)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    server = pk.Server(params, server_items, cache_plaintexts=True)
+    torch.cuda.synchronize()
+    prep_s = time.perf_counter() - t0
+    log(f"[bench] serving server ready in {prep_s:.1f} s: max load {server.max_load}, "
+        f"{server.cached_batches} of {server.max_load} batches cached")
+    srv = pk.Serve(server, max_active=slots)
+    outs = [torch.zeros((2, L, n), dtype=torch.int64, device="cuda") for _ in range(requests)]
+    torch.cuda.synchronize()
+
+    def submit(i):
+        q = qs[i % pool]
+        return srv.submit(q["cts"], q["rlk"], q["mask"], outs[i])
+
+    # saturated capacity: one full set of slots at once
+    c0 = pk.clock()
+    ids = [submit(i) for i in range(slots)]
+    st = [srv.wait(r) for r in ids]
+    capacity = slots / (max(s.done_s for s in st) - c0)
+    rate = load * capacity
+    log(f"[bench] saturated capacity {capacity:.2f} queries/s; arrivals at {rate:.2f}/s")
+    arrivals = np.cumsum(W.rng(seed, "serve-arrivals").exponential(1.0 / rate, size=requests))
+    ids = []
+    c0 = pk.clock()
+    for i in range(requests):
+        while pk.clock() < c0 + arrivals[i]:
+            time.sleep(min(0.002, max(0.0, c0 + arrivals[i] - pk.clock())))
+        ids.append(submit(i))
+        if (i + 1) % 100 == 0:
+            log(f"[bench] submitted {i + 1}/{requests}, completed {srv.info().completed - slots}")
+    st = [srv.wait(r) for r in ids]
+    info = srv.info()
+    srv.close()
+    lat = np.array([s.done_s - (c0 + a) for s, a in zip(st, arrivals)])
+    span = max(s.done_s for s in st) - c0
+    # every request decrypts to its planted cardinality, and repeats of one query are bit-identical
+    bad = 0
+    first = {}
+    for i in range(requests):
+        k = i % pool
+        if k in first:
+            bad += not torch.equal(outs[i], outs[first[k]])
+            continue
+        first[k] = i
+        slots_t = torch.zeros((1, n), dtype=torch.int32, device="cuda")
+        params.decrypt(qs[k]["sk"], outs[i].reshape(1, 2, L, n), slots_t)
+        torch.cuda.synchronize()
+        bad += int(slots_t.cpu().numpy().view(np.uint32).astype(np.int64).sum() % 65537) != qs[k]["planted"]
+    if bad:
+        log(f"[bench] WRONG RESULT in {bad} served requests")
+        sys.exit(1)
+    max_load, cached_batches = server.max_load, server.cached_batches
+    server.close()
+    comparisons = n * sc["mu"]
+    return {
+        "workload": (f"N={n} L={L} h={sc['h']} ell={params.ell} n={sc['n_server']} mu={sc['mu']}, "
+                     f"m log-uniform [{sc['m_lo']}, {sc['m_hi']}], 25% planted"),
+        "requests": requests,
+        "query_pool": pool,
+        "slots": info.slots,
+        "tiles_per_cycle": info.tiles,
+        "cached_batches": int(cached_batches),
+        "server_max_load": int(max_load),
+        "saturated_queries_per_s": round(capacity, 3),
+        "arrival_rate_per_s": round(rate, 3),
+        "queries_per_s": round(requests / span, 3),
+        "value": round(requests * comparisons / span, 1),
+        "unit": "slot-comparisons/s",
+        "latency_ms": {"p50": round(1e3 * float(np.percentile(lat, 50)), 1),
+                       "p99": round(1e3 * float(np.percentile(lat, 99)), 1),
+                       "max": round(1e3 * float(lat.max()), 1)},
+        "prep_s": round(prep_s, 2),
+        "checked": "cardinality of every pool query; repeats bit-identical",
+    }
+
+
 def batched_leg(params, server, server_items, cfg, nq, steps, seed, plain_value):
     """Config 'batched': nq queries, m log-uniform in [64, 2048], 25% planted, one launch sequence."""
     import torch
@@ -177,11 +274,18 @@ def main():
     ap.add_argument("--batch", type=int, default=64, help="queries per batched launch (0: skip the batched leg)")
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--seed", type=int, default=2024)
+    ap.add_argument("--serve", type=int, default=500, help="requests in the serving leg (0: skip it)")
+    ap.add_argument("--serve-pool", type=int, default=16, help="distinct client queries behind the requests")
+    ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate / saturated capacity")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="after the plain leg, run one elementwise negation of MIB MiB of int64 (a copy kernel "
+                         "of known traffic, for scaling hardware byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: every GPU box of this build has one GPU "
-              "(the multi-GPU sharding of the path is a design note, not a measured line)", file=sys.stderr)
+        print("bench.py measures one GPU only; sharding the server computation over several GPUs "
+              "is described in the design notes, not measured", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -300,9 +404,24 @@ def main():
         "server_max_load": server.max_load,
         "check": {"cardinality": card, "noise_budget_bits": budget},
     }
+    if args.copy_calibration > 0:
+        words = (args.copy_calibration << 20) // 8
+        src = torch.ones(words, dtype=torch.int64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        line["copy_calibration_bytes"] = {"read": words * 8, "written": words * 8}
+        del src, dst
     if args.batch > 0:
         line["batched"] = batched_leg(params, server, server_items, cfg, args.batch, args.batch_steps,
                                       args.seed + 7, value)
+    if args.serve > 0:
+        server.close()
+        del cts, rlk, out
+        torch.cuda.empty_cache()
+        line["serving"] = serving_leg(pk, args.serve, args.serve_pool, args.serve_slots, args.serve_load,
+                                      args.seed + 11)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample)")
         line["cpu_baseline"] = cpu_baseline(cfg, params, server_items, args.seed)

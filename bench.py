@@ -54,15 +54,24 @@ def dev(a: np.ndarray):
     return torch.from_numpy(a.view(view).copy()).cuda()
 
 
+def select_sum_source_digest() -> str:
+    """SHA-256 of the select-and-sum kernel's source (its constants, helper, kernel body and launcher):
+    hardware byte counts taken for one version of the kernel are void for any other."""
+    src = open(os.path.join(ROOT, "paper_2310_14565_amd", "csrc", "rns.hip")).read()
+    a = src.index("constexpr int IB = 8;")
+    z = src.index("// Select-and-sum of several queries")
+    la = src.index("void select_sum(const Tables& T")
+    lz = src.index("\n}\n", la) + 3
+    return hashlib.sha256((src[a:z] + src[la:lz]).encode()).hexdigest()
+
+
 def traffic_record(kernel: str):
-    """HBM traffic from committed rocprofv3 counter runs, if they match the current kernel source."""
+    """HBM traffic from committed rocprofv3 counter runs, if they were taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = os.path.join(ROOT, "paper_2310_14565_amd", "csrc", rec.get("source", "rns.hip"))
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if sha != rec.get("source_sha256"):
+    if rec.get("source_sha256") != select_sum_source_digest():
         return None
     return rec
 

@@ -409,8 +409,8 @@ struct Engine {
   int TBq = 0, Qmax = 0, levels = 0;
   std::vector<int> jobs_at;            // tensor jobs per pair at each tree level
   DevBuf chat, rlkhat, acc;            // per query: request and key in NTT form, running sum
-  DevBuf sq, scoef, sb, alpha, e;      // per pair
-  DevBuf d, c3, c3h, D, rcoef;         // per tensor job
+  DevBuf sq, scoef, sb, sbh, alpha, e; // per pair: S over Q (NTT, coefficients), over B (both), ...
+  DevBuf d, c01, c01h, c2, D, rcoef;   // per tensor job
   std::vector<DevBuf> rq, rb;          // per tree level outputs
   DevBuf jobs;                         // device TensorJob arrays, all levels
   DevBuf gen_poly, gen_p;              // on-the-fly plaintext generation
@@ -418,8 +418,8 @@ struct Engine {
   EventTimer* timer = nullptr;
 
   ~Engine() {
-    for (DevBuf* b : {&chat, &rlkhat, &acc, &sq, &scoef, &sb, &alpha, &e, &d, &c3, &c3h, &D, &rcoef,
-                      &jobs, &gen_poly, &gen_p})
+    for (DevBuf* b : {&chat, &rlkhat, &acc, &sq, &scoef, &sb, &sbh, &alpha, &e, &d, &c01, &c01h, &c2, &D,
+                      &rcoef, &jobs, &gen_poly, &gen_p})
       b->release();
     for (auto& b : rq) b.release();
     for (auto& b : rb) b.release();
@@ -449,10 +449,12 @@ struct Engine {
       const size_t J = PC * jobs_at[0];
       if ((rc = scoef.ensure(PC * 2 * L * n * 8))) return rc;
       if ((rc = sb.ensure(PC * 2 * K * n * 8))) return rc;
+      if ((rc = sbh.ensure(PC * 2 * K * n * 8))) return rc;
       if ((rc = alpha.ensure(PC * H.h * Pn * 8))) return rc;
       if ((rc = d.ensure(J * 3 * Pn * n * 8))) return rc;
-      if ((rc = c3.ensure(J * 3 * L * n * 8))) return rc;
-      if ((rc = c3h.ensure(J * 3 * L * n * 8))) return rc;
+      if ((rc = c01.ensure(J * 2 * L * n * 8))) return rc;
+      if ((rc = c01h.ensure(J * 2 * L * n * 8))) return rc;
+      if ((rc = c2.ensure(J * L * n * 8))) return rc;
       if ((rc = D.ensure(J * L * L * n * 8))) return rc;
       if ((rc = rcoef.ensure(J * 2 * L * n * 8))) return rc;
       rq.resize(levels);
@@ -485,7 +487,7 @@ struct Engine {
       std::vector<std::vector<Operand>> ops(npairs);
       for (int p = 0; p < npairs; ++p)
         for (int r = 0; r < H.h; ++r)
-          ops[p].push_back(Operand{sq.as<uint64_t>((size_t)p * 2 * L * n), sb.as<uint64_t>((size_t)p * 2 * K * n),
+          ops[p].push_back(Operand{sq.as<uint64_t>((size_t)p * 2 * L * n), sbh.as<uint64_t>((size_t)p * 2 * K * n),
                                    alpha.as<uint64_t>(((size_t)p * H.h + r) * Pn)});
       for (int lv = 0; lv < levels; ++lv) {
         const int pairs = jobs_at[lv];
@@ -516,28 +518,52 @@ struct Engine {
     return 0;
   }
 
-  // Products + relinearisation of njobs jobs (results NTT form into out [njobs][2][L][N]);
-  // with ext_out also the Q -> B extension of the results, NTT form.
-  void multiply_relin(const TensorJob* dev_jobs, int njobs, int jobs_per_pair, int nq, const int* qslot,
-                      uint64_t* out, uint64_t* ext_out, hipStream_t s, int key_slot = 0) {
+  // Relinearisation of the products in c01 / c2 (coefficient form) into out [jobs][2][L][N], NTT
+  // form: units share one component 2 (jobs_per_unit jobs each); unit / units_per_pair is the
+  // pair.  With ext_out also the Q -> B extension of the results, NTT form.
+  void relin_stage(int units, int jobs_per_unit, int units_per_pair, int nq, const int* qslot, uint64_t* out,
+                   uint64_t* ext_out, hipStream_t s, int key_slot) {
     const HostParams& H = P->H;
-    const int L = H.L, K = H.K, Pn = L + K;
-    uint64_t* dd = d.as<uint64_t>();
-    tensor(P->T, H.consts, dev_jobs, njobs, s);
-    ntt_inverse(P->T, H.logn, dd, dd, njobs * 3 * Pn, Pn, 0, s);
-    scale_round(P->T, H.consts, dd, c3.as<uint64_t>(), njobs, P->fallback.as<uint32_t>(), s);
-    relin_digits(P->T, H.consts, c3.as<uint64_t>(), D.as<uint64_t>(), njobs, s);
-    ntt_forward(P->T, H.logn, D.p, LOAD_U64, D.p, STORE_U64, njobs * L * L, L, 0, s);
-    ntt_forward(P->T, H.logn, c3.p, LOAD_U64, c3h.p, STORE_U64, njobs * 3 * L, L, 0, s);
-    relin_inner(P->T, H.consts, c3h.as<uint64_t>(), D.as<uint64_t>(),
-                rlkhat.as<uint64_t>((size_t)key_slot * rstride()), (long)rstride(), qslot, jobs_per_pair, nq, out,
-                njobs, s);
+    const int L = H.L, K = H.K;
+    const int njobs = units * jobs_per_unit;
+    relin_digits(P->T, H.consts, c2.as<uint64_t>(), D.as<uint64_t>(), units, s);
+    ntt_forward(P->T, H.logn, D.p, LOAD_U64, D.p, STORE_U64, units * L * L, L, 0, s);
+    ntt_forward(P->T, H.logn, c01.p, LOAD_U64, c01h.p, STORE_U64, njobs * 2 * L, L, 0, s);
+    relin_inner(P->T, H.consts, c01h.as<uint64_t>(), D.as<uint64_t>(),
+                rlkhat.as<uint64_t>((size_t)key_slot * rstride()), (long)rstride(), qslot, jobs_per_unit,
+                units_per_pair, nq, out, units, s);
     if (ext_out) {
       ntt_inverse(P->T, H.logn, out, rcoef.as<uint64_t>(), njobs * 2 * L, L, 0, s);
       ext_q_to_b(P->T, H.consts, rcoef.as<uint64_t>(), ext_out, (long)K * H.n, njobs * 2,
                  P->fallback.as<uint32_t>(), s);
       ntt_forward(P->T, H.logn, ext_out, LOAD_U64, ext_out, STORE_U64, njobs * 2 * K, K, L, s);
     }
+  }
+
+  // First tree level of npairs pairs: the h / 2 products (f_2u, f_2u+1) of each pair share the
+  // products of S (k_square), one inverse NTT of them and one relinearisation sum.
+  void first_level(int npairs, int nq, const int* qslot, uint64_t* out, uint64_t* ext_out, hipStream_t s,
+                   int key_slot) {
+    const HostParams& H = P->H;
+    const int Pn = H.L + H.K;
+    uint64_t* dd = d.as<uint64_t>();
+    square_products(P->T, H.consts, sq.as<uint64_t>(), sbh.as<uint64_t>(), dd, npairs, s);
+    ntt_inverse(P->T, H.logn, dd, dd, npairs * 3 * Pn, Pn, 0, s);
+    scale_round_first(P->T, H.consts, dd, scoef.as<uint64_t>(), sb.as<uint64_t>(), alpha.as<uint64_t>(), H.h,
+                      npairs, c01.as<uint64_t>(), c2.as<uint64_t>(), P->fallback.as<uint32_t>(), s);
+    relin_stage(npairs, H.h / 2, 1, nq, qslot, out, ext_out, s, key_slot);
+  }
+
+  // A later tree level: njobs independent products (TensorJob operands), then relinearisation.
+  void later_level(const TensorJob* dev_jobs, int njobs, int jobs_per_pair, int nq, const int* qslot,
+                   uint64_t* out, uint64_t* ext_out, hipStream_t s, int key_slot) {
+    const HostParams& H = P->H;
+    const int Pn = H.L + H.K;
+    uint64_t* dd = d.as<uint64_t>();
+    tensor(P->T, H.consts, dev_jobs, njobs, s);
+    ntt_inverse(P->T, H.logn, dd, dd, njobs * 3 * Pn, Pn, 0, s);
+    scale_round(P->T, H.consts, dd, c01.as<uint64_t>(), c2.as<uint64_t>(), njobs, P->fallback.as<uint32_t>(), s);
+    relin_stage(njobs, 1, jobs_per_pair, nq, qslot, out, ext_out, s, key_slot);
   }
 
   // A query enters slot `slot`: request and key to NTT form, running sum to zero.
@@ -597,17 +623,22 @@ struct Engine {
     ntt_inverse(P->T, H.logn, Sq, scoef.as<uint64_t>(), npairs * 2 * (int)L, (int)L, 0, s);
     ext_q_to_b(P->T, H.consts, scoef.as<uint64_t>(), sb.as<uint64_t>(), (long)(K * n), npairs * 2,
                P->fallback.as<uint32_t>(), s);
-    ntt_forward(P->T, H.logn, sb.p, LOAD_U64, sb.p, STORE_U64, npairs * 2 * (int)K, (int)K, (int)L, s);
+    ntt_forward(P->T, H.logn, sb.p, LOAD_U64, sbh.p, STORE_U64, npairs * 2 * (int)K, (int)K, (int)L, s);
     factor_constants(P->T, H.consts, scoef.as<uint64_t>(), npairs, H.h, alpha.as<uint64_t>(),
                      P->fallback.as<uint32_t>(), s);
     // the key of a single active query: shift the key base to its slot
     const int* rslot = nq == 1 ? nullptr : qslot;
+    const int key_slot = nq == 1 ? single_slot : 0;
     for (int lv = 0; lv < levels; ++lv) {
-      const int njobs = npairs * jobs_at[lv];
-      const TensorJob* jl = jobs.as<TensorJob>() + job_off_na[nq][lv];
       const bool last = lv + 1 == levels;
-      multiply_relin(jl, njobs, jobs_at[lv], nq, rslot, last ? e.as<uint64_t>() : rq[lv].as<uint64_t>(),
-                     last ? nullptr : rb[lv].as<uint64_t>(), s, nq == 1 ? single_slot : 0);
+      uint64_t* out = last ? e.as<uint64_t>() : rq[lv].as<uint64_t>();
+      uint64_t* ext_out = last ? nullptr : rb[lv].as<uint64_t>();
+      if (lv == 0) {
+        first_level(npairs, nq, rslot, out, ext_out, s, key_slot);
+      } else {
+        const TensorJob* jl = jobs.as<TensorJob>() + job_off_na[nq][lv];
+        later_level(jl, npairs * jobs_at[lv], jobs_at[lv], nq, rslot, out, ext_out, s, key_slot);
+      }
     }
     accumulate(P->T, H.consts, e.as<uint64_t>(), (long)(2 * L * n), nb, nq, acc_slot, acc_base, s);
   }
@@ -973,7 +1004,7 @@ extern "C" int pepsi_serve_create(pepsi_server* sv, uint32_t max_active, uint64_
   // device memory per slot: request + key + sum in NTT form, and tbq pairs of tile buffers
   const size_t n = H.n, L = H.L, K = H.K, Pn = L + K;
   const size_t jobs0 = (size_t)(H.h / 2 > 0 ? H.h / 2 : 1);
-  const size_t per_pair = 8 * n * (2 * L * 3 + 2 * K + jobs0 * (3 * Pn + 6 * L + L * L + 2 * L + 2 * L + 2 * K));
+  const size_t per_pair = 8 * n * (2 * L * 3 + 4 * K + jobs0 * (3 * Pn + 5 * L + L * L + 2 * L + 2 * L + 2 * K));
   const size_t per_slot = 8 * ((size_t)H.ell * 2 * L * n + L * 2 * L * n + 2 * L * n) + tbq * per_pair;
   uint32_t slots = max_active ? max_active : PEPSI_MAX_BATCH;
   if (hbm_budget) slots = (uint32_t)std::min<uint64_t>(slots, hbm_budget / per_slot);
@@ -1158,7 +1189,7 @@ extern "C" int pepsi_multiply(const pepsi_params* Pc, const uint64_t* x, const u
   HIPCHK(hipMemcpyAsync(P->job_dev.p, &job, sizeof(job), hipMemcpyHostToDevice, s));
   tensor(P->T, H.consts, P->job_dev.as<TensorJob>(), 1, s);
   ntt_inverse(P->T, H.logn, dd, dd, (int)(3 * Pn), (int)Pn, 0, s);
-  scale_round(P->T, H.consts, dd, out, 1, P->fallback.as<uint32_t>(), s);
+  scale_round(P->T, H.consts, dd, out, out + 2 * L * n, 1, P->fallback.as<uint32_t>(), s);
   HIPCHK(hipStreamSynchronize(s));       // the job record lives on the host stack
   return PEPSI_OK;
 }
@@ -1178,11 +1209,11 @@ extern "C" int pepsi_relin(const pepsi_params* Pc, const uint64_t* ct3, const ui
   uint64_t* rh = Dd + w_D;
   uint64_t* o = rh + w_r;
   hipStream_t s = S(stream);
-  relin_digits(P->T, H.consts, ct3, Dd, 1, s);
+  relin_digits(P->T, H.consts, ct3 + 2 * L * n, Dd, 1, s);
   ntt_forward(P->T, H.logn, Dd, LOAD_U64, Dd, STORE_U64, (int)(L * L), (int)L, 0, s);
-  ntt_forward(P->T, H.logn, ct3, LOAD_U64, c3h, STORE_U64, (int)(3 * L), (int)L, 0, s);
+  ntt_forward(P->T, H.logn, ct3, LOAD_U64, c3h, STORE_U64, (int)(2 * L), (int)L, 0, s);
   ntt_forward(P->T, H.logn, rlk, LOAD_U64, rh, STORE_U64, (int)(2 * L * L), (int)L, 0, s);
-  relin_inner(P->T, H.consts, c3h, Dd, rh, 0, nullptr, 1, 1, o, 1, s);
+  relin_inner(P->T, H.consts, c3h, Dd, rh, 0, nullptr, 1, 1, 1, o, 1, s);
   ntt_inverse(P->T, H.logn, o, out, (int)(2 * L), (int)L, 0, s);
   HIPCHK(hipGetLastError());
   return PEPSI_OK;

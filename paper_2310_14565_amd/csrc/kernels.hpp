@@ -50,20 +50,32 @@ struct TensorJob {
   const uint64_t* ax; const uint64_t* ay; uint64_t* d;
 };
 void tensor(const Tables& T, const Consts& hc, const TensorJob* jobs_dev, int njobs, hipStream_t s);
-// round(t d / Q) for d over Q u B (coefficient form [rows][3][L+K][N]) -> [rows][3][L][N] mod Q
-void scale_round(const Tables& T, const Consts& hc, const uint64_t* d, uint64_t* out, int rows,
+// First tree level: d[p] = (X0^2, 2 X0 X1, X1^2) over Q u B for each pair's select-and-sum X,
+// given in NTT form as xq [pairs][2][L][N] and xb [pairs][2][K][N]; d [pairs][3][L+K][N].
+void square_products(const Tables& T, const Consts& hc, const uint64_t* xq, const uint64_t* xb, uint64_t* d,
+                     int pairs, hipStream_t s);
+// round(t d / Q) for d over Q u B (coefficient form [jobs][3][L+K][N]), mod Q: components 0, 1
+// to c01 [jobs][2][L][N], component 2 to c2 [jobs][L][N].
+void scale_round(const Tables& T, const Consts& hc, const uint64_t* d, uint64_t* c01, uint64_t* c2, int jobs,
                  uint32_t* fallback_count, hipStream_t s);
-// relinearisation digits: c3 [rows][3][L][N] coefficient form -> D [rows][L][L][N]
-void relin_digits(const Tables& T, const Consts& hc, const uint64_t* c3, uint64_t* D, int rows,
+// The same for the h / 2 first-level products (f_2u, f_2u+1) of each pair, f_r = X + delta_r:
+// d = square_products output after the inverse NTT; xq, xb: X in coefficient form over Q and B;
+// alpha [pairs][h][L+K] = delta_r mod each prime.  c01 [pairs * h/2][2][L][N], c2 [pairs][L][N]
+// (component 2 is X1^2 for every product of a pair).
+void scale_round_first(const Tables& T, const Consts& hc, const uint64_t* d, const uint64_t* xq,
+                       const uint64_t* xb, const uint64_t* alpha, int h, int pairs, uint64_t* c01, uint64_t* c2,
+                       uint32_t* fallback_count, hipStream_t s);
+// relinearisation digits: c2 [units][L][N] coefficient form -> D [units][L][L][N]
+void relin_digits(const Tables& T, const Consts& hc, const uint64_t* c2, uint64_t* D, int units,
                   hipStream_t s);
-// out[r][c] = dhat_c + sum_i Dhat_i * rlk_i,c  (all NTT form); dhat: [rows][3][L][N] (first 2
-// polys used), Dhat [rows][L][L][N]; out [rows][2][L][N].  Row r belongs to pair r / jobs_per_pair,
-// pair = b * nq + q, and uses the key rlk + slot(q) * rlk_stride ([L][2][L][N] each), where
-// slot(q) = qslot[q] (device array) or q when qslot is null; likewise for the other
-// per-query arrays below.
-void relin_inner(const Tables& T, const Consts& hc, const uint64_t* dhat, const uint64_t* Dhat,
-                 const uint64_t* rlk, long rlk_stride, const int* qslot, int jobs_per_pair, int nq, uint64_t* out,
-                 int rows, hipStream_t s);
+// out[job][c] = c01h[job][c] + sum_i Dhat[unit]_i * rlk_i,c (all NTT form) for the jobs_per_unit
+// jobs of each unit (job = unit * jobs_per_unit + u); c01h, out [jobs][2][L][N], Dhat
+// [units][L][L][N].  Unit u belongs to pair u / units_per_pair, pair = b * nq + q, and uses the
+// key rlk + slot(q) * rlk_stride ([L][2][L][N] each), where slot(q) = qslot[q] (device array) or
+// q when qslot is null; likewise for the other per-query arrays below.
+void relin_inner(const Tables& T, const Consts& hc, const uint64_t* c01h, const uint64_t* Dhat,
+                 const uint64_t* rlk, long rlk_stride, const int* qslot, int jobs_per_unit, int units_per_pair,
+                 int nq, uint64_t* out, int units, hipStream_t s);
 // acc[q][2][L][N] += sum over b < nb of x[b * nq + q] (entries xstride words apart)
 void accumulate(const Tables& T, const Consts& hc, const uint64_t* x, long xstride, int nb, int nq,
                 const int* qslot, uint64_t* acc, hipStream_t s);

@@ -193,20 +193,90 @@ __global__ void __launch_bounds__(TPB) k_tensor(Tables T, const TensorJob* __res
   J.d[(size_t)(2 * P + p) * N + k] = mulmod(x1, y1, pr);
 }
 
-// round(t d / Q) into B, then the centred B -> Q extension.
-template <int L>
+// First tree level.  Every factor is f_r = X + delta_r (X the select-and-sum ciphertext, delta_r
+// an integer added to coefficient 0 of c0, the exact difference of the centred lifts), so over
+// the integers
+//   (X + delta_a) (X + delta_b) = (X0^2 + s X0 + p,  2 X0 X1 + s X1,  X1^2),
+// s = delta_a + delta_b, p = delta_a delta_b.  The three products of X are formed once per pair
+// here; k_scale_round<L, true> adds the linear terms of each job in coefficient form.
+__global__ void __launch_bounds__(TPB) k_square(Tables T, const uint64_t* __restrict__ xq,
+                                               const uint64_t* __restrict__ xb, uint64_t* __restrict__ d) {
+  const Consts& C = *T.c;
+  const int N = C.n, L = C.L, K = C.K, P = L + K;
+  const int k = blockIdx.x * TPB + threadIdx.x;
+  const int p = blockIdx.y;
+  const size_t pair = blockIdx.z;
+  if (k >= N) return;
+  const Prime& pr = C.prm[p];
+  uint64_t x0, x1;
+  if (p < L) {
+    x0 = xq[((pair * 2 + 0) * L + p) * N + k];
+    x1 = xq[((pair * 2 + 1) * L + p) * N + k];
+  } else {
+    x0 = xb[((pair * 2 + 0) * K + p - L) * N + k];
+    x1 = xb[((pair * 2 + 1) * K + p - L) * N + k];
+  }
+  d[((pair * 3 + 0) * P + p) * N + k] = mulmod(x0, x0, pr);
+  d[((pair * 3 + 1) * P + p) * N + k] = mulmod(addmod(x0, x0, pr.p), x1, pr);
+  d[((pair * 3 + 2) * P + p) * N + k] = mulmod(x1, x1, pr);
+}
+
+// round(t d / Q) into B, then the centred B -> Q extension.  Components 0 and 1 of every job go
+// to c01 [job][2][L][N], component 2 to c2 [unit][L][N].
+//   FIRST = false: d [job][3][P][N], one unit per job (poly = job * 3 + component).
+//   FIRST = true:  d [pair][3][P][N] holds the products of X (k_square); each pair has J0 jobs
+//                  (factors 2u, 2u + 1) sharing one component 2, poly = pair * (2 J0 + 1) + e.
+template <int L, bool FIRST>
 __global__ void __launch_bounds__(TPB) k_scale_round(Tables T, const uint64_t* __restrict__ d,
-                                                    uint64_t* __restrict__ out, uint32_t* fallback) {
+                                                    const uint64_t* __restrict__ xq,
+                                                    const uint64_t* __restrict__ xb,
+                                                    const uint64_t* __restrict__ alpha, int h, int J0,
+                                                    uint64_t* __restrict__ c01, uint64_t* __restrict__ c2,
+                                                    uint32_t* fallback) {
   const Consts& C = *T.c;
   constexpr int K = L + 1, P = L + K;
   const int N = C.n;
   const int k = blockIdx.x * TPB + threadIdx.x;
-  const size_t poly = blockIdx.y;                 // row * 3 + component
+  const size_t poly = blockIdx.y;
   if (k >= N) return;
+  const uint64_t* src;
+  uint64_t* dst;
+  size_t pair = 0;
+  int u = 0, comp;
+  bool lin = false;
+  if (FIRST) {
+    const int per = 2 * J0 + 1;
+    pair = poly / per;
+    const int e = (int)(poly % per);
+    if (e < 2 * J0) {
+      u = e >> 1;
+      comp = e & 1;
+      lin = true;
+      src = d + (pair * 3 + comp) * P * N;
+      dst = c01 + ((pair * J0 + u) * 2 + comp) * L * N;
+    } else {
+      comp = 2;
+      src = d + (pair * 3 + 2) * P * N;
+      dst = c2 + pair * L * N;
+    }
+  } else {
+    const size_t job = poly / 3;
+    comp = (int)(poly % 3);
+    src = d + poly * P * N;
+    dst = comp < 2 ? c01 + (job * 2 + comp) * L * N : c2 + job * L * N;
+  }
   uint64_t y[P];
 #pragma unroll
   for (int p = 0; p < P; ++p) {
-    const uint64_t v = d[(poly * P + p) * N + k];
+    uint64_t v = src[(size_t)p * N + k];
+    if (FIRST && lin) {
+      const Prime& pr = C.prm[p];
+      const uint64_t da = alpha[(pair * h + 2 * u) * P + p], db = alpha[(pair * h + 2 * u + 1) * P + p];
+      const uint64_t xv = p < L ? xq[((pair * 2 + comp) * L + p) * N + k]
+                                : xb[((pair * 2 + comp) * K + p - L) * N + k];
+      v = addmod(v, mulmod(addmod(da, db, pr.p), xv, pr), pr.p);
+      if (comp == 0 && k == 0) v = addmod(v, mulmod(da, db, pr), pr.p);
+    }
     y[p] = shoup(v, C.phat_inv[p], C.phat_inv_shoup[p], C.prm[p].p);
   }
   FixAcc a{0, 0};
@@ -245,12 +315,13 @@ __global__ void __launch_bounds__(TPB) k_scale_round(Tables T, const uint64_t* _
     u128 acc = (u128)v * (pr.p - C.b_mod_q[i]);
 #pragma unroll
     for (int j = 0; j < K; ++j) acc += (u128)yb[j] * C.bhat_mod_q[j][i];
-    out[(poly * L + i) * N + k] = reduce116((uint64_t)acc, (uint64_t)(acc >> 64), pr);
+    dst[(size_t)i * N + k] = reduce116((uint64_t)acc, (uint64_t)(acc >> 64), pr);
   }
 }
 
+// D_i = [c2 (Q/q_i)^-1]_{q_i} of every unit, as residues mod every q_j: D [unit][i][j][N].
 template <int L>
-__global__ void __launch_bounds__(TPB) k_relin_digits(Tables T, const uint64_t* __restrict__ c3,
+__global__ void __launch_bounds__(TPB) k_relin_digits(Tables T, const uint64_t* __restrict__ c2,
                                                      uint64_t* __restrict__ D) {
   const Consts& C = *T.c;
   const int N = C.n;
@@ -259,7 +330,7 @@ __global__ void __launch_bounds__(TPB) k_relin_digits(Tables T, const uint64_t* 
   if (k >= N) return;
 #pragma unroll
   for (int i = 0; i < L; ++i) {
-    const uint64_t v = c3[((row * 3 + 2) * L + i) * N + k];
+    const uint64_t v = c2[(row * L + i) * N + k];
     const uint64_t Di = shoup(v, C.qhat_inv[i], C.qhat_inv_shoup[i], C.prm[i].p);
 #pragma unroll
     for (int j = 0; j < L; ++j) {
@@ -269,32 +340,39 @@ __global__ void __launch_bounds__(TPB) k_relin_digits(Tables T, const uint64_t* 
   }
 }
 
+// out[job] = c01h[job] + sum_i Dhat_i (.) rlk_i for the jobs_per_unit jobs of each unit (they
+// share one component 2, so the key sum is formed once).  unit / units_per_pair is the pair
+// b * nq + q, whose query q selects the key.
 template <int L>
-__global__ void __launch_bounds__(TPB) k_relin_inner(Tables T, const uint64_t* __restrict__ dhat,
+__global__ void __launch_bounds__(TPB) k_relin_inner(Tables T, const uint64_t* __restrict__ c01h,
                                                     const uint64_t* __restrict__ Dhat,
                                                     const uint64_t* __restrict__ rlk_base, long rlk_stride,
-                                                    const int* __restrict__ qslot, int jobs_per_pair, int nq,
-                                                    uint64_t* __restrict__ out) {
+                                                    const int* __restrict__ qslot, int jobs_per_unit,
+                                                    int units_per_pair, int nq, uint64_t* __restrict__ out) {
   const Consts& C = *T.c;
   const int N = C.n;
   const int k = blockIdx.x * TPB + threadIdx.x;
   const int j = blockIdx.y;
-  const size_t row = blockIdx.z;
+  const size_t unit = blockIdx.z;
   if (k >= N) return;
   const Prime& pr = C.prm[j];
-  // pair = b * nq + q: the key of the job's query
-  const int q = (int)((row / jobs_per_pair) % nq);
+  const int q = (int)((unit / units_per_pair) % nq);
   const uint64_t* rlk = rlk_base + (size_t)(qslot ? qslot[q] : q) * rlk_stride;
-  u128 a0 = dhat[((row * 3 + 0) * L + j) * N + k];
-  u128 a1 = dhat[((row * 3 + 1) * L + j) * N + k];
+  u128 a0 = 0, a1 = 0;
 #pragma unroll
   for (int i = 0; i < L; ++i) {
-    const uint64_t dv = Dhat[((row * L + i) * L + j) * N + k];
+    const uint64_t dv = Dhat[((unit * L + i) * L + j) * N + k];
     a0 += (u128)dv * rlk[(((size_t)i * 2 + 0) * L + j) * N + k];
     a1 += (u128)dv * rlk[(((size_t)i * 2 + 1) * L + j) * N + k];
   }
-  out[(row * 2 + 0) * L * N + (size_t)j * N + k] = reduce116((uint64_t)a0, (uint64_t)(a0 >> 64), pr);
-  out[(row * 2 + 1) * L * N + (size_t)j * N + k] = reduce116((uint64_t)a1, (uint64_t)(a1 >> 64), pr);
+  const uint64_t r0 = reduce116((uint64_t)a0, (uint64_t)(a0 >> 64), pr);
+  const uint64_t r1 = reduce116((uint64_t)a1, (uint64_t)(a1 >> 64), pr);
+  for (int u = 0; u < jobs_per_unit; ++u) {
+    const size_t job = unit * jobs_per_unit + u;
+    const size_t o0 = ((job * 2 + 0) * L + j) * N + k, o1 = ((job * 2 + 1) * L + j) * N + k;
+    out[o0] = addmod(r0, c01h[o0], pr.p);
+    out[o1] = addmod(r1, c01h[o1], pr.p);
+  }
 }
 
 // acc[q] += sum over batches b of x[b * nq + q]  (each entry [2][L][N], xstride words apart)
@@ -705,22 +783,44 @@ void tensor(const Tables& T, const Consts& hc, const TensorJob* jobs, int njobs,
   if (njobs <= 0) return;
   hipLaunchKernelGGL(k_tensor, grid_for(hc.n, hc.L + hc.K, njobs), dim3(TPB), 0, s, T, jobs);
 }
-void scale_round(const Tables& T, const Consts& hc, const uint64_t* d, uint64_t* out, int rows,
+void square_products(const Tables& T, const Consts& hc, const uint64_t* xq, const uint64_t* xb, uint64_t* d,
+                     int pairs, hipStream_t s) {
+  if (pairs <= 0) return;
+  hipLaunchKernelGGL(k_square, grid_for(hc.n, hc.L + hc.K, pairs), dim3(TPB), 0, s, T, xq, xb, d);
+}
+void scale_round(const Tables& T, const Consts& hc, const uint64_t* d, uint64_t* c01, uint64_t* c2, int jobs,
                  uint32_t* fb, hipStream_t s) {
-  if (rows <= 0) return;
-  PEPSI_L_LAUNCH(k_scale_round, hc.L, grid_for(hc.n, rows * 3), dim3(TPB), s, T, d, out, fb);
+  if (jobs <= 0) return;
+  switch (hc.L) {
+#define PEPSI_SR(LL) case LL: hipLaunchKernelGGL((k_scale_round<LL, false>), grid_for(hc.n, jobs * 3), dim3(TPB), \
+                                                 0, s, T, d, nullptr, nullptr, nullptr, 0, 0, c01, c2, fb); break;
+    PEPSI_SR(1) PEPSI_SR(2) PEPSI_SR(3) PEPSI_SR(4) PEPSI_SR(5) PEPSI_SR(6) PEPSI_SR(7) PEPSI_SR(8)
+#undef PEPSI_SR
+  }
 }
-void relin_digits(const Tables& T, const Consts& hc, const uint64_t* c3, uint64_t* D, int rows,
+void scale_round_first(const Tables& T, const Consts& hc, const uint64_t* d, const uint64_t* xq,
+                       const uint64_t* xb, const uint64_t* alpha, int h, int pairs, uint64_t* c01, uint64_t* c2,
+                       uint32_t* fb, hipStream_t s) {
+  if (pairs <= 0 || h < 2) return;
+  const int J0 = h / 2;
+  switch (hc.L) {
+#define PEPSI_SR(LL) case LL: hipLaunchKernelGGL((k_scale_round<LL, true>), grid_for(hc.n, pairs * (2 * J0 + 1)), \
+                                                 dim3(TPB), 0, s, T, d, xq, xb, alpha, h, J0, c01, c2, fb); break;
+    PEPSI_SR(1) PEPSI_SR(2) PEPSI_SR(3) PEPSI_SR(4) PEPSI_SR(5) PEPSI_SR(6) PEPSI_SR(7) PEPSI_SR(8)
+#undef PEPSI_SR
+  }
+}
+void relin_digits(const Tables& T, const Consts& hc, const uint64_t* c2, uint64_t* D, int units,
                   hipStream_t s) {
-  if (rows <= 0) return;
-  PEPSI_L_LAUNCH(k_relin_digits, hc.L, grid_for(hc.n, rows), dim3(TPB), s, T, c3, D);
+  if (units <= 0) return;
+  PEPSI_L_LAUNCH(k_relin_digits, hc.L, grid_for(hc.n, units), dim3(TPB), s, T, c2, D);
 }
-void relin_inner(const Tables& T, const Consts& hc, const uint64_t* dhat, const uint64_t* Dhat,
-                 const uint64_t* rlk, long rlk_stride, const int* qslot, int jobs_per_pair, int nq, uint64_t* out,
-                 int rows, hipStream_t s) {
-  if (rows <= 0) return;
-  PEPSI_L_LAUNCH(k_relin_inner, hc.L, grid_for(hc.n, hc.L, rows), dim3(TPB), s, T, dhat, Dhat, rlk,
-                 rlk_stride, qslot, jobs_per_pair, nq, out);
+void relin_inner(const Tables& T, const Consts& hc, const uint64_t* c01h, const uint64_t* Dhat,
+                 const uint64_t* rlk, long rlk_stride, const int* qslot, int jobs_per_unit, int units_per_pair,
+                 int nq, uint64_t* out, int units, hipStream_t s) {
+  if (units <= 0) return;
+  PEPSI_L_LAUNCH(k_relin_inner, hc.L, grid_for(hc.n, hc.L, units), dim3(TPB), s, T, c01h, Dhat, rlk,
+                 rlk_stride, qslot, jobs_per_unit, units_per_pair, nq, out);
 }
 void accumulate(const Tables& T, const Consts& hc, const uint64_t* x, long xstride, int nb, int nq,
                 const int* qslot, uint64_t* acc, hipStream_t s) {

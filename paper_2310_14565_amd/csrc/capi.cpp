@@ -408,7 +408,7 @@ struct Engine {
   pepsi_params* P = nullptr;
   int TBq = 0, Qmax = 0, levels = 0;
   std::vector<int> jobs_at;            // tensor jobs per pair at each tree level
-  DevBuf chat, rlkhat, acc;            // per query: request and key in NTT form, running sum
+  DevBuf chat, rlkhat, acc, accD;      // per query: request and key in NTT form, running sums
   DevBuf sq, scoef, sb, sbh, alpha, e; // per pair: S over Q (NTT, coefficients), over B (both), ...
   DevBuf d, c01, c01h, c2, D, rcoef;   // per tensor job
   std::vector<DevBuf> rq, rb;          // per tree level outputs
@@ -418,7 +418,7 @@ struct Engine {
   EventTimer* timer = nullptr;
 
   ~Engine() {
-    for (DevBuf* b : {&chat, &rlkhat, &acc, &sq, &scoef, &sb, &sbh, &alpha, &e, &d, &c01, &c01h, &c2, &D,
+    for (DevBuf* b : {&chat, &rlkhat, &acc, &accD, &sq, &scoef, &sb, &sbh, &alpha, &e, &d, &c01, &c01h, &c2, &D,
                       &rcoef, &jobs, &gen_poly, &gen_p})
       b->release();
     for (auto& b : rq) b.release();
@@ -428,6 +428,7 @@ struct Engine {
   size_t cstride() const { return (size_t)P->H.ell * 2 * P->H.L * P->H.n; }
   size_t rstride() const { return (size_t)P->H.L * 2 * P->H.L * P->H.n; }
   size_t ctw() const { return (size_t)2 * P->H.L * P->H.n; }
+  size_t dtw() const { return (size_t)P->H.L * P->H.L * P->H.n; }
 
   int setup(pepsi_params* params, int tbq, int qmax, bool need_gen) {
     P = params;
@@ -441,11 +442,12 @@ struct Engine {
     if ((rc = rlkhat.ensure(Qmax * rstride() * 8))) return rc;
     if ((rc = acc.ensure(Qmax * ctw() * 8))) return rc;
     if ((rc = sq.ensure(PC * 2 * L * n * 8))) return rc;
-    if ((rc = e.ensure(PC * 2 * L * n * 8))) return rc;
+    if ((rc = e.ensure(n * 8))) return rc;
     jobs_at.clear();
     for (int cnt = H.h; cnt > 1; cnt = cnt / 2 + cnt % 2) jobs_at.push_back(cnt / 2);
     levels = (int)jobs_at.size();
     if (levels > 0) {
+      if ((rc = accD.ensure(Qmax * dtw() * 8))) return rc;
       const size_t J = PC * jobs_at[0];
       if ((rc = scoef.ensure(PC * 2 * L * n * 8))) return rc;
       if ((rc = sb.ensure(PC * 2 * K * n * 8))) return rc;
@@ -541,9 +543,9 @@ struct Engine {
   }
 
   // First tree level of npairs pairs: the h / 2 products (f_2u, f_2u+1) of each pair share the
-  // products of S (k_square), one inverse NTT of them and one relinearisation sum.
-  void first_level(int npairs, int nq, const int* qslot, uint64_t* out, uint64_t* ext_out, hipStream_t s,
-                   int key_slot) {
+  // products of S (k_square), one inverse NTT of them and one component 2 (so one
+  // relinearisation sum).  Leaves the rescaled products in c01 / c2.
+  void first_level(int npairs, hipStream_t s) {
     const HostParams& H = P->H;
     const int Pn = H.L + H.K;
     uint64_t* dd = d.as<uint64_t>();
@@ -551,19 +553,16 @@ struct Engine {
     ntt_inverse(P->T, H.logn, dd, dd, npairs * 3 * Pn, Pn, 0, s);
     scale_round_first(P->T, H.consts, dd, scoef.as<uint64_t>(), sb.as<uint64_t>(), alpha.as<uint64_t>(), H.h,
                       npairs, c01.as<uint64_t>(), c2.as<uint64_t>(), P->fallback.as<uint32_t>(), s);
-    relin_stage(npairs, H.h / 2, 1, nq, qslot, out, ext_out, s, key_slot);
   }
 
-  // A later tree level: njobs independent products (TensorJob operands), then relinearisation.
-  void later_level(const TensorJob* dev_jobs, int njobs, int jobs_per_pair, int nq, const int* qslot,
-                   uint64_t* out, uint64_t* ext_out, hipStream_t s, int key_slot) {
+  // A later tree level: njobs independent products (TensorJob operands) into c01 / c2.
+  void later_level(const TensorJob* dev_jobs, int njobs, hipStream_t s) {
     const HostParams& H = P->H;
     const int Pn = H.L + H.K;
     uint64_t* dd = d.as<uint64_t>();
     tensor(P->T, H.consts, dev_jobs, njobs, s);
     ntt_inverse(P->T, H.logn, dd, dd, njobs * 3 * Pn, Pn, 0, s);
     scale_round(P->T, H.consts, dd, c01.as<uint64_t>(), c2.as<uint64_t>(), njobs, P->fallback.as<uint32_t>(), s);
-    relin_stage(njobs, 1, jobs_per_pair, nq, qslot, out, ext_out, s, key_slot);
   }
 
   // A query enters slot `slot`: request and key to NTT form, running sum to zero.
@@ -574,6 +573,7 @@ struct Engine {
                 0, s);
     ntt_forward(P->T, H.logn, rlk, LOAD_U64, rlkhat.as<uint64_t>(slot * rstride()), STORE_U64, L * 2 * L, L, 0, s);
     (void)hipMemsetAsync(acc.as<uint64_t>(slot * ctw()), 0, ctw() * 8, s);
+    if (levels > 0) (void)hipMemsetAsync(accD.as<uint64_t>(slot * dtw()), 0, dtw() * 8, s);
   }
 
   void timed_select_sum(const uint64_t* phat, int nb, int nq, const int* qslot, int single_slot, uint64_t* Sx,
@@ -615,9 +615,10 @@ struct Engine {
       }
     }
     const int* acc_slot = nq == 1 ? nullptr : qslot;
-    uint64_t* acc_base = nq == 1 ? acc.as<uint64_t>((size_t)single_slot * ctw()) : acc.as<uint64_t>();
+    const size_t acc_q = nq == 1 ? (size_t)single_slot : 0;
+    uint64_t* acc_base = acc.as<uint64_t>(acc_q * ctw());
     if (levels == 0) {                                           // h = 1: e = S
-      accumulate(P->T, H.consts, Sq, (long)(2 * L * n), nb, nq, acc_slot, acc_base, s);
+      accumulate(P->T, H.consts, Sq, (long)(2 * L * n), nb, nq, 2 * (int)L, acc_slot, acc_base, (long)ctw(), s);
       return;
     }
     ntt_inverse(P->T, H.logn, Sq, scoef.as<uint64_t>(), npairs * 2 * (int)L, (int)L, 0, s);
@@ -630,17 +631,28 @@ struct Engine {
     const int* rslot = nq == 1 ? nullptr : qslot;
     const int key_slot = nq == 1 ? single_slot : 0;
     for (int lv = 0; lv < levels; ++lv) {
-      const bool last = lv + 1 == levels;
-      uint64_t* out = last ? e.as<uint64_t>() : rq[lv].as<uint64_t>();
-      uint64_t* ext_out = last ? nullptr : rb[lv].as<uint64_t>();
+      int units, jobs_per_unit, units_per_pair;
       if (lv == 0) {
-        first_level(npairs, nq, rslot, out, ext_out, s, key_slot);
+        first_level(npairs, s);
+        units = npairs, jobs_per_unit = H.h / 2, units_per_pair = 1;
       } else {
         const TensorJob* jl = jobs.as<TensorJob>() + job_off_na[nq][lv];
-        later_level(jl, npairs * jobs_at[lv], jobs_at[lv], nq, rslot, out, ext_out, s, key_slot);
+        units = npairs * jobs_at[lv], jobs_per_unit = 1, units_per_pair = jobs_at[lv];
+        later_level(jl, units, s);
+      }
+      if (lv + 1 < levels) {
+        relin_stage(units, jobs_per_unit, units_per_pair, nq, rslot, rq[lv].as<uint64_t>(), rb[lv].as<uint64_t>(),
+                    s, key_slot);
+      } else {
+        // The last level's relinearisation is linear in (c01, D), so both are summed over the
+        // batches (coefficient form, one entry per pair) and the key is applied once per query.
+        relin_digits(P->T, H.consts, c2.as<uint64_t>(), D.as<uint64_t>(), npairs, s);
+        accumulate(P->T, H.consts, c01.as<uint64_t>(), (long)(2 * L * n), nb, nq, 2 * (int)L, acc_slot, acc_base,
+                   (long)ctw(), s);
+        accumulate(P->T, H.consts, D.as<uint64_t>(), (long)(L * L * n), nb, nq, (int)(L * L), acc_slot,
+                   accD.as<uint64_t>(acc_q * dtw()), (long)dtw(), s);
       }
     }
-    accumulate(P->T, H.consts, e.as<uint64_t>(), (long)(2 * L * n), nb, nq, acc_slot, acc_base, s);
   }
 
   // out = coefficient form of query q's sum, optionally times (h!)^-1 plus Delta [encode(mask)]_t
@@ -648,6 +660,14 @@ struct Engine {
     const HostParams& H = P->H;
     const int L = H.L;
     uint64_t* a = acc.as<uint64_t>(q * ctw());
+    if (levels > 0) {
+      // a = NTT(sum of c01) + sum_i NTT(sum of D_i) (.) rlk_i
+      uint64_t* dq = accD.as<uint64_t>(q * dtw());
+      ntt_forward(P->T, H.logn, a, LOAD_U64, a, STORE_U64, 2 * L, L, 0, s);
+      ntt_forward(P->T, H.logn, dq, LOAD_U64, dq, STORE_U64, L * L, L, 0, s);
+      relin_inner(P->T, H.consts, a, dq, rlkhat.as<uint64_t>((size_t)q * rstride()), (long)rstride(), nullptr, 1, 1,
+                  1, a, 1, s);
+    }
     if (finalize) {
       uint64_t hf = 1;
       for (int r = 2; r <= H.h; ++r) hf = hf * r % PEPSI_T;

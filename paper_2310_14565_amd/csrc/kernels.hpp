@@ -76,9 +76,10 @@ void relin_digits(const Tables& T, const Consts& hc, const uint64_t* c2, uint64_
 void relin_inner(const Tables& T, const Consts& hc, const uint64_t* c01h, const uint64_t* Dhat,
                  const uint64_t* rlk, long rlk_stride, const int* qslot, int jobs_per_unit, int units_per_pair,
                  int nq, uint64_t* out, int units, hipStream_t s);
-// acc[q][2][L][N] += sum over b < nb of x[b * nq + q] (entries xstride words apart)
+// acc[slot(q)] += sum over b < nb of x[b * nq + q]; entries are `rows` rows of N residues (row r
+// modulo q_(r mod L)), xstride words apart in x and astride words apart in acc.
 void accumulate(const Tables& T, const Consts& hc, const uint64_t* x, long xstride, int nb, int nq,
-                const int* qslot, uint64_t* acc, hipStream_t s);
+                int rows, const int* qslot, uint64_t* acc, long astride, hipStream_t s);
 // select-and-sum: S[b][c][l][k] = sum_j C[j][c][l][k] * P[b][j][l][k] mod q_l.
 // C: NTT form [ell][2][L][N]; P: split-27 NTT form [nb][ell][L][N]; S rows of stride sstride.
 void select_sum(const Tables& T, const Consts& hc, const uint64_t* C, const uint64_t* P, int ell,

@@ -375,18 +375,19 @@ __global__ void __launch_bounds__(TPB) k_relin_inner(Tables T, const uint64_t* _
   }
 }
 
-// acc[q] += sum over batches b of x[b * nq + q]  (each entry [2][L][N], xstride words apart)
+// acc[slot(q)] += sum over batches b of x[b * nq + q]: entries of `rows` rows of N residues,
+// row r modulo q_(r mod L), xstride words apart in x and astride words apart in acc.
 __global__ void __launch_bounds__(TPB) k_accumulate(Tables T, const uint64_t* __restrict__ x,
                                                    long xstride, int nb, int nq, const int* __restrict__ qslot,
-                                                   uint64_t* __restrict__ acc) {
+                                                   uint64_t* __restrict__ acc, long astride) {
   const Consts& C = *T.c;
   const int N = C.n, L = C.L;
   const int k = blockIdx.x * TPB + threadIdx.x;
-  const int cl = blockIdx.y;                       // component * L + limb
+  const int cl = blockIdx.y;
   const int q = blockIdx.z;
   if (k >= N) return;
   const Prime& pr = C.prm[cl % L];
-  uint64_t* a = acc + (size_t)(qslot ? qslot[q] : q) * 2 * L * N;
+  uint64_t* a = acc + (size_t)(qslot ? qslot[q] : q) * astride;
   uint64_t s = a[(size_t)cl * N + k];
   int b = 0;
   while (b < nb) {
@@ -823,10 +824,10 @@ void relin_inner(const Tables& T, const Consts& hc, const uint64_t* c01h, const 
                  rlk_stride, qslot, jobs_per_unit, units_per_pair, nq, out);
 }
 void accumulate(const Tables& T, const Consts& hc, const uint64_t* x, long xstride, int nb, int nq,
-                const int* qslot, uint64_t* acc, hipStream_t s) {
-  if (nb <= 0 || nq <= 0) return;
-  hipLaunchKernelGGL(k_accumulate, grid_for(hc.n, 2 * hc.L, nq), dim3(TPB), 0, s, T, x, xstride, nb, nq, qslot,
-                     acc);
+                int rows, const int* qslot, uint64_t* acc, long astride, hipStream_t s) {
+  if (nb <= 0 || nq <= 0 || rows <= 0) return;
+  hipLaunchKernelGGL(k_accumulate, grid_for(hc.n, rows, nq), dim3(TPB), 0, s, T, x, xstride, nb, nq, qslot,
+                     acc, astride);
 }
 void select_sum(const Tables& T, const Consts& hc, const uint64_t* Cn, const uint64_t* P, int ell,
                 int nb, uint64_t* S, long sstride, hipStream_t s) {

@@ -545,11 +545,11 @@ struct Engine {
   // First tree level of npairs pairs: the h / 2 products (f_2u, f_2u+1) of each pair share the
   // products of S (k_square), one inverse NTT of them and one component 2 (so one
   // relinearisation sum).  Leaves the rescaled products in c01 / c2.
-  void first_level(int npairs, hipStream_t s) {
+  void first_level(const uint64_t* Sq, int npairs, hipStream_t s) {
     const HostParams& H = P->H;
     const int Pn = H.L + H.K;
     uint64_t* dd = d.as<uint64_t>();
-    square_products(P->T, H.consts, sq.as<uint64_t>(), sbh.as<uint64_t>(), dd, npairs, s);
+    square_products(P->T, H.consts, Sq, sbh.as<uint64_t>(), dd, npairs, s);
     ntt_inverse(P->T, H.logn, dd, dd, npairs * 3 * Pn, Pn, 0, s);
     scale_round_first(P->T, H.consts, dd, scoef.as<uint64_t>(), sb.as<uint64_t>(), alpha.as<uint64_t>(), H.h,
                       npairs, c01.as<uint64_t>(), c2.as<uint64_t>(), P->fallback.as<uint32_t>(), s);
@@ -595,31 +595,45 @@ struct Engine {
     }
   }
 
-  // One tile: batches [b0, b0 + nb) of nq active queries (slots qslot[0..nq), or single_slot when
-  // nq == 1); plaintexts from the cache (phat) or generated.
-  void run_tile(const uint16_t* cw, int b0, int nb, int nq, const int* qslot, int single_slot,
-                const uint64_t* phat, hipStream_t s) {
+  // Select-and-sum of one tile: batches [b0, b0 + nb) of nq active queries (slots qslot[0..nq), or
+  // single_slot when nq == 1) into Sout [nb * nq][2][L][N]; plaintexts from the cache (phat) or
+  // generated.
+  void produce_s(const uint16_t* cw, int b0, int nb, int nq, const int* qslot, int single_slot,
+                 const uint64_t* phat, uint64_t* Sout, hipStream_t s) {
+    const HostParams& H = P->H;
+    const size_t n = H.n, L = H.L;
+    if (phat) {
+      timed_select_sum(phat, nb, nq, qslot, single_slot, Sout, s);
+      return;
+    }
+    for (int g0 = 0; g0 < nb; g0 += GB) {
+      const int g = std::min(GB, nb - g0);
+      encode_server_planes(P->T, H.logn, cw, H.h, H.ell, b0 + g0, g, gen_poly.as<uint32_t>(), s);
+      ntt_forward(P->T, H.logn, gen_poly.p, LOAD_LIFT_T, gen_p.p, STORE_SPLIT27, g * H.ell * (int)L, (int)L, 0,
+                  s);
+      timed_select_sum(gen_p.as<uint64_t>(), g, nq, qslot, single_slot, Sout + (size_t)g0 * nq * 2 * L * n, s);
+    }
+  }
+
+  // The product tree of one tile from its select-and-sum outputs Sin, and the accumulation.
+  void consume_s(uint64_t* Sin, int nb, int nq, const int* qslot, int single_slot, hipStream_t s) {
     const HostParams& H = P->H;
     const size_t n = H.n, L = H.L, K = H.K;
-    uint64_t* Sq = sq.as<uint64_t>();
     const int npairs = nb * nq;
-    if (phat) {
-      timed_select_sum(phat, nb, nq, qslot, single_slot, Sq, s);
-    } else {
-      for (int g0 = 0; g0 < nb; g0 += GB) {
-        const int g = std::min(GB, nb - g0);
-        encode_server_planes(P->T, H.logn, cw, H.h, H.ell, b0 + g0, g, gen_poly.as<uint32_t>(), s);
-        ntt_forward(P->T, H.logn, gen_poly.p, LOAD_LIFT_T, gen_p.p, STORE_SPLIT27, g * H.ell * (int)L,
-                    (int)L, 0, s);
-        timed_select_sum(gen_p.as<uint64_t>(), g, nq, qslot, single_slot, Sq + (size_t)g0 * nq * 2 * L * n, s);
-      }
-    }
     const int* acc_slot = nq == 1 ? nullptr : qslot;
     const size_t acc_q = nq == 1 ? (size_t)single_slot : 0;
     uint64_t* acc_base = acc.as<uint64_t>(acc_q * ctw());
     if (levels == 0) {                                           // h = 1: e = S
-      accumulate(P->T, H.consts, Sq, (long)(2 * L * n), nb, nq, 2 * (int)L, acc_slot, acc_base, (long)ctw(), s);
+      accumulate(P->T, H.consts, Sin, (long)(2 * L * n), nb, nq, 2 * (int)L, acc_slot, acc_base, (long)ctw(), s);
       return;
+    }
+    uint64_t* Sq = sq.as<uint64_t>();
+    if (Sin != Sq) {
+      if (H.h % 2) {            // a raw factor reaches a later level: its tensor jobs read sq
+        (void)hipMemcpyAsync(Sq, Sin, (size_t)npairs * 2 * L * n * 8, hipMemcpyDeviceToDevice, s);
+      } else {
+        Sq = Sin;
+      }
     }
     ntt_inverse(P->T, H.logn, Sq, scoef.as<uint64_t>(), npairs * 2 * (int)L, (int)L, 0, s);
     ext_q_to_b(P->T, H.consts, scoef.as<uint64_t>(), sb.as<uint64_t>(), (long)(K * n), npairs * 2,
@@ -633,7 +647,7 @@ struct Engine {
     for (int lv = 0; lv < levels; ++lv) {
       int units, jobs_per_unit, units_per_pair;
       if (lv == 0) {
-        first_level(npairs, s);
+        first_level(Sq, npairs, s);
         units = npairs, jobs_per_unit = H.h / 2, units_per_pair = 1;
       } else {
         const TensorJob* jl = jobs.as<TensorJob>() + job_off_na[nq][lv];
@@ -653,6 +667,13 @@ struct Engine {
                    accD.as<uint64_t>(acc_q * dtw()), (long)dtw(), s);
       }
     }
+  }
+
+  // One tile on one stream.
+  void run_tile(const uint16_t* cw, int b0, int nb, int nq, const int* qslot, int single_slot,
+                const uint64_t* phat, hipStream_t s) {
+    produce_s(cw, b0, nb, nq, qslot, single_slot, phat, sq.as<uint64_t>(), s);
+    consume_s(sq.as<uint64_t>(), nb, nq, qslot, single_slot, s);
   }
 
   // out = coefficient form of query q's sum, optionally times (h!)^-1 plus Delta [encode(mask)]_t
@@ -690,7 +711,9 @@ struct Engine {
     return (cache && b0 + (uint32_t)nb <= cached) ? cache + per * b0 : nullptr;
   }
 
-  // The whole computation for nq queries in slots 0..nq-1 over batches [begin, stop).
+  // The whole computation for nq queries in slots 0..nq-1 over batches [begin, stop).  (Running
+  // the HBM-bound select-and-sum of the next tile on a second stream beside the product tree
+  // was measured slower: the select-and-sum needs nearly full occupancy to cover HBM latency.)
   int run(const uint16_t* cw, const uint64_t* cache, uint32_t cached, uint32_t begin, uint32_t stop, int nq,
           const uint64_t* const* cts, const uint64_t* const* rlk, hipStream_t s) {
     for (int q = 0; q < nq; ++q) admit(q, cts[q], rlk[q], s);

@@ -413,16 +413,24 @@ __device__ __forceinline__ uint64_t fold3(uint64_t lo, uint64_t mid, uint64_t hi
   const u128 v = (u128)lo + ((u128)mid << 27) + ((u128)hi << 54);
   return reduce128((uint64_t)v, (uint64_t)(v >> 64), pr);
 }
+
+// Block numbering: a slice (TPB positions of one limb) has zg = ceil(nb / IB) batch groups that
+// read the same client values.  Workgroups go to the 8 XCDs round-robin, so block b runs on XCD
+// b & 7; the zg groups of a slice get consecutive numbers on one XCD, are resident together and
+// share the client values through that XCD's L2.
 __global__ void __launch_bounds__(TPB) k_select_sum(Tables T, const uint64_t* __restrict__ Cn,
                                                    const uint64_t* __restrict__ Pc, int ell, int nb,
-                                                   uint64_t* __restrict__ S, long sstride) {
+                                                   uint64_t* __restrict__ S, long sstride, int slices, int zg) {
   const Consts& C = *T.c;
   const int N = C.n, L = C.L;
-  const int k = blockIdx.x * TPB + threadIdx.x;
-  const int l = blockIdx.y;
-  const int b0 = blockIdx.z * IB;
+  const int bid = blockIdx.x, local = bid >> 3;
+  const int slice = (local / zg) * 8 + (bid & 7);
+  if (slice >= slices) return;
+  const int kchunks = N / TPB;
+  const int k = (slice % kchunks) * TPB + threadIdx.x;
+  const int l = slice / kchunks;
+  const int b0 = (local % zg) * IB;
   const int nbl = min(IB, nb - b0);
-  if (k >= N) return;
   const Prime& pr = C.prm[l];
   constexpr uint64_t M27 = (1ull << 27) - 1;
   uint64_t lo[2][IB], mid[2][IB], hi[2][IB];
@@ -832,8 +840,9 @@ void accumulate(const Tables& T, const Consts& hc, const uint64_t* x, long xstri
 void select_sum(const Tables& T, const Consts& hc, const uint64_t* Cn, const uint64_t* P, int ell,
                 int nb, uint64_t* S, long sstride, hipStream_t s) {
   if (nb <= 0) return;
-  hipLaunchKernelGGL(k_select_sum, grid_for(hc.n, hc.L, (nb + IB - 1) / IB), dim3(TPB), 0, s, T, Cn,
-                     P, ell, nb, S, sstride);
+  const int slices = hc.n / TPB * hc.L, zg = (nb + IB - 1) / IB;
+  hipLaunchKernelGGL(k_select_sum, dim3((slices + 7) / 8 * 8 * zg), dim3(TPB), 0, s, T, Cn, P, ell, nb, S,
+                     sstride, slices, zg);
 }
 void select_sum_multi(const Tables& T, const Consts& hc, const uint64_t* Cq, long cq_stride, const int* qslot,
                       int nq, const uint64_t* P, int ell, int nb, uint64_t* S, hipStream_t s) {

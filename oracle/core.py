@@ -56,7 +56,7 @@ def lib():
             "or_relin": (None, [vp, u64p, u64p, u64p]),
             "or_select_sum": (None, [vp, i, i, u64p, u16p, u64p]),
             "or_server_batch": (None, [vp, i, i, u64p, u16p, u64p, u64p]),
-            "or_server_eval": (None, [vp, i, i, i, i, u64p, u16p, u64p, vp, i, u64p]),
+            "or_server_eval": (None, [vp, i, i, i, i, u64p, u16p, u64p, vp, vp, i, u64p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -196,7 +196,9 @@ class Context:
         return out
 
     def server_eval(self, cts, cw_table, rlk, h: int, mask=None, finalize=True,
-                    begin: int = 0, end: int | None = None):
+                    begin: int = 0, end: int | None = None, vals=None):
+        """Alg. 2 / 5 over server batches [begin, end); vals [mu][N] (values < t, one per table
+        entry) multiplies each batch's equality ciphertext by its server values (Alg. 4 / 5)."""
         out = self.zeros_ct()
         cts = _c(cts, np.uint64)
         cw_table = _c(cw_table, np.uint16)
@@ -204,9 +206,13 @@ class Context:
         m = None
         if mask is not None:
             m = _c(mask, np.uint32)
+        v = None
+        if vals is not None:
+            v = _c(vals, np.uint32)
+            assert v.shape == cw_table.shape[:2]
         lib().or_server_eval(self._h, cts.shape[0], h, begin, end, cts, cw_table,
                              _c(rlk, np.uint64), None if m is None else m.ctypes.data,
-                             1 if finalize else 0, out)
+                             None if v is None else v.ctypes.data, 1 if finalize else 0, out)
         return out
 
     # integer views used by the pins

@@ -101,10 +101,11 @@ void or_server_batch(const or_ctx* c, int ell, int h, const uint64_t* cts,
 void or_select_sum(const or_ctx* c, int ell, int h, const uint64_t* cts,
                    const uint16_t* cw, uint64_t* out);
 /* The full server computation over batches [i0, i1) of a [mu][N][h] table:
- *   acc = sum e_{i'};  out = [(h!)^-1]_t * acc;  if mask: c0 += Delta*[encode(mask)]_t
+ *   acc = sum e_{i'}  (with vals [mu][N]: sum of encode(vals[i']) * e_{i'}, Alg. 4/5);
+ *   out = [(h!)^-1]_t * acc;  if mask: c0 += Delta*[encode(mask)]_t
  * (finalize != 0 applies the factor and the mask; otherwise out = acc). */
 void or_server_eval(const or_ctx* c, int ell, int h, int mu_begin, int mu_end,
                     const uint64_t* cts, const uint16_t* cw_table,
-                    const uint64_t* rlk, const uint32_t* mask, int finalize,
-                    uint64_t* out);
+                    const uint64_t* rlk, const uint32_t* mask, const uint32_t* vals,
+                    int finalize, uint64_t* out);
 #endif

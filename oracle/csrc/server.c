@@ -3,8 +3,10 @@
  * PSI-cardinality.
  *   Alg. 1 (Arith-CW-Eq):  h' = sum_j x_j y_j;  e = (1/h!) prod_{r in [h]} (h' - r)
  *   Alg. 2 (Intersect):    ct_ind = sum over server batches i' of ct_eq[i']
- *   Alg. 5 (PSI-Sum, server values = 1, i.e. PSI-Cardinality): add a mask r
- *                          with sum_k r_k = 0 to the sum.
+ *   Alg. 5 (PSI-Sum):      sum over i' of val_s[i'] * ct_eq[i'] (server values as
+ *                          batch-encoded plaintexts; all ones = PSI-Cardinality), plus a
+ *                          mask r with sum_k r_k = 0.
+ *   Alg. 4 (labelled PSI): the same sum of val_s[i'] * ct_eq[i'], no mask.
  * With the client bits encrypted slot-wise (one ciphertext per codeword bit j)
  * and the server bits as plaintexts, h' for one server batch is the sum over
  * j of the plaintext products ct_j (*) pt_s[i'][j].  The constant (1/h!) is
@@ -117,8 +119,8 @@ void or_server_batch(const or_ctx* c, int ell, int h, const uint64_t* cts,
 
 void or_server_eval(const or_ctx* c, int ell, int h, int mu_begin, int mu_end,
                     const uint64_t* cts, const uint16_t* cw_table,
-                    const uint64_t* rlk, const uint32_t* mask, int finalize,
-                    uint64_t* out) {
+                    const uint64_t* rlk, const uint32_t* mask, const uint32_t* vals,
+                    int finalize, uint64_t* out) {
   int n = c->n, L = c->L;
   uint64_t t = c->t;
   size_t csz = (size_t)2 * L * n;
@@ -130,10 +132,18 @@ void or_server_eval(const or_ctx* c, int ell, int h, int mu_begin, int mu_end,
     uint64_t* S = (uint64_t*)malloc(sizeof(uint64_t) * csz);
     uint64_t* e = (uint64_t*)malloc(sizeof(uint64_t) * csz);
     uint64_t* part = (uint64_t*)calloc(csz, sizeof(uint64_t));
+    uint32_t* vp = vals ? (uint32_t*)malloc(sizeof(uint32_t) * n) : NULL;
 #pragma omp for schedule(dynamic, 1)
     for (int ip = mu_begin; ip < mu_end; ip++) {
       select_sum_eval(c, ell, h, E, cw_table + (size_t)ip * n * h, S);
       equality_product(c, h, S, rlk, e);
+      if (vals) {
+        /* Alg. 4 / Alg. 5: val_s[i'] * ct_eq[i'], the server values of batch i' as a
+         * batch-encoded plaintext (slot k = value of the item in bin k) */
+        or_encode(c, vals + (size_t)ip * n, vp);
+        or_mul_plain(c, e, vp, S);
+        memcpy(e, S, sizeof(uint64_t) * csz);
+      }
       for (int comp = 0; comp < 2; comp++)
         for (int l = 0; l < L; l++)
           for (int k = 0; k < n; k++) {
@@ -148,7 +158,7 @@ void or_server_eval(const or_ctx* c, int ell, int h, int mu_begin, int mu_end,
           size_t at = ((size_t)comp * L + l) * n + k;
           out[at] = or_addmod(out[at], part[at], c->q[l]);
         }
-    free(S); free(e); free(part);
+    free(S); free(e); free(part); free(vp);
   }
   free(E);
   if (finalize) {

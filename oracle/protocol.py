@@ -5,8 +5,10 @@ positions -> one slot vector per codeword bit j -> encode -> encrypt.
 Server preparation (Alg. 6 ServerDataPrep): simple hashing -> CW positions,
 kept as a [mu][b][h] table of positions (the plaintexts pt_s[i'][j] are the
 bit planes of this table).
-Extraction (Alg. 3 and Alg. 5 ExtractPSISum): decrypt, read the indicator or
-sum the slots mod t.
+Server values (Alg. 4 labelled PSI, Alg. 5 PSI-Sum): val_s[i'] is the batch-encoded
+plaintext whose slot k is the value of the server element at entry (i', k) of T_s.
+Extraction (Alg. 3, Alg. 4 ExtractLabels and Alg. 5 ExtractPSISum): decrypt, read the
+indicator or the labels, or sum the slots mod t.
 """
 from __future__ import annotations
 
@@ -65,3 +67,39 @@ def plaintext_membership(client_table, client_valid, server_table, server_valid)
 
 def extract_cardinality(slots, t: int = P.T_PLAIN) -> int:
     return int(np.asarray(slots, dtype=np.int64).sum() % t)
+
+
+def extract_sum(slots, t: int = P.T_PLAIN) -> int:
+    """Alg. 5 ExtractPSISum: the sum of all slots mod t."""
+    return int(np.asarray(slots, dtype=np.int64).sum() % t)
+
+
+def server_values(cfg: Config, items, values):
+    """val_s as a [mu][b] table: entry (i', k) = the value of the server element at (i', k)
+    of T_s (Alg. 6 layout), 0 for dummies.  values[e] belongs to items[e]; values < t."""
+    table, valid, _ = hashing.simple_table(items, cfg.n, cfg.mu, cfg.hash_seed, cfg.n_hash)
+    items = np.asarray(items, dtype=np.uint64)
+    values = np.asarray(values, dtype=np.uint64)
+    assert values.shape == items.shape and (values < P.T_PLAIN).all()
+    order = np.argsort(items)
+    sorted_items = items[order]
+    sel = valid.astype(bool)
+    idx = np.searchsorted(sorted_items, table[sel].astype(np.uint64))
+    out = np.zeros(table.shape, dtype=np.uint32)
+    out[sel] = values[order][idx].astype(np.uint32)
+    return out
+
+
+def plaintext_labels(client_table, client_valid, server_table, server_valid, vals_table):
+    """Alg. 4 in the clear: slot k = the value of the server element equal to the client's
+    bin-k element (at most one, the sets have distinct elements), 0 if there is none."""
+    hit = (server_table == client_table[None, :]) & server_valid.astype(bool) & \
+        client_valid.astype(bool)[None, :]
+    return (vals_table.astype(np.int64) * hit).sum(axis=0).astype(np.uint32)
+
+
+def plaintext_sum(client_items, server_items, values, t: int = P.T_PLAIN) -> int:
+    """Alg. 5 in the clear: the sum of the values of the common elements, mod t."""
+    server_items = np.asarray(server_items, dtype=np.uint64)
+    common = np.isin(server_items, np.asarray(client_items, dtype=np.uint64))
+    return int(np.asarray(values, dtype=np.int64)[common].sum() % t)

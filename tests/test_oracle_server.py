@@ -1,4 +1,4 @@
-"""Pins of the oracle's server computation (Alg. 1, Alg. 2, Alg. 5)."""
+"""Pins of the oracle's server computation (Alg. 1, Alg. 2, Alg. 4, Alg. 5)."""
 import itertools
 import math
 
@@ -137,6 +137,35 @@ def test_small_psi_cardinality_and_indicator(seed):
     assert PR.extract_cardinality(slots) == len(set(client.tolist()) & set(server.tolist())) == 7
     ind = ctx.decrypt_slots(sk, ctx.server_eval(cts, spos, rlk, cfg.h))
     assert (ind == PR.plaintext_membership(ctab, cval, stab, sval)).all()
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_small_psi_sum_and_labels(seed):
+    """Alg. 5 (PSI-Sum, masked) and Alg. 4 (labelled PSI) against their plaintext meaning, and
+    unit values reproduce the PSI-cardinality ciphertext (Sec. 5.3)."""
+    cfg = PR.Config(n=64, L=3, h=2, item_bits=8, mu=0)
+    server = W.server_items(60, 8, seed)
+    cfg.mu = P.server_bin_bound(60, 64)
+    client = W.client_items(20, server, 9, 8, seed + 100)
+    values = W.item_values(60, 1, 5000, seed + 500)
+    ctx = Context.standard(cfg.n, cfg.L)
+    sk, rlk = small_keys(ctx, seed + 200)
+    ctab, cval, _, planes = PR.client_prepare(cfg, client)
+    stab, sval, spos, _ = PR.server_prepare(cfg, server)
+    vtab = PR.server_values(cfg, server, values)
+    assert (vtab[sval == 0] == 0).all() and (vtab[sval == 1] > 0).all()
+    cts = encrypt_planes(ctx, sk, planes, seed + 300)
+    mask = W.zero_sum_mask(cfg.n, ctx.t, seed + 400)
+    total = ctx.server_eval(cts, spos, rlk, cfg.h, mask=mask, vals=vtab)
+    want = PR.plaintext_sum(client, server, values)
+    assert want != 0
+    assert PR.extract_sum(ctx.decrypt_slots(sk, total)) == want
+    labels = ctx.decrypt_slots(sk, ctx.server_eval(cts, spos, rlk, cfg.h, vals=vtab))
+    assert (labels == PR.plaintext_labels(ctab, cval, stab, sval, vtab)).all()
+    assert np.count_nonzero(labels) == 9
+    ones = np.ones_like(vtab)
+    assert (ctx.server_eval(cts, spos, rlk, cfg.h, mask=mask, vals=ones) ==
+            ctx.server_eval(cts, spos, rlk, cfg.h, mask=mask)).all()
 
 
 @pytest.mark.slow

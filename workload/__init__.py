@@ -92,3 +92,8 @@ def zero_sum_mask(n: int, t: int, seed: int) -> np.ndarray:
 def planes_random(count: int, n: int, seed: int, tag: str = "planes") -> np.ndarray:
     """Random 0/1 slot vectors (used for kernel-level checks)."""
     return rng(seed, tag).integers(0, 2, size=(count, n), dtype=np.uint32)
+
+
+def item_values(n: int, lo: int, hi: int, seed: int) -> np.ndarray:
+    """Server values (PSI-Sum) or labels (labelled PSI): n uniform integers in [lo, hi)."""
+    return rng(seed, "item-values").integers(lo, hi, size=n, dtype=np.int64).astype(np.uint32)

@@ -130,7 +130,7 @@ def make_query(params, server_items, cfg, m, planted, seed):
     rlk = torch.empty((L, 2, L, n), dtype=torch.int64, device="cuda")
     params.keygen_relin(sk, ka, ke, rlk)
     mask = dev(W.zero_sum_mask(n, 65537, seed + 2))
-    return dict(sk=sk, cts=cts, rlk=rlk, mask=mask, planted=planted, m=m)
+    return dict(sk=sk, cts=cts, rlk=rlk, mask=mask, planted=planted, m=m, client=client)
 
 
 def serving_leg(pk, requests, pool, slots, load, seed):

@@ -185,13 +185,28 @@ typedef struct {
  * PEPSI_E_NOMEM. */
 int pepsi_server_create(const pepsi_params* params, const uint32_t* items, uint64_t n,
                         uint32_t flags, void* stream, pepsi_server** out);
+/* Server preparation with server values (Alg. 4 labelled PSI, Alg. 5 PSI-Sum): as
+ * pepsi_server_create, where values[e] < t belongs to items[e] (host arrays of n).  The
+ * value plaintext val_s[i'] of every batch that holds items (slot k = the value of the item
+ * at entry (i', k) of the table, 0 for dummies) is batch-encoded and transformed into NTT
+ * form here, [max_load][L][N] uint64 in HBM owned by the handle.  Every evaluation of the
+ * handle (single, range, batched, served) then multiplies each batch's equality ciphertext
+ * by val_s[i'] before the sum: with a mask the output is PSI-Sum (the decrypted slots sum
+ * to the sum of the values of the common items, mod t); without one it is labelled PSI
+ * (decrypted slot k = the value of the matched item in bin k, 0 if none, so labels should
+ * be non-zero).  values == NULL is pepsi_server_create.  Synchronises the stream.  Errors:
+ * as pepsi_server_create; PEPSI_E_RANGE for a value >= t. */
+int pepsi_server_create_with_values(const pepsi_params* params, const uint32_t* items,
+                                    const uint32_t* values, uint64_t n, uint32_t flags, void* stream,
+                                    pepsi_server** out);
 int pepsi_server_get_info(const pepsi_server* server, pepsi_server_info* out);
 /* Copy of the codeword-position table uint16 [mu][N][h] to host memory. */
 int pepsi_server_codewords(const pepsi_server* server, uint16_t* out);
 void pepsi_server_destroy(pepsi_server* server);
 
 /* Server computation, PSI-Cardinality (Alg. 5 with unit server values) or the
- * indicator of Alg. 2 when d_mask is NULL:
+ * indicator of Alg. 2 when d_mask is NULL (with server values, PSI-Sum or labelled PSI:
+ * each e below is first multiplied by val_s[i'], see pepsi_server_create_with_values):
  *   for every server batch i':  S = sum_j ct_j (*) pt_s[i'][j]          (Alg. 1, h')
  *                               e = prod_{r in [h]} (S + Delta [-r]_t)  (balanced tree,
  *                                   relinearised after every product)

@@ -47,9 +47,25 @@ int fail(int code, const char* fmt, ...) {
 inline hipStream_t S(void* s) { return static_cast<hipStream_t>(s); }
 
 // Device buffer that only grows; growing waits for the device first.
+// Device buffer owned by value: grows on demand, freed with its owner.
 struct DevBuf {
   void* p = nullptr;
   size_t cap = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), cap(o.cap) { o.p = nullptr; o.cap = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p;
+      cap = o.cap;
+      o.p = nullptr;
+      o.cap = 0;
+    }
+    return *this;
+  }
+  ~DevBuf() { release(); }
   int ensure(size_t bytes) {
     if (bytes <= cap) return 0;
     if (p) {
@@ -416,6 +432,7 @@ struct Engine {
   DevBuf gen_poly, gen_p;              // on-the-fly plaintext generation
   int GB = 0;
   EventTimer* timer = nullptr;
+  const uint64_t* vhat = nullptr;      // server-value plaintexts [max_load][L][N] (NTT form) or null
 
   ~Engine() {
     for (DevBuf* b : {&chat, &rlkhat, &acc, &accD, &sq, &scoef, &sb, &sbh, &alpha, &e, &d, &c01, &c01h, &c2, &D,
@@ -430,7 +447,8 @@ struct Engine {
   size_t ctw() const { return (size_t)2 * P->H.L * P->H.n; }
   size_t dtw() const { return (size_t)P->H.L * P->H.L * P->H.n; }
 
-  int setup(pepsi_params* params, int tbq, int qmax, bool need_gen) {
+  int setup(pepsi_params* params, int tbq, int qmax, bool need_gen, const uint64_t* values_hat = nullptr) {
+    vhat = values_hat;
     P = params;
     const HostParams& H = P->H;
     const size_t n = H.n, L = H.L, K = H.K, Pn = L + K;
@@ -442,7 +460,8 @@ struct Engine {
     if ((rc = rlkhat.ensure(Qmax * rstride() * 8))) return rc;
     if ((rc = acc.ensure(Qmax * ctw() * 8))) return rc;
     if ((rc = sq.ensure(PC * 2 * L * n * 8))) return rc;
-    if ((rc = e.ensure(n * 8))) return rc;
+    // e: the mask's encoding in finish, and with server values each pair's equality ciphertext
+    if ((rc = e.ensure(vhat ? PC * 2 * L * n * 8 : n * 8))) return rc;
     jobs_at.clear();
     for (int cnt = H.h; cnt > 1; cnt = cnt / 2 + cnt % 2) jobs_at.push_back(cnt / 2);
     levels = (int)jobs_at.size();
@@ -616,15 +635,19 @@ struct Engine {
   }
 
   // The product tree of one tile from its select-and-sum outputs Sin, and the accumulation.
-  void consume_s(uint64_t* Sin, int nb, int nq, const int* qslot, int single_slot, hipStream_t s) {
+  void consume_s(uint64_t* Sin, int b0, int nb, int nq, const int* qslot, int single_slot, hipStream_t s) {
     const HostParams& H = P->H;
     const size_t n = H.n, L = H.L, K = H.K;
     const int npairs = nb * nq;
     const int* acc_slot = nq == 1 ? nullptr : qslot;
     const size_t acc_q = nq == 1 ? (size_t)single_slot : 0;
     uint64_t* acc_base = acc.as<uint64_t>(acc_q * ctw());
+    const uint64_t* vtile = vhat ? vhat + (size_t)b0 * L * n : nullptr;
     if (levels == 0) {                                           // h = 1: e = S
-      accumulate(P->T, H.consts, Sin, (long)(2 * L * n), nb, nq, 2 * (int)L, acc_slot, acc_base, (long)ctw(), s);
+      if (vtile)
+        value_accumulate(P->T, H.consts, Sin, (long)(2 * L * n), vtile, nb, nq, acc_slot, acc_base, (long)ctw(), s);
+      else
+        accumulate(P->T, H.consts, Sin, (long)(2 * L * n), nb, nq, 2 * (int)L, acc_slot, acc_base, (long)ctw(), s);
       return;
     }
     uint64_t* Sq = sq.as<uint64_t>();
@@ -657,6 +680,12 @@ struct Engine {
       if (lv + 1 < levels) {
         relin_stage(units, jobs_per_unit, units_per_pair, nq, rslot, rq[lv].as<uint64_t>(), rb[lv].as<uint64_t>(),
                     s, key_slot);
+      } else if (vtile) {
+        // server values (Alg. 4 / 5): each pair's equality ciphertext is needed on its own,
+        // relinearised, to be multiplied by its batch's value plaintext
+        relin_stage(units, jobs_per_unit, units_per_pair, nq, rslot, e.as<uint64_t>(), nullptr, s, key_slot);
+        value_accumulate(P->T, H.consts, e.as<uint64_t>(), (long)(2 * L * n), vtile, nb, nq, acc_slot, acc_base,
+                         (long)ctw(), s);
       } else {
         // The last level's relinearisation is linear in (c01, D), so both are summed over the
         // batches (coefficient form, one entry per pair) and the key is applied once per query.
@@ -673,7 +702,7 @@ struct Engine {
   void run_tile(const uint16_t* cw, int b0, int nb, int nq, const int* qslot, int single_slot,
                 const uint64_t* phat, hipStream_t s) {
     produce_s(cw, b0, nb, nq, qslot, single_slot, phat, sq.as<uint64_t>(), s);
-    consume_s(sq.as<uint64_t>(), nb, nq, qslot, single_slot, s);
+    consume_s(sq.as<uint64_t>(), b0, nb, nq, qslot, single_slot, s);
   }
 
   // out = coefficient form of query q's sum, optionally times (h!)^-1 plus Delta [encode(mask)]_t
@@ -681,7 +710,7 @@ struct Engine {
     const HostParams& H = P->H;
     const int L = H.L;
     uint64_t* a = acc.as<uint64_t>(q * ctw());
-    if (levels > 0) {
+    if (levels > 0 && !vhat) {
       // a = NTT(sum of c01) + sum_i NTT(sum of D_i) (.) rlk_i
       uint64_t* dq = accD.as<uint64_t>(q * dtw());
       ntt_forward(P->T, H.logn, a, LOAD_U64, a, STORE_U64, 2 * L, L, 0, s);
@@ -741,10 +770,19 @@ struct pepsi_server {
   bool ready = false;
   Engine beng;           // many queries per launch (batched path)
   int bqmax = 0;
+  DevBuf vhat;           // server values (Alg. 4 / 5): [max_load][L][N] plaintexts, NTT form
+  bool valued = false;
+  const uint64_t* values_hat() const { return valued ? vhat.as<uint64_t>() : nullptr; }
 };
 
 extern "C" int pepsi_server_create(const pepsi_params* Pc, const uint32_t* items, uint64_t n,
                                    uint32_t flags, void* stream, pepsi_server** out) {
+  return pepsi_server_create_with_values(Pc, items, nullptr, n, flags, stream, out);
+}
+
+extern "C" int pepsi_server_create_with_values(const pepsi_params* Pc, const uint32_t* items,
+                                               const uint32_t* values, uint64_t n, uint32_t flags, void* stream,
+                                               pepsi_server** out) {
   pepsi_params* P = const_cast<pepsi_params*>(Pc);
   if (!P || (!items && n) || !out) return fail(PEPSI_E_ARG, "null argument");
   *out = nullptr;
@@ -755,12 +793,14 @@ extern "C" int pepsi_server_create(const pepsi_params* Pc, const uint32_t* items
     for (uint64_t i = 0; i < n; ++i) {
       if (H.item_bits < 32 && (items[i] >> H.item_bits)) return fail(PEPSI_E_RANGE, "server item out of range");
       if (!seen.insert(items[i]).second) return fail(PEPSI_E_RANGE, "duplicate server item");
+      if (values && values[i] >= PEPSI_T) return fail(PEPSI_E_RANGE, "server value not below t");
     }
   }
-  std::vector<uint32_t> table;
+  std::vector<uint32_t> table, index;
   std::vector<uint8_t> valid;
   uint32_t max_load = 0;
-  if (simple_hash(items, n, H.n, H.hash_seed, H.n_hash, H.mu, &table, &valid, &max_load))
+  if (simple_hash(items, n, H.n, H.hash_seed, H.n_hash, H.mu, &table, &valid, &max_load,
+                  values ? &index : nullptr))
     return fail(PEPSI_E_BIN_OVERFLOW, "a server bin exceeds mu = %d", H.mu);
   std::vector<uint16_t> cw((size_t)H.mu * H.n * H.h, 0xFFFF);
   CwEncoder enc(H.ell, H.h);
@@ -774,6 +814,28 @@ extern "C" int pepsi_server_create(const pepsi_params* Pc, const uint32_t* items
   if (hipMemcpy(sv->cw.p, cw.data(), cw.size() * 2, hipMemcpyHostToDevice) != hipSuccess) {
     delete sv;
     return fail(PEPSI_E_DEVICE, "codeword upload failed");
+  }
+  if (values && max_load > 0) {
+    // val_s[i'] for the batches that hold real items: slot k = value of the item at (i', k)
+    // (0 for dummies), batch-encoded, lifted and transformed once into NTT form
+    std::vector<uint32_t> vt((size_t)max_load * H.n, 0);
+    for (size_t i = 0; i < vt.size(); ++i)
+      if (valid[i]) vt[i] = values[index[i]];
+    DevBuf raw, poly;
+    if ((rc = raw.ensure(vt.size() * 4)) || (rc = poly.ensure(vt.size() * 4)) ||
+        (rc = sv->vhat.ensure(vt.size() * H.L * 8))) {
+      delete sv;
+      return rc;
+    }
+    hipStream_t s = S(stream);
+    if (hipMemcpyAsync(raw.p, vt.data(), vt.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess) {
+      delete sv;
+      return fail(PEPSI_E_DEVICE, "value upload failed");
+    }
+    encode_slots(P->T, H.logn, raw.as<uint32_t>(), poly.as<uint32_t>(), (int)max_load, s);
+    ntt_forward(P->T, H.logn, poly.p, LOAD_LIFT_T, sv->vhat.p, STORE_U64, (int)max_load * H.L, H.L, 0, s);
+    if (hipStreamSynchronize(s) != hipSuccess) { delete sv; return fail(PEPSI_E_DEVICE, "value encoding failed"); }
+    sv->valued = true;
   }
   if ((flags & PEPSI_SERVER_CACHE_PLAINTEXTS) && max_load > 0) {
     // as many batches as fit beside a working reserve, in whole 16-batch tiles unless all fit
@@ -813,7 +875,7 @@ extern "C" int pepsi_server_get_info(const pepsi_server* sv, pepsi_server_info* 
   o->max_load = sv->max_load;
   o->cached = sv->cached ? 1 : 0;
   o->cached_batches = sv->cached_batches;
-  o->device_bytes = sv->cw.cap + sv->cache.cap;
+  o->device_bytes = sv->cw.cap + sv->cache.cap + sv->vhat.cap;
   return PEPSI_OK;
 }
 
@@ -829,6 +891,7 @@ extern "C" void pepsi_server_destroy(pepsi_server* sv) {
   (void)hipDeviceSynchronize();
   sv->cw.release();
   sv->cache.release();
+  sv->vhat.release();
   delete sv;
 }
 
@@ -841,7 +904,7 @@ extern "C" int pepsi_server_eval_range(pepsi_server* sv, const uint64_t* cts, co
   hipStream_t s = S(stream);
   if (!sv->ready) {
     const int tb = std::min<int>(128, std::max<int>(1, (int)sv->max_load));
-    int rc = sv->eng.setup(sv->P, tb, 1, sv->cached_batches < sv->max_load);
+    int rc = sv->eng.setup(sv->P, tb, 1, sv->cached_batches < sv->max_load, sv->values_hat());
     if (rc) return rc;
     sv->eng.timer = &sv->timer;
     sv->ready = true;
@@ -884,7 +947,7 @@ extern "C" int pepsi_server_eval_batch(pepsi_server* sv, uint32_t nq, const uint
   if ((int)nq > sv->bqmax) {
     // batches per tile: one batch group of the multi-query select-and-sum (16)
     int rc = sv->beng.setup(sv->P, std::min<int>(16, std::max<int>(1, (int)sv->max_load)), (int)nq,
-                            sv->cached_batches < sv->max_load);
+                            sv->cached_batches < sv->max_load, sv->values_hat());
     if (rc) return rc;
     sv->beng.timer = &sv->timer;
     sv->bqmax = (int)nq;
@@ -1058,7 +1121,7 @@ extern "C" int pepsi_serve_create(pepsi_server* sv, uint32_t max_active, uint64_
   sr->slots = (int)slots;
   sr->stop_b = std::min<uint32_t>(H.mu, sv->max_load);
   sr->T = (int)((sr->stop_b + tbq - 1) / tbq);
-  int rc = sr->eng.setup(sv->P, tbq, (int)slots, sv->cached_batches < sv->max_load);
+  int rc = sr->eng.setup(sv->P, tbq, (int)slots, sv->cached_batches < sv->max_load, sv->values_hat());
   if (!rc) rc = sr->qslot_dev.ensure(sizeof(int) * slots);
   if (!rc && hipHostMalloc((void**)&sr->qslot_host, sizeof(int) * slots, hipHostMallocDefault) != hipSuccess)
     rc = fail(PEPSI_E_NOMEM, "pinned slot buffer");

@@ -80,6 +80,10 @@ void relin_inner(const Tables& T, const Consts& hc, const uint64_t* c01h, const 
 // modulo q_(r mod L)), xstride words apart in x and astride words apart in acc.
 void accumulate(const Tables& T, const Consts& hc, const uint64_t* x, long xstride, int nb, int nq,
                 int rows, const int* qslot, uint64_t* acc, long astride, hipStream_t s);
+// acc[slot(q)][2][L][N] += sum over b < nb of x[b * nq + q] (.) vhat[b] (NTT form; vhat
+// [nb][L][N], the server-value plaintexts of the batches; x entries xstride words apart).
+void value_accumulate(const Tables& T, const Consts& hc, const uint64_t* x, long xstride, const uint64_t* vhat,
+                      int nb, int nq, const int* qslot, uint64_t* acc, long astride, hipStream_t s);
 // select-and-sum: S[b][c][l][k] = sum_j C[j][c][l][k] * P[b][j][l][k] mod q_l.
 // C: NTT form [ell][2][L][N]; P: split-27 NTT form [nb][ell][L][N]; S rows of stride sstride.
 void select_sum(const Tables& T, const Consts& hc, const uint64_t* C, const uint64_t* P, int ell,

@@ -49,10 +49,12 @@ int cuckoo_insert(const uint32_t* items, uint64_t m, uint32_t nbins, uint64_t se
 }
 
 int simple_hash(const uint32_t* items, uint64_t n, uint32_t nbins, uint64_t seed, int k, uint32_t mu,
-                std::vector<uint32_t>* table, std::vector<uint8_t>* valid, uint32_t* max_load) {
+                std::vector<uint32_t>* table, std::vector<uint8_t>* valid, uint32_t* max_load,
+                std::vector<uint32_t>* index) {
   std::vector<uint32_t> load(nbins, 0);
   table->assign((size_t)mu * nbins, 0);
   valid->assign((size_t)mu * nbins, 0);
+  if (index) index->assign((size_t)mu * nbins, 0);
   uint32_t bins[8];
   for (uint64_t e = 0; e < n; ++e) {
     const uint32_t y = items[e];
@@ -68,6 +70,7 @@ int simple_hash(const uint32_t* items, uint64_t n, uint32_t nbins, uint64_t seed
       if (load[b] >= mu) return -4;
       (*table)[(size_t)load[b] * nbins + b] = y;
       (*valid)[(size_t)load[b] * nbins + b] = 1;
+      if (index) (*index)[(size_t)load[b] * nbins + b] = (uint32_t)e;
       ++load[b];
     }
   }

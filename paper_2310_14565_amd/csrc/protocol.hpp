@@ -14,9 +14,11 @@ uint32_t hash_bin(uint64_t x, int i, uint64_t seed, uint32_t nbins);
 int cuckoo_insert(const uint32_t* items, uint64_t m, uint32_t nbins, uint64_t seed, int k,
                   int max_evictions, uint32_t* table, uint8_t* valid);
 // Every element to each distinct bin among H_1..H_k, input order; table/valid [mu][nbins];
-// returns 0 or -4 (a bin exceeds mu).
+// with index non-null also the element's input position per entry; returns 0 or -4 (a bin
+// exceeds mu).
 int simple_hash(const uint32_t* items, uint64_t n, uint32_t nbins, uint64_t seed, int k, uint32_t mu,
-                std::vector<uint32_t>* table, std::vector<uint8_t>* valid, uint32_t* max_load);
+                std::vector<uint32_t>* table, std::vector<uint8_t>* valid, uint32_t* max_load,
+                std::vector<uint32_t>* index = nullptr);
 
 // Constant-weight code CW(ell, h) by the combinatorial number system.
 class CwEncoder {

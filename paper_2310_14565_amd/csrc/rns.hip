@@ -399,6 +399,34 @@ __global__ void __launch_bounds__(TPB) k_accumulate(Tables T, const uint64_t* __
   a[(size_t)cl * N + k] = s;
 }
 
+// acc[slot(q)] += sum over batches b of x[b * nq + q] (.) vhat[b]: the server values of each
+// batch (NTT form [L][N], one plaintext per batch) times that batch's equality ciphertexts
+// (NTT form [2][L][N], xstride words apart), accumulated per query (NTT form).
+__global__ void __launch_bounds__(TPB) k_value_accumulate(Tables T, const uint64_t* __restrict__ x,
+                                                         long xstride, const uint64_t* __restrict__ vhat,
+                                                         int nb, int nq, const int* __restrict__ qslot,
+                                                         uint64_t* __restrict__ acc, long astride) {
+  const Consts& C = *T.c;
+  const int N = C.n, L = C.L;
+  const int k = blockIdx.x * TPB + threadIdx.x;
+  const int cl = blockIdx.y;                       // component * L + limb
+  const int q = blockIdx.z;
+  if (k >= N) return;
+  const int l = cl % L;
+  const Prime& pr = C.prm[l];
+  uint64_t* a = acc + (size_t)(qslot ? qslot[q] : q) * astride;
+  uint64_t s = a[(size_t)cl * N + k];
+  int b = 0;
+  while (b < nb) {
+    u128 t = s;
+    const int end = min(nb, b + 200);              // 200 products below 2^108 stay below 2^116
+    for (; b < end; ++b)
+      t += (u128)x[((size_t)b * nq + q) * xstride + (size_t)cl * N + k] * vhat[((size_t)b * L + l) * N + k];
+    s = reduce116((uint64_t)t, (uint64_t)(t >> 64), pr);
+  }
+  a[(size_t)cl * N + k] = s;
+}
+
 // Select-and-sum.  Thread = one slot position k of one limb, IB server batches at a time (the
 // client ciphertext value is loaded once and used IB times).  A product of two residues below
 // 2^54 is formed from 27-bit halves, a = a1 2^27 + a0 and b = b1 2^27 + b0 (the plaintexts are
@@ -836,6 +864,12 @@ void accumulate(const Tables& T, const Consts& hc, const uint64_t* x, long xstri
   if (nb <= 0 || nq <= 0 || rows <= 0) return;
   hipLaunchKernelGGL(k_accumulate, grid_for(hc.n, rows, nq), dim3(TPB), 0, s, T, x, xstride, nb, nq, qslot,
                      acc, astride);
+}
+void value_accumulate(const Tables& T, const Consts& hc, const uint64_t* x, long xstride, const uint64_t* vhat,
+                      int nb, int nq, const int* qslot, uint64_t* acc, long astride, hipStream_t s) {
+  if (nb <= 0 || nq <= 0) return;
+  hipLaunchKernelGGL(k_value_accumulate, grid_for(hc.n, 2 * hc.L, nq), dim3(TPB), 0, s, T, x, xstride, vhat, nb,
+                     nq, qslot, acc, astride);
 }
 void select_sum(const Tables& T, const Consts& hc, const uint64_t* Cn, const uint64_t* P, int ell,
                 int nb, uint64_t* S, long sstride, hipStream_t s) {

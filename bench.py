@@ -226,6 +226,41 @@ def serving_leg(pk, requests, pool, slots, load, seed):
     }
 
 
+def psi_sum_leg(pk, params, server_items, cfg, steps, seed):
+    """PSI-Sum (Alg. 5) on the same workload: server values uniform 12-bit, plaintexts cached."""
+    import torch
+    import workload as W
+    n, L = params.n, params.L
+    values = W.item_values(server_items.shape[0], 0, 1 << 12, seed)
+    server = pk.Server(params, server_items, cache_plaintexts=True, values=values)
+    q = make_query(params, server_items, cfg, cfg["m_client"], cfg["planted"], seed + 1)
+    out = torch.zeros((2, L, n), dtype=torch.int64, device="cuda")
+    server.eval(q["cts"], q["rlk"], q["mask"], out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        server.eval(q["cts"], q["rlk"], q["mask"], out)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    slots = torch.zeros((1, n), dtype=torch.int32, device="cuda")
+    params.decrypt(q["sk"], out.reshape(1, 2, L, n), slots)
+    torch.cuda.synchronize()
+    got = int(slots.cpu().numpy().view(np.uint32).astype(np.int64).sum() % 65537)
+    common = np.isin(server_items, q["client"])
+    want = int(values[common].astype(np.int64).sum() % 65537)
+    server.close()
+    if got != want:
+        log(f"[bench] WRONG PSI-Sum: {got} (want {want})")
+        sys.exit(1)
+    return {
+        "ms_per_query": round(1e3 * t, 3),
+        "value": round(n * cfg["mu"] / t, 1),
+        "unit": "slot-comparisons/s",
+        "steps": steps,
+        "check": {"sum_mod_t": got},
+    }
+
+
 def batched_leg(params, server, server_items, cfg, nq, steps, seed, plain_value):
     """Config 'batched': nq queries, m log-uniform in [64, 2048], 25% planted, one launch sequence."""
     import torch
@@ -283,6 +318,7 @@ def main():
     ap.add_argument("--batch", type=int, default=64, help="queries per batched launch (0: skip the batched leg)")
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--seed", type=int, default=2024)
+    ap.add_argument("--psi-sum-steps", type=int, default=5, help="steps of the PSI-Sum leg (0: skip it)")
     ap.add_argument("--serve", type=int, default=500, help="requests in the serving leg (0: skip it)")
     ap.add_argument("--serve-pool", type=int, default=16, help="distinct client queries behind the requests")
     ap.add_argument("--serve-slots", type=int, default=64)
@@ -425,6 +461,9 @@ def main():
     if args.batch > 0:
         line["batched"] = batched_leg(params, server, server_items, cfg, args.batch, args.batch_steps,
                                       args.seed + 7, value)
+    if args.psi_sum_steps > 0 and args.config == "paper":
+        server.close()
+        line["psi_sum"] = psi_sum_leg(pk, params, server_items, cfg, args.psi_sum_steps, args.seed + 9)
     if args.serve > 0:
         server.close()
         del cts, rlk, out

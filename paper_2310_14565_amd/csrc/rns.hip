@@ -430,14 +430,18 @@ __global__ void __launch_bounds__(TPB) k_value_accumulate(Tables T, const uint64
 // Select-and-sum.  Thread = one slot position k of one limb, IB server batches at a time (the
 // client ciphertext value is loaded once and used IB times).  A product of two residues below
 // 2^54 is formed from 27-bit halves, a = a1 2^27 + a0 and b = b1 2^27 + b0 (the plaintexts are
-// stored pre-split: b0 in the low and b1 in the high 32-bit word), into three accumulators
-//   lo += a0 b0,  mid += a0 b1 + a1 b0,  hi += a1 b1,
-// each term below 2^54 (2^55 for mid), so 511 terms fit in 64 bits; every 511 terms the value
-// lo + mid 2^27 + hi 2^54 is reduced and restarts lo.  Loads of a partial group are clamped to
-// its last batch so that every load is unconditional (results of padding lanes are dropped).
+// stored pre-split: b0 in the low and b1 in the high 32-bit word), with three products
+// (Karatsuba) into three 64-bit accumulators
+//   lo += a0 b0,  hi += a1 b1,  ms += (a0 + a1)(b0 + b1),
+// so that the middle term a0 b1 + a1 b0 is ms - lo - hi, exactly.  Terms are below 2^56, so
+// FOLD = 254 terms (plus a restart value below 2^54) fit in 64 bits; every FOLD terms the value
+// lo + (ms - lo - hi) 2^27 + hi 2^54 is reduced and restarts both lo and ms (hi restarts at 0).
+// Loads of a partial group are clamped to its last batch so that every load is unconditional
+// (results of padding lanes are dropped).
 constexpr int IB = 8;
-constexpr int FOLD = 511;
-__device__ __forceinline__ uint64_t fold3(uint64_t lo, uint64_t mid, uint64_t hi, const Prime& pr) {
+constexpr int FOLD = 254;
+__device__ __forceinline__ uint64_t fold3(uint64_t lo, uint64_t ms, uint64_t hi, const Prime& pr) {
+  const uint64_t mid = ms - lo - hi;
   const u128 v = (u128)lo + ((u128)mid << 27) + ((u128)hi << 54);
   return reduce128((uint64_t)v, (uint64_t)(v >> 64), pr);
 }
@@ -455,41 +459,43 @@ __global__ void __launch_bounds__(TPB) k_select_sum(Tables T, const uint64_t* __
   const int slice = (local / zg) * 8 + (bid & 7);
   if (slice >= slices) return;
   const int kchunks = N / TPB;
-  const int k = (slice % kchunks) * TPB + threadIdx.x;
+  const int k0 = (slice % kchunks) * TPB;
+  const uint32_t tid = threadIdx.x;
+  const int k = k0 + (int)tid;
   const int l = slice / kchunks;
   const int b0 = (local % zg) * IB;
   const int nbl = min(IB, nb - b0);
   const Prime& pr = C.prm[l];
   constexpr uint64_t M27 = (1ull << 27) - 1;
-  uint64_t lo[2][IB], mid[2][IB], hi[2][IB];
+  uint64_t lo[2][IB], ms[2][IB], hi[2][IB];
 #pragma unroll
   for (int c = 0; c < 2; ++c)
 #pragma unroll
-    for (int b = 0; b < IB; ++b) lo[c][b] = mid[c][b] = hi[c][b] = 0;
+    for (int b = 0; b < IB; ++b) lo[c][b] = ms[c][b] = hi[c][b] = 0;
   const size_t pstep = (size_t)L * N, cstep = (size_t)2 * L * N;
+  // wave-uniform row bases; each lane adds its position (scalar base + 32-bit lane offset)
   const uint64_t* pb[IB];
 #pragma unroll
-  for (int b = 0; b < IB; ++b) pb[b] = Pc + ((size_t)(b0 + min(b, nbl - 1)) * ell * L + l) * N + k;
-  const uint64_t* cb = Cn + (size_t)l * N + k;
+  for (int b = 0; b < IB; ++b) pb[b] = Pc + ((size_t)(b0 + min(b, nbl - 1)) * ell * L + l) * N + k0;
+  const uint64_t* cb = Cn + (size_t)l * N + k0;
   int fold = 0;
   for (int j = 0; j < ell; ++j) {
     uint64_t w[IB];
 #pragma unroll
-    for (int b = 0; b < IB; ++b) w[b] = __builtin_nontemporal_load(pb[b] + j * pstep);
-    const uint64_t c0 = cb[j * cstep], c1 = cb[j * cstep + (size_t)L * N];
+    for (int b = 0; b < IB; ++b) w[b] = __builtin_nontemporal_load(pb[b] + j * pstep + tid);
+    const uint64_t c0 = cb[j * cstep + tid], c1 = cb[j * cstep + (size_t)L * N + tid];
     const uint32_t a00 = (uint32_t)(c0 & M27), a01 = (uint32_t)(c0 >> 27);
     const uint32_t a10 = (uint32_t)(c1 & M27), a11 = (uint32_t)(c1 >> 27);
+    const uint32_t as0 = a00 + a01, as1 = a10 + a11;
 #pragma unroll
     for (int b = 0; b < IB; ++b) {
-      const uint32_t blo = (uint32_t)w[b], bhi = (uint32_t)(w[b] >> 32);
+      const uint32_t blo = (uint32_t)w[b], bhi = (uint32_t)(w[b] >> 32), bs = blo + bhi;
       lo[0][b] += (uint64_t)a00 * blo;
-      mid[0][b] += (uint64_t)a00 * bhi;
-      mid[0][b] += (uint64_t)a01 * blo;
       hi[0][b] += (uint64_t)a01 * bhi;
+      ms[0][b] += (uint64_t)as0 * bs;
       lo[1][b] += (uint64_t)a10 * blo;
-      mid[1][b] += (uint64_t)a10 * bhi;
-      mid[1][b] += (uint64_t)a11 * blo;
       hi[1][b] += (uint64_t)a11 * bhi;
+      ms[1][b] += (uint64_t)as1 * bs;
     }
     if (++fold == FOLD) {
       fold = 0;
@@ -497,8 +503,8 @@ __global__ void __launch_bounds__(TPB) k_select_sum(Tables T, const uint64_t* __
       for (int c = 0; c < 2; ++c)
 #pragma unroll
         for (int b = 0; b < IB; ++b) {
-          lo[c][b] = fold3(lo[c][b], mid[c][b], hi[c][b], pr);
-          mid[c][b] = hi[c][b] = 0;
+          lo[c][b] = ms[c][b] = fold3(lo[c][b], ms[c][b], hi[c][b], pr);
+          hi[c][b] = 0;
         }
     }
   }
@@ -507,7 +513,7 @@ __global__ void __launch_bounds__(TPB) k_select_sum(Tables T, const uint64_t* __
     if (b < nbl)
 #pragma unroll
       for (int c = 0; c < 2; ++c)
-        S[(size_t)(b0 + b) * sstride + ((size_t)c * L + l) * N + k] = fold3(lo[c][b], mid[c][b], hi[c][b], pr);
+        S[(size_t)(b0 + b) * sstride + ((size_t)c * L + l) * N + k] = fold3(lo[c][b], ms[c][b], hi[c][b], pr);
 }
 
 // Select-and-sum of several queries against one tile of server plaintexts.
@@ -547,13 +553,13 @@ __global__ void __launch_bounds__(MTPB) k_select_sum_multi(Tables T, const uint6
 #pragma unroll
   for (int b = 0; b < MBB; ++b)
     pp[b] = Pc + ((size_t)(b0 + min(b, nbl - 1)) * ell * L + l) * N + kbase + lane;
-  uint64_t lo[MQ][2][MBB], mid[MQ][2][MBB], hi[MQ][2][MBB];
+  uint64_t lo[MQ][2][MBB], ms[MQ][2][MBB], hi[MQ][2][MBB];
 #pragma unroll
   for (int a = 0; a < MQ; ++a)
 #pragma unroll
     for (int c = 0; c < 2; ++c)
 #pragma unroll
-      for (int b = 0; b < MBB; ++b) lo[a][c][b] = mid[a][c][b] = hi[a][c][b] = 0;
+      for (int b = 0; b < MBB; ++b) lo[a][c][b] = ms[a][c][b] = hi[a][c][b] = 0;
   uint64_t nc[MQ][2], np[MBB];
 #pragma unroll
   for (int a = 0; a < MQ; ++a)
@@ -564,7 +570,7 @@ __global__ void __launch_bounds__(MTPB) k_select_sum_multi(Tables T, const uint6
   int fold = 0;
   for (int j = 0; j < ell; ++j) {
     const int jn = min(j + 1, ell - 1);
-    uint32_t a0[MQ][2], a1[MQ][2];
+    uint32_t a0[MQ][2], a1[MQ][2], as[MQ][2];
 #pragma unroll
     for (int a = 0; a < MQ; ++a)
 #pragma unroll
@@ -573,6 +579,7 @@ __global__ void __launch_bounds__(MTPB) k_select_sum_multi(Tables T, const uint6
         nc[a][c] = cp[a][c][jn * cjs];
         a0[a][c] = (uint32_t)(v & M27);
         a1[a][c] = (uint32_t)(v >> 27);
+        as[a][c] = a0[a][c] + a1[a][c];
       }
     uint64_t pv[MBB];
 #pragma unroll
@@ -582,15 +589,14 @@ __global__ void __launch_bounds__(MTPB) k_select_sum_multi(Tables T, const uint6
     }
 #pragma unroll
     for (int b = 0; b < MBB; ++b) {
-      const uint32_t blo = (uint32_t)pv[b], bhi = (uint32_t)(pv[b] >> 32);
+      const uint32_t blo = (uint32_t)pv[b], bhi = (uint32_t)(pv[b] >> 32), bs = blo + bhi;
 #pragma unroll
       for (int a = 0; a < MQ; ++a)
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
           lo[a][c][b] += (uint64_t)a0[a][c] * blo;
-          mid[a][c][b] += (uint64_t)a0[a][c] * bhi;
-          mid[a][c][b] += (uint64_t)a1[a][c] * blo;
           hi[a][c][b] += (uint64_t)a1[a][c] * bhi;
+          ms[a][c][b] += (uint64_t)as[a][c] * bs;
         }
     }
     if (++fold == FOLD) {
@@ -601,8 +607,8 @@ __global__ void __launch_bounds__(MTPB) k_select_sum_multi(Tables T, const uint6
         for (int c = 0; c < 2; ++c)
 #pragma unroll
           for (int b = 0; b < MBB; ++b) {
-            lo[a][c][b] = fold3(lo[a][c][b], mid[a][c][b], hi[a][c][b], pr);
-            mid[a][c][b] = hi[a][c][b] = 0;
+            lo[a][c][b] = ms[a][c][b] = fold3(lo[a][c][b], ms[a][c][b], hi[a][c][b], pr);
+            hi[a][c][b] = 0;
           }
     }
   }
@@ -615,7 +621,7 @@ __global__ void __launch_bounds__(MTPB) k_select_sum_multi(Tables T, const uint6
 #pragma unroll
         for (int c = 0; c < 2; ++c)
           S[((size_t)(b0 + b) * nq + q0 + a) * 2 * L * N + ((size_t)c * L + l) * N + k] =
-              fold3(lo[a][c][b], mid[a][c][b], hi[a][c][b], pr);
+              fold3(lo[a][c][b], ms[a][c][b], hi[a][c][b], pr);
 }
 
 __global__ void __launch_bounds__(TPB) k_pointwise(Tables T, const uint64_t* __restrict__ a,

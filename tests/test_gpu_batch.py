@@ -35,16 +35,19 @@ def make_queries(ctx, cfg, server, nq, seed):
     return out
 
 
-@pytest.mark.parametrize("h,nq,cache", [(2, 1, False), (2, 3, True), (4, 9, True), (3, 17, False)])
-def test_batch_equals_alone(h, nq, cache):
+@pytest.mark.parametrize("h,nq,cache,n_server", [(2, 1, False, 400), (2, 3, True, 400), (4, 9, True, 400),
+                                                 (3, 17, False, 400), (2, 5, True, 12000), (4, 3, False, 12000)])
+def test_batch_equals_alone(h, nq, cache, n_server):
+    """Small sets give tiles of a few batches; 12000 items give full 16-batch tiles."""
     import paper_2310_14565_amd as pk
-    log_n, L, bits = 10, 3, {2: 10, 3: 12, 4: 12}[h]
+    log_n, L = 10, 3
+    bits = 16 if n_server > 1000 else {2: 10, 3: 12, 4: 12}[h]
     n = 1 << log_n
-    mu = P.server_bin_bound(400, n)
+    mu = P.server_bin_bound(n_server, n)
     cfg = PR.Config(n=n, L=L, h=h, item_bits=bits, mu=mu)
     gp = pk.Params(log_n, L, h, bits, mu, hash_seed=cfg.hash_seed)
     ctx = Context(n, gp.q_primes)
-    server = W.server_items(400, bits, 70 + h)
+    server = W.server_items(n_server, bits, 70 + h)
     sv = pk.Server(gp, server, cache_plaintexts=cache)
     qs = make_queries(ctx, cfg, server, nq, 100 * h + nq)
     say(f"batch h={h} nq={nq} cache={cache} ell={cfg.ell} max_load={sv.max_load}")

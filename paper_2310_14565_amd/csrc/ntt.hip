@@ -7,9 +7,11 @@
 // one word every 32 so that the strided pass patterns spread over banks).
 // Forward: Cooley-Tukey with the bit-reversed power table psi^brv(k), output
 // in bit-reversed evaluation order.  Inverse: Gentleman-Sande with psi^-brv(k)
-// and a final N^-1.  Butterflies are lazy (Harvey): residues live in [0, 4p)
-// in the forward and [0, 2p) in the inverse transform, with one Shoup
-// product per butterfly.
+// and a final N^-1.  One Shoup product per butterfly, whose result lies in
+// [0, 2p) for any 64-bit input.  Forward butterflies are not reduced at all:
+// (U, V) -> (U + V, U - V + 2p) with V < 2p raises the bound by 2p per stage,
+// so reduced inputs stay below (1 + 2 log2 N) p <= 29p < 2^59 and the output is
+// reduced once at the store.  Inverse butterflies keep U + V below 2p.
 //
 // Transforms over t = 65537 (batch encoding of slots) are cheap 32-bit
 // radix-2 loops over LDS.
@@ -48,8 +50,7 @@ __device__ __forceinline__ void fwd_pass(uint64_t* x, int tid, const uint64_t* _
 #pragma unroll
         for (int m = 0; m < half; ++m) {
           const int a = u * (1 << D) + blk * 2 * half + m, b = a + half;
-          uint64_t U = x[a];
-          if (U >= two_p) U -= two_p;
+          const uint64_t U = x[a];
           const uint64_t V = shoup_lazy(x[b], w, wq, p);
           x[a] = U + V;
           x[b] = U - V + two_p;
@@ -151,12 +152,11 @@ k_ntt_fwd(Tables T, const void* __restrict__ in, void* __restrict__ out, int npr
     to_lds<LOGN, 10, D2>(lds, x, tid);
     __syncthreads();
   }
-  const uint64_t two_p = 2 * p;
+  const uint64_t p64 = T.c->prm[pidx].barrett >> 52;     // floor(2^64 / p)
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int j = m * TT + tid;
-    uint64_t v = lds[lds_idx(j)];
-    if (v >= two_p) v -= two_p;
+    uint64_t v = shoup_lazy(lds[lds_idx(j)], 1, p64, p);   // [0, 29p) -> [0, 2p)
     if (v >= p) v -= p;
     if constexpr (ST == STORE_U64) {
       static_cast<uint64_t*>(out)[row * N + j] = v;

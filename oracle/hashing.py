@@ -14,6 +14,15 @@ in its bin H_i(x') is evicted and moves on to H_{(i mod k)+1}(x'); more than
 ``max_evictions`` evictions for one insertion is a protocol failure (no stash).
 Server simple hashing: y is appended to each DISTINCT bin among H_1..H_k(y),
 elements in input order; a bin holding more than mu elements is a failure.
+
+Permutation-based hashing (PBH, Sec. 3.3) with b = 2^c bins and lambda-bit
+elements x = x_H || x_L (|x_H| = c): hash function i puts x into bin
+x_H XOR H_i(x_L) and stores the shorter value (i - 1) 2^(lambda - c) + x_L.  The
+paper's description has one hash function; with k of them the stored value must
+also name i, or x placed by H_i and a different y placed by H_j could meet in a
+bin with x_L = y_L.  Equal stored values in equal bins then imply equal
+elements.  The server stores all k (bin, value) entries of an element (entries
+of one element never share a value, so none is dropped and none can match twice).
 """
 from __future__ import annotations
 
@@ -57,8 +66,19 @@ def bins_of_array(xs: np.ndarray, i: int, seed: int, n_bins: int) -> np.ndarray:
     return (z % np.uint64(n_bins)).astype(np.int64)
 
 
-def cuckoo_table(items, n_bins: int, seed: int, n_hash: int = 3, max_evictions: int = 500):
-    """Client table T_c (gamma = 1): returns (table uint32[b], valid uint8[b])."""
+def pbh_place(x: int, i: int, seed: int, n_bins: int, lam: int):
+    """PBH: (bin, stored value) of element x under hash function i (b = n_bins = 2^c)."""
+    c = n_bins.bit_length() - 1
+    assert n_bins == 1 << c and lam > c
+    low = lam - c
+    xh, xl = x >> low, x & ((1 << low) - 1)
+    return xh ^ bin_of(xl, i, seed, n_bins), ((i - 1) << low) | xl
+
+
+def cuckoo_table(items, n_bins: int, seed: int, n_hash: int = 3, max_evictions: int = 500,
+                 pbh_bits: int | None = None):
+    """Client table T_c (gamma = 1): returns (table uint32[b], valid uint8[b]).  With pbh_bits
+    (the element length lambda) the table holds PBH values instead of the elements."""
     items = [int(x) for x in items]
     if len(set(items)) != len(items):
         raise ValueError("duplicate client items")
@@ -67,7 +87,10 @@ def cuckoo_table(items, n_bins: int, seed: int, n_hash: int = 3, max_evictions: 
     for x in items:
         cur, idx, evictions = x, 1, 0
         while True:
-            pos = bin_of(cur, idx, seed, n_bins)
+            if pbh_bits:
+                pos = pbh_place(cur, idx, seed, n_bins, pbh_bits)[0]
+            else:
+                pos = bin_of(cur, idx, seed, n_bins)
             if table[pos] is None:
                 table[pos], which[pos] = cur, idx
                 break
@@ -82,29 +105,44 @@ def cuckoo_table(items, n_bins: int, seed: int, n_hash: int = 3, max_evictions: 
     valid = np.zeros(n_bins, dtype=np.uint8)
     for k, v in enumerate(table):
         if v is not None:
-            out[k] = v
+            out[k] = pbh_place(v, which[k], seed, n_bins, pbh_bits)[1] if pbh_bits else v
             valid[k] = 1
     return out, valid
 
 
-def simple_table(items: np.ndarray, n_bins: int, mu: int, seed: int, n_hash: int = 3):
-    """Server table T_s: returns (table uint32[mu][b], valid uint8[mu][b], max_load).
+def simple_table(items: np.ndarray, n_bins: int, mu: int, seed: int, n_hash: int = 3,
+                 pbh_bits: int | None = None, with_index: bool = False):
+    """Server table T_s: returns (table uint32[mu][b], valid uint8[mu][b], max_load), and with
+    with_index also the element's input position per entry (int64[mu][b], -1 for dummies).
 
-    Entry (i', k) is the i'-th element appended to bin k, in input order."""
+    Entry (i', k) is the i'-th element appended to bin k, in input order.  With pbh_bits the
+    entries are PBH values, one per hash function (in hash-function order within an element)."""
     items = np.asarray(items, dtype=np.uint64)
     n = items.shape[0]
-    h = np.stack([bins_of_array(items, i, seed, n_bins) for i in range(1, n_hash + 1)])  # [k][n]
-    # distinct bins of each element: drop H_i(y) equal to an earlier H_j(y)
-    keep = np.ones_like(h, dtype=bool)
-    for i in range(1, n_hash):
-        for j in range(i):
-            keep[i] &= h[i] != h[j]
-    elem = np.broadcast_to(np.arange(n), h.shape)
-    sel_bin = h[keep]
-    sel_elem = elem[keep]
-    # input order within each bin: stable sort by (bin, element index)
-    order = np.lexsort((sel_elem, sel_bin))
-    sel_bin, sel_elem = sel_bin[order], sel_elem[order]
+    elem = np.broadcast_to(np.arange(n), (n_hash, n))
+    if pbh_bits:
+        c = n_bins.bit_length() - 1
+        assert n_bins == 1 << c and pbh_bits > c
+        low = pbh_bits - c
+        xh = items >> np.uint64(low)
+        xl = items & np.uint64((1 << low) - 1)
+        h = np.stack([(xh ^ bins_of_array(xl, i, seed, n_bins).astype(np.uint64)).astype(np.int64)
+                      for i in range(1, n_hash + 1)])                                    # [k][n]
+        vals = np.stack([(np.uint64(i - 1) << np.uint64(low)) | xl for i in range(1, n_hash + 1)])
+        keep = np.ones_like(h, dtype=bool)
+    else:
+        h = np.stack([bins_of_array(items, i, seed, n_bins) for i in range(1, n_hash + 1)])  # [k][n]
+        vals = np.broadcast_to(items, (n_hash, n))
+        # distinct bins of each element: drop H_i(y) equal to an earlier H_j(y)
+        keep = np.ones_like(h, dtype=bool)
+        for i in range(1, n_hash):
+            for j in range(i):
+                keep[i] &= h[i] != h[j]
+    fn = np.broadcast_to(np.arange(n_hash)[:, None], (n_hash, n))
+    sel_bin, sel_elem, sel_fn, sel_val = h[keep], elem[keep], fn[keep], vals[keep]
+    # input order within each bin: stable sort by (bin, element index, hash function)
+    order = np.lexsort((sel_fn, sel_elem, sel_bin))
+    sel_bin, sel_elem, sel_val = sel_bin[order], sel_elem[order], sel_val[order]
     counts = np.bincount(sel_bin, minlength=n_bins)
     max_load = int(counts.max()) if counts.size else 0
     if max_load > mu:
@@ -113,6 +151,10 @@ def simple_table(items: np.ndarray, n_bins: int, mu: int, seed: int, n_hash: int
     rank = np.arange(sel_bin.shape[0]) - starts[sel_bin]
     table = np.zeros((mu, n_bins), dtype=np.uint32)
     valid = np.zeros((mu, n_bins), dtype=np.uint8)
-    table[rank, sel_bin] = items[sel_elem].astype(np.uint32)
+    table[rank, sel_bin] = sel_val.astype(np.uint32)
     valid[rank, sel_bin] = 1
+    if with_index:
+        index = np.full((mu, n_bins), -1, dtype=np.int64)
+        index[rank, sel_bin] = sel_elem
+        return table, valid, max_load, index
     return table, valid, max_load

@@ -26,25 +26,40 @@ class Config:
     n: int               # ring degree N (= number of bins b)
     L: int               # ciphertext primes
     h: int               # Hamming weight
-    item_bits: int       # lambda_bar (no PBH: the full element length)
+    item_bits: int       # lambda, the element length
     mu: int              # server maximum bin load
     hash_seed: int = 0x5EED
     n_hash: int = 3
     max_evictions: int = 500
+    pbh: bool = False    # permutation-based hashing (Sec. 3.3)
+
+    @property
+    def effective_bits(self) -> int:
+        """lambda_bar: the length of the stored values.  Without PBH the element itself; with
+        PBH lambda - log2(b) plus the bits that name the hash function."""
+        if not self.pbh:
+            return self.item_bits
+        return self.item_bits - (self.n.bit_length() - 1) + (self.n_hash - 1).bit_length()
 
     @property
     def ell(self) -> int:
-        return P.code_length(self.item_bits, self.h)
+        return P.code_length(self.effective_bits, self.h)
+
+    @property
+    def pbh_bits(self):
+        return self.item_bits if self.pbh else None
 
 
 def client_prepare(cfg: Config, items):
-    table, valid = hashing.cuckoo_table(items, cfg.n, cfg.hash_seed, cfg.n_hash, cfg.max_evictions)
+    table, valid = hashing.cuckoo_table(items, cfg.n, cfg.hash_seed, cfg.n_hash, cfg.max_evictions,
+                                        pbh_bits=cfg.pbh_bits)
     pos = cw.positions_table(table, valid, cfg.ell, cfg.h)          # [b][h]
     return table, valid, pos, cw.planes(pos, cfg.ell)               # planes [l][b]
 
 
 def server_prepare(cfg: Config, items):
-    table, valid, max_load = hashing.simple_table(items, cfg.n, cfg.mu, cfg.hash_seed, cfg.n_hash)
+    table, valid, max_load = hashing.simple_table(items, cfg.n, cfg.mu, cfg.hash_seed, cfg.n_hash,
+                                                  pbh_bits=cfg.pbh_bits)
     pos = cw.positions_table(table, valid, cfg.ell, cfg.h)          # [mu][b][h]
     return table, valid, pos, max_load
 
@@ -77,16 +92,13 @@ def extract_sum(slots, t: int = P.T_PLAIN) -> int:
 def server_values(cfg: Config, items, values):
     """val_s as a [mu][b] table: entry (i', k) = the value of the server element at (i', k)
     of T_s (Alg. 6 layout), 0 for dummies.  values[e] belongs to items[e]; values < t."""
-    table, valid, _ = hashing.simple_table(items, cfg.n, cfg.mu, cfg.hash_seed, cfg.n_hash)
-    items = np.asarray(items, dtype=np.uint64)
     values = np.asarray(values, dtype=np.uint64)
-    assert values.shape == items.shape and (values < P.T_PLAIN).all()
-    order = np.argsort(items)
-    sorted_items = items[order]
+    assert values.shape == np.asarray(items).shape and (values < P.T_PLAIN).all()
+    _, valid, _, index = hashing.simple_table(items, cfg.n, cfg.mu, cfg.hash_seed, cfg.n_hash,
+                                              pbh_bits=cfg.pbh_bits, with_index=True)
+    out = np.zeros(valid.shape, dtype=np.uint32)
     sel = valid.astype(bool)
-    idx = np.searchsorted(sorted_items, table[sel].astype(np.uint64))
-    out = np.zeros(table.shape, dtype=np.uint32)
-    out[sel] = values[order][idx].astype(np.uint32)
+    out[sel] = values[index[sel]].astype(np.uint32)
     return out
 
 

@@ -261,6 +261,48 @@ def psi_sum_leg(pk, params, server_items, cfg, steps, seed):
     }
 
 
+def paper32_leg(pk, steps, seed):
+    """The paper's own 32-bit parameters (Sec. 7): b = N = 8192, h = 8 with permutation-based
+    hashing (stored values of 21 bits with the hash index, l = 27), L = 4, n = 2^20, m = 1024 with
+    256 planted, mu = 526, plaintexts cached."""
+    import torch
+    import workload as W
+    n, L = 8192, 4
+    params = pk.Params(13, L, 8, 32, 526, pbh=True)
+    items = W.server_items(1 << 20, 32, seed)
+    t0 = time.perf_counter()
+    server = pk.Server(params, items, cache_plaintexts=True)
+    torch.cuda.synchronize()
+    prep = time.perf_counter() - t0
+    q = make_query(params, items, {"item_bits": 32}, 1024, 256, seed + 1)
+    out = torch.zeros((2, L, n), dtype=torch.int64, device="cuda")
+    server.eval(q["cts"], q["rlk"], q["mask"], out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        server.eval(q["cts"], q["rlk"], q["mask"], out)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    slots = torch.zeros((1, n), dtype=torch.int32, device="cuda")
+    params.decrypt(q["sk"], out.reshape(1, 2, L, n), slots)
+    torch.cuda.synchronize()
+    card = int(slots.cpu().numpy().view(np.uint32).astype(np.int64).sum() % 65537)
+    budget = params.noise_budget(q["sk"], out)
+    server.close()
+    if card != 256 or budget <= 0:
+        log(f"[bench] WRONG RESULT with the paper's 32-bit parameters: {card}, budget {budget}")
+        sys.exit(1)
+    return {
+        "workload": "N=8192 L=4 h=8 PBH lambda=32 (lambda_bar=21, ell=27) n=2^20 m=1024 planted=256 mu=526",
+        "ms_per_query": round(1e3 * t, 3),
+        "value": round(n * 526 / t, 1),
+        "unit": "slot-comparisons/s",
+        "offline_s": round(prep, 3),
+        "paper_online_s": 0.83,
+        "check": {"cardinality": card, "noise_budget_bits": budget},
+    }
+
+
 def batched_leg(params, server, server_items, cfg, nq, steps, seed, plain_value):
     """Config 'batched': nq queries, m log-uniform in [64, 2048], 25% planted, one launch sequence."""
     import torch
@@ -319,6 +361,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--seed", type=int, default=2024)
     ap.add_argument("--psi-sum-steps", type=int, default=5, help="steps of the PSI-Sum leg (0: skip it)")
+    ap.add_argument("--paper32-steps", type=int, default=5,
+                    help="steps of the leg with the paper's own 32-bit parameters (0: skip it)")
     ap.add_argument("--serve", type=int, default=500, help="requests in the serving leg (0: skip it)")
     ap.add_argument("--serve-pool", type=int, default=16, help="distinct client queries behind the requests")
     ap.add_argument("--serve-slots", type=int, default=64)
@@ -464,6 +508,9 @@ def main():
     if args.psi_sum_steps > 0 and args.config == "paper":
         server.close()
         line["psi_sum"] = psi_sum_leg(pk, params, server_items, cfg, args.psi_sum_steps, args.seed + 9)
+    if args.paper32_steps > 0 and args.config == "paper":
+        server.close()
+        line["paper32"] = paper32_leg(pk, args.paper32_steps, args.seed + 13)
     if args.serve > 0:
         server.close()
         del cts, rlk, out

@@ -73,13 +73,21 @@ typedef struct {
   uint32_t log_n;          /* N = 2^log_n = number of bins b; 10..14                   */
   uint32_t n_q;            /* L, number of ciphertext primes; 1..8                     */
   uint32_t h;              /* Hamming weight of the constant-weight code; 1..16        */
-  uint32_t item_bits;      /* element bit length (effective bitlength); 1..32          */
+  uint32_t item_bits;      /* element bit length lambda; 1..32                         */
   uint32_t mu;             /* server maximum bin load                                  */
   uint32_t n_hash;         /* number of hash functions k (3 in the paper)             */
   uint32_t max_evictions;  /* cuckoo eviction limit per insertion                     */
-  uint32_t reserved;       /* must be 0                                                */
+  uint32_t flags;          /* 0 or PEPSI_PARAMS_PBH                                    */
   uint64_t hash_seed;      /* seed of the hash functions H_1..H_k                      */
 } pepsi_params_desc;
+
+/* Permutation-based hashing (Sec. 3.3): an element x = x_H || x_L (|x_H| = log_n) is
+ * placed by hash function i in bin x_H ^ H_i(x_L) and stored as the shorter value
+ * (i - 1) 2^(lambda - log_n) + x_L; the code length follows from the stored length
+ * lambda_bar = lambda - log_n + ceil(log2 k) (the hash index is part of the value, so
+ * that equal values in equal bins mean equal elements with k > 1 hash functions).
+ * Needs item_bits > log_n. */
+#define PEPSI_PARAMS_PBH 1u
 
 #define PEPSI_MAX_PRIMES 17
 
@@ -96,6 +104,8 @@ typedef struct {
   uint64_t ct_bytes;       /* 2 * L * N * 8                                            */
   uint64_t rlk_bytes;      /* L * 2 * L * N * 8                                        */
   uint64_t cache_bytes;    /* mu * ell * L * N * 8: the server plaintexts in NTT form  */
+  uint32_t effective_bits; /* lambda_bar: bit length of the stored (encoded) values     */
+  uint32_t flags;          /* as in the descriptor                                     */
 } pepsi_params_info;
 
 /* Creates a parameter set on the current HIP device: primes, NTT tables and RNS
@@ -117,7 +127,8 @@ int pepsi_exact_path_count(const pepsi_params* params, uint64_t* out);
  * hash functions H_i(x) = mix64(x ^ (seed + i * 0x9E3779B97F4A7C15)) mod N,
  * i = 1..k, mix64 the SplitMix64 finaliser; an evicted element moves on to its
  * next hash function cyclically (Sec. 3.3).  table [N] receives the item of
- * each bin, valid [N] 1 for a real item and 0 for a dummy.
+ * each bin (with PEPSI_PARAMS_PBH its stored PBH value), valid [N] 1 for a real
+ * item and 0 for a dummy.
  * Errors: PEPSI_E_RANGE (duplicate / out of range), PEPSI_E_CUCKOO. */
 int pepsi_client_table(const pepsi_params* params, const uint32_t* items, uint64_t m,
                        uint32_t* table, uint8_t* valid);

@@ -16,6 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpepsi.so")
 
+PEPSI_PARAMS_PBH = 1
 PEPSI_SERVER_CACHE_PLAINTEXTS = 1
 MAX_PRIMES = 17
 
@@ -29,7 +30,7 @@ class PepsiError(RuntimeError):
 class ParamsDesc(C.Structure):
     _fields_ = [("log_n", C.c_uint32), ("n_q", C.c_uint32), ("h", C.c_uint32),
                 ("item_bits", C.c_uint32), ("mu", C.c_uint32), ("n_hash", C.c_uint32),
-                ("max_evictions", C.c_uint32), ("reserved", C.c_uint32),
+                ("max_evictions", C.c_uint32), ("flags", C.c_uint32),
                 ("hash_seed", C.c_uint64)]
 
 
@@ -40,7 +41,8 @@ class ParamsInfo(C.Structure):
                 ("primes", C.c_uint64 * MAX_PRIMES), ("psi", C.c_uint64 * MAX_PRIMES),
                 ("psi_t", C.c_uint32), ("q_bits", C.c_uint32),
                 ("query_bytes", C.c_uint64), ("ct_bytes", C.c_uint64),
-                ("rlk_bytes", C.c_uint64), ("cache_bytes", C.c_uint64)]
+                ("rlk_bytes", C.c_uint64), ("cache_bytes", C.c_uint64),
+                ("effective_bits", C.c_uint32), ("flags", C.c_uint32)]
 
 
 class ServerInfo(C.Structure):
@@ -157,8 +159,10 @@ class Params:
     """A parameter set on the current HIP device (pepsi_params_*)."""
 
     def __init__(self, log_n: int, n_q: int, h: int, item_bits: int, mu: int, n_hash: int = 3,
-                 max_evictions: int = 500, hash_seed: int = 0x5EED):
-        d = ParamsDesc(log_n, n_q, h, item_bits, mu, n_hash, max_evictions, 0, hash_seed)
+                 max_evictions: int = 500, hash_seed: int = 0x5EED, pbh: bool = False):
+        """pbh: permutation-based hashing (stored values of lambda - log_n + ceil(log2 k) bits)."""
+        d = ParamsDesc(log_n, n_q, h, item_bits, mu, n_hash, max_evictions, PEPSI_PARAMS_PBH if pbh else 0,
+                       hash_seed)
         h_ = C.c_void_p()
         _check(lib().pepsi_params_create(C.byref(d), C.byref(h_)))
         self._h = h_
@@ -168,6 +172,7 @@ class Params:
         self.n, self.L, self.K = info.n, info.n_q, info.n_aux
         self.h, self.ell, self.mu = info.h, info.ell, info.mu
         self.primes = [int(info.primes[i]) for i in range(self.L + self.K)]
+        self.effective_bits, self.pbh = info.effective_bits, bool(info.flags & PEPSI_PARAMS_PBH)
         self.q_primes = self.primes[:self.L]
 
     @property

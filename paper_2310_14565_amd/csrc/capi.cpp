@@ -174,11 +174,12 @@ int upload_tables(pepsi_params* P) {
 extern "C" int pepsi_params_create(const pepsi_params_desc* d, pepsi_params** out) {
   if (!d || !out) return fail(PEPSI_E_ARG, "null argument");
   *out = nullptr;
-  if (d->reserved) return fail(PEPSI_E_ARG, "reserved must be 0");
+  if (d->flags & ~PEPSI_PARAMS_PBH) return fail(PEPSI_E_ARG, "unknown flags");
   pepsi_params* P = new pepsi_params();
   char err[256] = {0};
   int rc = build_host_params((int)d->log_n, (int)d->n_q, (int)d->h, (int)d->item_bits, (int)d->mu,
-                             (int)d->n_hash, d->hash_seed, (int)d->max_evictions, &P->H, err,
+                             (int)d->n_hash, d->hash_seed, (int)d->max_evictions,
+                             (d->flags & PEPSI_PARAMS_PBH) ? 1 : 0, &P->H, err,
                              sizeof(err));
   if (rc) {
     delete P;
@@ -214,6 +215,8 @@ extern "C" int pepsi_params_get_info(const pepsi_params* P, pepsi_params_info* o
   o->query_bytes = (uint64_t)H.ell * o->ct_bytes;
   o->rlk_bytes = L * o->ct_bytes;
   o->cache_bytes = (uint64_t)H.mu * H.ell * L * n * 8;
+  o->effective_bits = (uint32_t)H.eff_bits;
+  o->flags = H.pbh ? PEPSI_PARAMS_PBH : 0u;
   return PEPSI_OK;
 }
 
@@ -245,7 +248,8 @@ extern "C" int pepsi_client_table(const pepsi_params* P, const uint32_t* items, 
     if (!seen.insert(items[i]).second) return fail(PEPSI_E_RANGE, "duplicate client item");
   }
   if (m > (uint64_t)H.n) return fail(PEPSI_E_CUCKOO, "more items than bins");
-  if (cuckoo_insert(items, m, H.n, H.hash_seed, H.n_hash, H.max_evictions, table, valid))
+  if (cuckoo_insert(items, m, H.n, H.hash_seed, H.n_hash, H.max_evictions, table, valid,
+                    H.pbh ? H.item_bits : 0))
     return fail(PEPSI_E_CUCKOO, "cuckoo insertion exceeded %d evictions", H.max_evictions);
   return PEPSI_OK;
 }
@@ -259,7 +263,7 @@ extern "C" int pepsi_codeword_planes(const pepsi_params* P, const uint32_t* tabl
   std::vector<uint16_t> pos(H.h);
   for (int k = 0; k < H.n; ++k) {
     if (!valid[k]) continue;
-    if (H.item_bits < 32 && (table[k] >> H.item_bits)) return fail(PEPSI_E_RANGE, "item out of range");
+    if (H.eff_bits < 32 && (table[k] >> H.eff_bits)) return fail(PEPSI_E_RANGE, "value out of range");
     enc.encode(table[k], pos.data());
     for (int r = 0; r < H.h; ++r) planes[(size_t)pos[r] * H.n + k] = 1;
   }
@@ -800,7 +804,7 @@ extern "C" int pepsi_server_create_with_values(const pepsi_params* Pc, const uin
   std::vector<uint8_t> valid;
   uint32_t max_load = 0;
   if (simple_hash(items, n, H.n, H.hash_seed, H.n_hash, H.mu, &table, &valid, &max_load,
-                  values ? &index : nullptr))
+                  values ? &index : nullptr, H.pbh ? H.item_bits : 0))
     return fail(PEPSI_E_BIN_OVERFLOW, "a server bin exceeds mu = %d", H.mu);
   std::vector<uint16_t> cw((size_t)H.mu * H.n * H.h, 0xFFFF);
   CwEncoder enc(H.ell, H.h);

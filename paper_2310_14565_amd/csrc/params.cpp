@@ -99,7 +99,7 @@ Prime make_prime(uint64_t p) {
 }  // namespace
 
 int build_host_params(int logn, int L, int h, int item_bits, int mu, int n_hash,
-                      uint64_t hash_seed, int max_evictions, HostParams* out,
+                      uint64_t hash_seed, int max_evictions, int pbh, HostParams* out,
                       char* err, int errlen) {
   if (logn < 10 || logn > 14) { snprintf(err, errlen, "log_n must be in [10, 14]"); return -2; }
   if (L < 1 || L > PEPSI_MAXL) { snprintf(err, errlen, "n_q must be in [1, %d]", PEPSI_MAXL); return -2; }
@@ -113,12 +113,22 @@ int build_host_params(int logn, int L, int h, int item_bits, int mu, int n_hash,
   const int K = L + 1;
   H.n = n; H.logn = logn; H.L = L; H.K = K;
   H.h = h; H.item_bits = item_bits; H.mu = mu; H.n_hash = n_hash;
+  // stored values: the element, or with PBH lambda - log2 N bits plus the hash-function index
+  H.pbh = pbh ? 1 : 0;
+  H.eff_bits = item_bits;
+  if (pbh) {
+    int ib = 0;
+    while ((1 << ib) < n_hash) ++ib;
+    if (item_bits <= logn) { snprintf(err, errlen, "PBH needs item_bits > log_n"); return -2; }
+    H.eff_bits = item_bits - logn + ib;
+    if (H.eff_bits > 32) { snprintf(err, errlen, "PBH values exceed 32 bits"); return -2; }
+  }
   H.hash_seed = hash_seed; H.max_evictions = max_evictions;
 
-  // code length, eq. (1): least l with C(l, h) >= 2^item_bits (C(l, h) grows with l, and
+  // code length, eq. (1): least l with C(l, h) >= 2^lambda_bar (C(l, h) grows with l, and
   // every C(l, r), r <= h, stays below the target until the answer, so u128 cannot overflow)
   {
-    const u128 target = (u128)1 << item_bits;
+    const u128 target = (u128)1 << H.eff_bits;
     int ell = h;
     for (;; ++ell) {
       if (ell > 0xFFFE) { snprintf(err, errlen, "code length exceeds 65534"); return -2; }

@@ -69,6 +69,7 @@ struct Tables {
 struct HostParams {
   int n, logn, L, K;
   int h, ell, mu, item_bits, n_hash, max_evictions;
+  int pbh, eff_bits;   // permutation-based hashing; length of the stored values (lambda_bar)
   uint64_t hash_seed;
   uint64_t primes[PEPSI_MAXP];
   uint64_t psi[PEPSI_MAXP];
@@ -78,5 +79,5 @@ struct HostParams {
 
 // Builds every constant; returns 0 or a negative status with a message.
 int build_host_params(int logn, int L, int h, int item_bits, int mu, int n_hash,
-                      uint64_t hash_seed, int max_evictions, HostParams* out,
+                      uint64_t hash_seed, int max_evictions, int pbh, HostParams* out,
                       char* err, int errlen);

@@ -21,15 +21,31 @@ uint32_t hash_bin(uint64_t x, int i, uint64_t seed, uint32_t nbins) {
   return (uint32_t)(mix64(x ^ (seed + (uint64_t)i * 0x9E3779B97F4A7C15ull)) % nbins);
 }
 
+void place(uint32_t x, int i, uint64_t seed, uint32_t nbins, int pbh_bits, uint32_t* bin, uint32_t* value) {
+  if (!pbh_bits) {
+    *bin = hash_bin(x, i, seed, nbins);
+    *value = x;
+    return;
+  }
+  int c = 0;
+  while ((1u << c) < nbins) ++c;
+  const int low = pbh_bits - c;
+  const uint32_t xl = low >= 32 ? x : (x & ((1u << low) - 1));
+  const uint32_t xh = low >= 32 ? 0 : (x >> low);
+  *bin = xh ^ hash_bin(xl, i, seed, nbins);
+  *value = ((uint32_t)(i - 1) << low) | xl;
+}
+
 int cuckoo_insert(const uint32_t* items, uint64_t m, uint32_t nbins, uint64_t seed, int k,
-                  int max_evictions, uint32_t* table, uint8_t* valid) {
+                  int max_evictions, uint32_t* table, uint8_t* valid, int pbh_bits) {
   std::vector<uint8_t> which(nbins, 0);   // hash function (1..k) an occupant sits under; 0 = empty
   for (uint32_t b = 0; b < nbins; ++b) { table[b] = 0; valid[b] = 0; }
   for (uint64_t n = 0; n < m; ++n) {
     uint32_t cur = items[n];
     int idx = 1, evictions = 0;
     for (;;) {
-      const uint32_t pos = hash_bin(cur, idx, seed, nbins);
+      uint32_t pos, val;
+      place(cur, idx, seed, nbins, pbh_bits, &pos, &val);
       if (!which[pos]) {
         table[pos] = cur;
         which[pos] = (uint8_t)idx;
@@ -45,30 +61,38 @@ int cuckoo_insert(const uint32_t* items, uint64_t m, uint32_t nbins, uint64_t se
       if (++evictions > max_evictions) return -3;
     }
   }
+  if (pbh_bits)                            // the table keeps the elements until here
+    for (uint32_t b = 0; b < nbins; ++b)
+      if (which[b]) {
+        uint32_t pos;
+        place(table[b], which[b], seed, nbins, pbh_bits, &pos, &table[b]);
+      }
   return 0;
 }
 
 int simple_hash(const uint32_t* items, uint64_t n, uint32_t nbins, uint64_t seed, int k, uint32_t mu,
                 std::vector<uint32_t>* table, std::vector<uint8_t>* valid, uint32_t* max_load,
-                std::vector<uint32_t>* index) {
+                std::vector<uint32_t>* index, int pbh_bits) {
   std::vector<uint32_t> load(nbins, 0);
   table->assign((size_t)mu * nbins, 0);
   valid->assign((size_t)mu * nbins, 0);
   if (index) index->assign((size_t)mu * nbins, 0);
-  uint32_t bins[8];
+  uint32_t bins[8], vals[8];
   for (uint64_t e = 0; e < n; ++e) {
     const uint32_t y = items[e];
     int nb = 0;
     for (int i = 1; i <= k; ++i) {
-      const uint32_t b = hash_bin(y, i, seed, nbins);
+      uint32_t b, v;
+      place(y, i, seed, nbins, pbh_bits, &b, &v);
       bool dup = false;
-      for (int q = 0; q < nb; ++q) dup |= bins[q] == b;
-      if (!dup) bins[nb++] = b;
+      if (!pbh_bits)
+        for (int q = 0; q < nb; ++q) dup |= bins[q] == b;
+      if (!dup) { bins[nb] = b; vals[nb] = v; ++nb; }
     }
     for (int q = 0; q < nb; ++q) {
       const uint32_t b = bins[q];
       if (load[b] >= mu) return -4;
-      (*table)[(size_t)load[b] * nbins + b] = y;
+      (*table)[(size_t)load[b] * nbins + b] = vals[q];
       (*valid)[(size_t)load[b] * nbins + b] = 1;
       if (index) (*index)[(size_t)load[b] * nbins + b] = (uint32_t)e;
       ++load[b];

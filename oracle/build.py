@@ -6,7 +6,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["poly.c", "bignum.c", "bfv.c", "server.c"]
+SOURCES = ["poly.c", "bignum.c", "bfv.c", "server.c", "compress.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 
 

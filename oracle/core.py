@@ -57,6 +57,10 @@ def lib():
             "or_select_sum": (None, [vp, i, i, u64p, u16p, u64p]),
             "or_server_batch": (None, [vp, i, i, u64p, u16p, u64p, u64p]),
             "or_server_eval": (None, [vp, i, i, i, i, u64p, u16p, u64p, vp, vp, i, u64p]),
+            "or_chacha_quarter": (None, [C.POINTER(C.c_uint32)] * 4),
+            "or_chacha20_block": (None, [u32p, C.c_uint32, u32p, u32p]),
+            "or_expand_uniform": (None, [vp, C.c_char_p, i, i, u64p, C.c_size_t]),
+            "or_mod_switch": (None, [vp, u64p, u64p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -215,6 +219,19 @@ class Context:
                              None if v is None else v.ctypes.data, 1 if finalize else 0, out)
         return out
 
+    def expand_uniform(self, seed: bytes, first: int, count: int):
+        """a_j, j in [first, first + count), [count][L][N], from a 32-byte seed (ChaCha20)."""
+        assert len(seed) == 32
+        out = np.zeros((count, self.L, self.n), dtype=np.uint64)
+        lib().or_expand_uniform(self._h, seed, first, count, out, self.L * self.n)
+        return out
+
+    def mod_switch(self, ct):
+        """[round(q_0 X / Q)]_{q_0} of every coefficient of ct [2][L][N] -> [2][N]."""
+        out = np.zeros((2, self.n), dtype=np.uint64)
+        lib().or_mod_switch(self._h, _c(ct, np.uint64), out)
+        return out
+
     # integer views used by the pins
     def residues_to_int(self, res):
         """CRT of one coefficient's residues (list of L ints) -> integer in [0, Q)."""
@@ -234,3 +251,15 @@ class Context:
         for l, q in enumerate(self.primes):
             out[l] = [int(v) % q for v in ints]
         return out
+
+
+def chacha_quarter(a: int, b: int, c: int, d: int):
+    v = [C.c_uint32(x) for x in (a, b, c, d)]
+    lib().or_chacha_quarter(*[C.byref(x) for x in v])
+    return tuple(x.value for x in v)
+
+
+def chacha20_block(key_words, counter: int, nonce_words):
+    out = np.zeros(16, dtype=np.uint32)
+    lib().or_chacha20_block(_c(key_words, np.uint32), counter, _c(nonce_words, np.uint32), out)
+    return out

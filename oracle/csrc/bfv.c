@@ -64,6 +64,8 @@ static void crt_centred(const or_ctx* c, const uint64_t* res, bn* x) {
   bn twice; bn_shl1(&twice, x);
   if (bn_cmp(&twice, &c->Q) > 0) bn_sub(x, x, &c->Q);
 }
+void or_crt_centred(const or_ctx* c, const uint64_t* res, bn* x) { crt_centred(c, res, x); }
+
 /* gather the L residues of coefficient i of a limb-major polynomial */
 static void gather(const or_ctx* c, const uint64_t* poly, int i, uint64_t* res) {
   for (int l = 0; l < c->L; l++) res[l] = poly[(size_t)l * c->n + i];

@@ -27,4 +27,7 @@ static inline uint64_t smod(int64_t v, uint64_t m) {
 static inline int64_t centre_t(uint64_t v, uint64_t t) {
   return v <= (t - 1) / 2 ? (int64_t)v : (int64_t)v - (int64_t)t;
 }
+/* centred CRT lift of one coefficient's residues (bfv.c) */
+void or_crt_centred(const or_ctx* c, const uint64_t* res, bn* x);
+
 #endif

@@ -108,4 +108,17 @@ void or_server_eval(const or_ctx* c, int ell, int h, int mu_begin, int mu_end,
                     const uint64_t* cts, const uint16_t* cw_table,
                     const uint64_t* rlk, const uint32_t* mask, const uint32_t* vals,
                     int finalize, uint64_t* out);
+/* ---- request and response compression (compress.c) ---- */
+/* RFC 8439 ChaCha20 quarter round and block function. */
+void or_chacha_quarter(uint32_t* a, uint32_t* b, uint32_t* c, uint32_t* d);
+void or_chacha20_block(const uint32_t key[8], uint32_t counter, const uint32_t nonce[3], uint32_t out[16]);
+/* The uniform polynomials a_j, j in [first, first + count), expanded from a 32-byte seed:
+ * a_{j,l}[k] = (16 keystream bytes of ChaCha20(seed, nonce (j, l, 0)) at 16k, LE) mod q_l;
+ * out[(j - first) * stride + l * N + k]. */
+void or_expand_uniform(const or_ctx* c, const uint8_t seed[32], int first, int count, uint64_t* out,
+                       size_t stride);
+/* Modulus switching to q_0: out[c][k] = [round(q_0 X / Q)]_{q_0}, X the centred lift of
+ * coefficient k of component c of ct [2][L][N]. */
+void or_mod_switch(const or_ctx* c, const uint64_t* ct, uint64_t* out);
+
 #endif

@@ -245,6 +245,26 @@ int pepsi_server_eval_batch(pepsi_server* server, uint32_t nq, const uint64_t* c
                             uint64_t* const* d_out, void* stream);
 
 /* ------------------------------------------------------------------ */
+/* Request and response compression (the request / response sizes of  */
+/* Table "dipsi-cpsi")                                                 */
+/* ------------------------------------------------------------------ */
+/* The c1 part of a secret-key ciphertext is the uniform polynomial a, so a request can
+ * carry a 32-byte seed instead of its ell c1 polynomials (half the request).  Both sides
+ * expand a_j for ciphertext index j: a_{j,l}[k] = W mod q_l, W = the 16 bytes at offset 16 k
+ * of the ChaCha20 keystream (RFC 8439; key = seed as 8 little-endian words, nonce = (j, l, 0),
+ * block counter from 0), read little-endian (bias below 2^-74).  Writes a_j, j in
+ * [first, first + count), at d_out + (j - first) * out_stride words, each [L][N]
+ * (out_stride = L * N for a plain array; 2 * L * N with d_out = d_cts + L * N fills the c1
+ * halves of a request [ell][2][L][N]).  Errors: PEPSI_E_ARG. */
+int pepsi_expand_uniform(const pepsi_params* params, const uint8_t* seed, uint32_t first, uint32_t count,
+                         uint64_t* d_out, uint64_t out_stride, void* stream);
+/* Modulus switching of a response to the first prime: d_out [2][N] =
+ * [round(q_0 X / Q)]_{q_0} for the centred lift X of every coefficient of d_ct [2][L][N]
+ * (coefficient form), computed exactly; it decrypts under q_0 alone (a quarter of the
+ * response at L = 4). */
+int pepsi_mod_switch(const pepsi_params* params, const uint64_t* d_ct, uint64_t* d_out, void* stream);
+
+/* ------------------------------------------------------------------ */
 /* Serving: continuous batching over one prepared server               */
 /* ------------------------------------------------------------------ */
 /* A serving handle runs a worker thread with its own HIP stream.  The server

@@ -89,6 +89,9 @@ _SIGS = {
     "pepsi_server_eval_batch": (C.c_int, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p,
                                           C.c_void_p, C.c_void_p]),
     "pepsi_clock": (C.c_double, []),
+    "pepsi_expand_uniform": (C.c_int, [C.c_void_p, C.c_char_p, C.c_uint32, C.c_uint32, C.c_void_p, C.c_uint64,
+                                       C.c_void_p]),
+    "pepsi_mod_switch": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pepsi_serve_create": (C.c_int, [C.c_void_p, C.c_uint32, C.c_uint64, C.POINTER(C.c_void_p)]),
     "pepsi_serve_submit": (C.c_int, [C.c_void_p] * 5 + [C.POINTER(C.c_uint64)]),
     "pepsi_serve_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_int), C.POINTER(ReqStats)]),
@@ -220,6 +223,23 @@ class Params:
     def decrypt(self, sk, ct, out_slots, stream=None):
         count = ct.shape[0] if ct.dim() == 4 else 1
         _check(lib().pepsi_decrypt(self._h, _dev(sk), _dev(ct), count, _dev(out_slots), _stream(stream)))
+
+    def expand_uniform(self, seed: bytes, first: int, count: int, out, out_stride: int | None = None,
+                       offset_words: int = 0, stream=None):
+        """a_j for j in [first, first + count) from a 32-byte seed (ChaCha20) into the device tensor
+        out, at word offset_words + j * out_stride (default a plain [count][L][N] array; pass
+        out_stride = 2 L N and offset_words = L N to fill the c1 halves of a request)."""
+        if len(seed) != 32:
+            raise ValueError("seed must be 32 bytes")
+        stride = self.L * self.n if out_stride is None else out_stride
+        if offset_words + (count - 1) * stride + self.L * self.n > out.numel() and count > 0:
+            raise ValueError("output tensor too small")
+        ptr = C.c_void_p(_dev(out).value + 8 * offset_words)
+        _check(lib().pepsi_expand_uniform(self._h, seed, first, count, ptr, stride, _stream(stream)))
+
+    def mod_switch(self, ct, out, stream=None):
+        """out [2][N] = the response ct [2][L][N] switched to the first prime."""
+        _check(lib().pepsi_mod_switch(self._h, _dev(ct), _dev(out), _stream(stream)))
 
     def noise_budget(self, sk, ct, stream=None) -> int:
         b = C.c_int32()

@@ -1218,6 +1218,29 @@ extern "C" void pepsi_serve_destroy(pepsi_serve* sr) {
   delete sr;
 }
 
+// ------------------------------------------------------------------ compression
+extern "C" int pepsi_expand_uniform(const pepsi_params* P, const uint8_t* seed, uint32_t first, uint32_t count,
+                                    uint64_t* out, uint64_t out_stride, void* stream) {
+  if (!P || !seed || (!out && count)) return fail(PEPSI_E_ARG, "null argument");
+  const HostParams& H = P->H;
+  if (count && out_stride < (uint64_t)H.L * H.n) return fail(PEPSI_E_ARG, "stride below L * N");
+  if ((uint64_t)first + count > 0xFFFFFFFFull) return fail(PEPSI_E_ARG, "index range exceeds 32 bits");
+  ChaChaKey key;
+  for (int i = 0; i < 8; ++i)
+    key.k[i] = (uint32_t)seed[4 * i] | (uint32_t)seed[4 * i + 1] << 8 | (uint32_t)seed[4 * i + 2] << 16 |
+               (uint32_t)seed[4 * i + 3] << 24;
+  expand_uniform(P->T, H.consts, key, (int)first, (int)count, out, (long)out_stride, S(stream));
+  HIPCHK(hipGetLastError());
+  return PEPSI_OK;
+}
+
+extern "C" int pepsi_mod_switch(const pepsi_params* P, const uint64_t* ct, uint64_t* out, void* stream) {
+  if (!P || !ct || !out) return fail(PEPSI_E_ARG, "null argument");
+  mod_switch(P->T, P->H.consts, ct, out, S(stream));
+  HIPCHK(hipGetLastError());
+  return PEPSI_OK;
+}
+
 // ------------------------------------------------------------------ single steps
 extern "C" int pepsi_ntt(const pepsi_params* P, uint64_t* data, uint32_t rows, uint32_t first,
                          uint32_t nprimes, int inverse, void* stream) {

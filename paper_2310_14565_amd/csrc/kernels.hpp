@@ -84,6 +84,13 @@ void accumulate(const Tables& T, const Consts& hc, const uint64_t* x, long xstri
 // [nb][L][N], the server-value plaintexts of the batches; x entries xstride words apart).
 void value_accumulate(const Tables& T, const Consts& hc, const uint64_t* x, long xstride, const uint64_t* vhat,
                       int nb, int nq, const int* qslot, uint64_t* acc, long astride, hipStream_t s);
+// Request compression: out[j * stride + l * N + k] = a_{first + j, l}[k] for j < count, the
+// uniform polynomials expanded from a 32-byte seed with ChaCha20 (key words little-endian).
+struct ChaChaKey { uint32_t k[8]; };
+void expand_uniform(const Tables& T, const Consts& hc, const ChaChaKey& key, int first, int count,
+                    uint64_t* out, long stride, hipStream_t s);
+// Response compression: out [2][N] = [round(q_0 X / Q)]_{q_0} of every coefficient X of ct [2][L][N].
+void mod_switch(const Tables& T, const Consts& hc, const uint64_t* ct, uint64_t* out, hipStream_t s);
 // select-and-sum: S[b][c][l][k] = sum_j C[j][c][l][k] * P[b][j][l][k] mod q_l.
 // C: NTT form [ell][2][L][N]; P: split-27 NTT form [nb][ell][L][N]; S rows of stride sstride.
 void select_sum(const Tables& T, const Consts& hc, const uint64_t* C, const uint64_t* P, int ell,

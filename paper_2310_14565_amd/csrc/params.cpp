@@ -235,5 +235,18 @@ int build_host_params(int logn, int L, int h, int item_bits, int mu, int n_hash,
     C.t_over_q[i] = frac128(PEPSI_T, q[i]);
     C.t_mod_q[i] = PEPSI_T % q[i];
   }
+
+  // modulus switching to q_0
+  mw_set(C.sw_Qw, 1);
+  for (int i = 1; i < L; ++i) mw_mul_small(C.sw_Qw, q[i]);
+  for (int i = 1; i < L; ++i) {
+    MWord h; mw_set(h, 1);
+    for (int k = 1; k < L; ++k) if (k != i) mw_mul_small(h, q[k]);
+    C.sw_hat_w[i - 1] = h;
+    C.sw_hat_inv[i - 1] = invm(mw_mod_small(h, q[i]), q[i]);
+    C.sw_hat_mod_q0[i - 1] = mw_mod_small(h, q[0]);
+  }
+  C.sw_q_mod_q0 = mw_mod_small(C.sw_Qw, q[0]);
+  C.sw_qinv_q0 = invm(C.sw_q_mod_q0, q[0]);
   return 0;
 }

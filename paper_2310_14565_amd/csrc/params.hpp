@@ -52,6 +52,12 @@ struct Consts {
   // multiword constants of the exact (multi-precision) path
   MWord Qw, Bw;                               // Q, B
   MWord qhat_w[PEPSI_MAXL], bhat_w[PEPSI_MAXK];// Q/q_i, B/b_j
+
+  // modulus switching to q_0 over Q' = q_1 ... q_{L-1} (entry i - 1 for prime q_i)
+  MWord sw_hat_w[PEPSI_MAXL], sw_Qw;          // Q'/q_i, Q'
+  uint64_t sw_hat_inv[PEPSI_MAXL];            // (Q'/q_i)^-1 mod q_i
+  uint64_t sw_hat_mod_q0[PEPSI_MAXL];         // (Q'/q_i) mod q_0
+  uint64_t sw_q_mod_q0, sw_qinv_q0;           // Q' mod q_0, Q'^-1 mod q_0
 };
 
 // Device-resident tables (all device pointers).

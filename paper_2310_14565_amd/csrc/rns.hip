@@ -624,6 +624,90 @@ __global__ void __launch_bounds__(MTPB) k_select_sum_multi(Tables T, const uint6
               fold3(lo[a][c][b], ms[a][c][b], hi[a][c][b], pr);
 }
 
+// Seeded uniform polynomials (request compression): a_{j,l}[k] = W mod q_l, W the 16 bytes
+// of the ChaCha20 keystream (RFC 8439; key = the seed, nonce = (j, l, 0)) at 16 k, little-
+// endian.  Thread = one 64-byte block = 4 coefficients.
+__device__ __forceinline__ uint32_t rotl32(uint32_t x, int r) { return (x << r) | (x >> (32 - r)); }
+__device__ __forceinline__ void chacha_qr(uint32_t& a, uint32_t& b, uint32_t& c, uint32_t& d) {
+  a += b; d ^= a; d = rotl32(d, 16);
+  c += d; b ^= c; b = rotl32(b, 12);
+  a += b; d ^= a; d = rotl32(d, 8);
+  c += d; b ^= c; b = rotl32(b, 7);
+}
+__global__ void __launch_bounds__(TPB) k_expand_uniform(Tables T, ChaChaKey key, int first,
+                                                       uint64_t* __restrict__ out, long stride) {
+  const Consts& C = *T.c;
+  const int N = C.n;
+  const int blk = blockIdx.x * TPB + threadIdx.x;    // keystream block = coefficients 4 blk ..
+  const int l = blockIdx.y;
+  const int jj = blockIdx.z;
+  if (4 * blk >= N) return;
+  uint32_t s[16] = {0x61707865u, 0x3320646eu, 0x79622d32u, 0x6b206574u};
+#pragma unroll
+  for (int i = 0; i < 8; ++i) s[4 + i] = key.k[i];
+  s[12] = (uint32_t)blk;
+  s[13] = (uint32_t)(first + jj);
+  s[14] = (uint32_t)l;
+  s[15] = 0;
+  uint32_t x[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) x[i] = s[i];
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    chacha_qr(x[0], x[4], x[8], x[12]);
+    chacha_qr(x[1], x[5], x[9], x[13]);
+    chacha_qr(x[2], x[6], x[10], x[14]);
+    chacha_qr(x[3], x[7], x[11], x[15]);
+    chacha_qr(x[0], x[5], x[10], x[15]);
+    chacha_qr(x[1], x[6], x[11], x[12]);
+    chacha_qr(x[2], x[7], x[8], x[13]);
+    chacha_qr(x[3], x[4], x[9], x[14]);
+  }
+  const Prime& pr = C.prm[l];
+  uint64_t* o = out + (size_t)jj * stride + (size_t)l * N + 4 * blk;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const uint64_t lo = (uint64_t)(x[4 * c] + s[4 * c]) | (uint64_t)(x[4 * c + 1] + s[4 * c + 1]) << 32;
+    const uint64_t hi = (uint64_t)(x[4 * c + 2] + s[4 * c + 2]) | (uint64_t)(x[4 * c + 3] + s[4 * c + 3]) << 32;
+    o[c] = reduce128(lo, hi, pr);
+  }
+}
+
+// Modulus switching to q_0 (response compression): out = [round(q_0 X / Q)]_{q_0} for the
+// centred lift X of each coefficient.  With Q' = Q / q_0 this is (X - [X]_{Q'}) / Q', and
+// [X]_{Q'} mod q_0 follows from the exact CRT over q_1..q_{L-1} (v reductions by Q', then the
+// centring) -- no rounding estimate is involved.  ct [2][L][N] -> out [2][N].
+template <int L>
+__global__ void __launch_bounds__(TPB) k_mod_switch(Tables T, const uint64_t* __restrict__ ct,
+                                                   uint64_t* __restrict__ out) {
+  const Consts& C = *T.c;
+  const int N = C.n;
+  const int k = blockIdx.x * TPB + threadIdx.x;
+  const int comp = blockIdx.y;
+  if (k >= N) return;
+  const Prime& p0 = C.prm[0];
+  const uint64_t x0 = ct[((size_t)comp * L) * N + k];
+  uint64_t res = x0;
+  if (L > 1) {
+    uint64_t y[L > 1 ? L - 1 : 1];
+    u128 acc = 0;
+#pragma unroll
+    for (int i = 1; i < L; ++i) {
+      const uint64_t xi = ct[((size_t)comp * L + i) * N + k];
+      y[i - 1] = mulmod(xi, C.sw_hat_inv[i - 1], C.prm[i]);
+      acc += (u128)y[i - 1] * C.sw_hat_mod_q0[i - 1];
+    }
+    bool gt;
+    const int v = crt_exact(y, L - 1, C.sw_hat_w, C.sw_Qw, &gt, nullptr);
+    // [X]_{Q'} mod q_0 = sum y_i (Q'/q_i) - (v + gt) Q'   (mod q_0)
+    uint64_t r = reduce128((uint64_t)acc, (uint64_t)(acc >> 64), p0);
+    const uint64_t sub = mulmod((uint64_t)(v + (gt ? 1 : 0)) % p0.p, C.sw_q_mod_q0, p0);
+    r = submod(r, sub, p0.p);
+    res = mulmod(submod(x0, r, p0.p), C.sw_qinv_q0, p0);
+  }
+  out[(size_t)comp * N + k] = res;
+}
+
 __global__ void __launch_bounds__(TPB) k_pointwise(Tables T, const uint64_t* __restrict__ a,
                                                   const uint64_t* __restrict__ b, uint64_t* __restrict__ out,
                                                   int nprimes, int bcast) {
@@ -876,6 +960,15 @@ void value_accumulate(const Tables& T, const Consts& hc, const uint64_t* x, long
   if (nb <= 0 || nq <= 0) return;
   hipLaunchKernelGGL(k_value_accumulate, grid_for(hc.n, 2 * hc.L, nq), dim3(TPB), 0, s, T, x, xstride, vhat, nb,
                      nq, qslot, acc, astride);
+}
+void expand_uniform(const Tables& T, const Consts& hc, const ChaChaKey& key, int first, int count,
+                    uint64_t* out, long stride, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_expand_uniform, grid_for(hc.n / 4, hc.L, count), dim3(TPB), 0, s, T, key, first, out,
+                     stride);
+}
+void mod_switch(const Tables& T, const Consts& hc, const uint64_t* ct, uint64_t* out, hipStream_t s) {
+  PEPSI_L_LAUNCH(k_mod_switch, hc.L, grid_for(hc.n, 2), dim3(TPB), s, T, ct, out);
 }
 void select_sum(const Tables& T, const Consts& hc, const uint64_t* Cn, const uint64_t* P, int ell,
                 int nb, uint64_t* S, long sstride, hipStream_t s) {

@@ -226,6 +226,38 @@ def serving_leg(pk, requests, pool, slots, load, seed):
     }
 
 
+def compression_leg(params, response, seed):
+    """Request sent as its c0 halves plus a 32-byte seed (the server expands the c1 halves with
+    ChaCha20), response switched to one prime: sizes and the GPU time of both steps."""
+    import torch
+    import workload as W
+    n, L, ell = params.n, params.L, params.ell
+    key = bytes(W.rng(seed, "request-seed").integers(0, 256, 32, dtype=np.uint8))
+    req = torch.empty((ell, 2, L, n), dtype=torch.int64, device="cuda")
+    small = torch.empty((2, n), dtype=torch.int64, device="cuda")
+    params.expand_uniform(key, 0, ell, req, out_stride=2 * L * n, offset_words=L * n)
+    params.mod_switch(response, small)
+    torch.cuda.synchronize()
+    a, b, c = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    a.record()
+    for _ in range(5):
+        params.expand_uniform(key, 0, ell, req, out_stride=2 * L * n, offset_words=L * n)
+    b.record()
+    for _ in range(5):
+        params.mod_switch(response, small)
+    c.record()
+    torch.cuda.synchronize()
+    del req
+    return {
+        "request_bytes": ell * 2 * L * n * 8,
+        "compressed_request_bytes": ell * L * n * 8 + 32,
+        "expand_ms": round(a.elapsed_time(b) / 5, 3),
+        "response_bytes": 2 * L * n * 8,
+        "switched_response_bytes": 2 * n * 8,
+        "mod_switch_ms": round(b.elapsed_time(c) / 5, 4),
+    }
+
+
 def psi_sum_leg(pk, params, server_items, cfg, steps, seed):
     """PSI-Sum (Alg. 5) on the same workload: server values uniform 12-bit, plaintexts cached."""
     import torch
@@ -493,6 +525,7 @@ def main():
         "server_max_load": server.max_load,
         "check": {"cardinality": card, "noise_budget_bits": budget},
     }
+    line["compression"] = compression_leg(params, out, args.seed + 17)
     if args.copy_calibration > 0:
         words = (args.copy_calibration << 20) // 8
         src = torch.ones(words, dtype=torch.int64, device="cuda")

@@ -99,6 +99,36 @@ __device__ __noinline__ uint64_t exact_round_b(const Consts& C, const uint64_t* 
   return v;
 }
 
+// Sums of products of residues below 2^54, without 128-bit carries: a = a1 2^27 + a0 and
+// w = w1 2^27 + w0 give a w = a0 w0 + (a0 w1 + a1 w0) 2^27 + a1 w1 2^54, and the middle term is
+// (a0 + a1)(w0 + w1) - a0 w0 - a1 w1 (Karatsuba), so three 64-bit accumulators of 32 x 32-bit
+// products hold a sum of up to 16 products exactly (each term below 2^56).  The splits of the
+// wave-uniform constants w stay on the scalar unit.
+struct Split27 { uint32_t lo, hi, s; };
+__device__ __forceinline__ Split27 split27(uint64_t x) {
+  Split27 r;
+  r.lo = (uint32_t)(x & ((1ull << 27) - 1));
+  r.hi = (uint32_t)(x >> 27);
+  r.s = r.lo + r.hi;
+  return r;
+}
+struct Acc3 {
+  uint64_t lo = 0, ms = 0, hi = 0;
+  __device__ __forceinline__ void mac(const Split27& a, uint64_t w) {
+    const uint32_t w0 = (uint32_t)(w & ((1ull << 27) - 1)), w1 = (uint32_t)(w >> 27);
+    lo += (uint64_t)a.lo * w0;
+    hi += (uint64_t)a.hi * w1;
+    ms += (uint64_t)a.s * (w0 + w1);
+  }
+  // adds a plain integer (below 2^60 here) to the value, not to the middle term
+  __device__ __forceinline__ void add(uint64_t v) { lo += v; ms += v; }
+  __device__ __forceinline__ uint64_t reduce(const Prime& pr) const {
+    const uint64_t mid = ms - lo - hi;
+    const u128 v = (u128)lo + ((u128)mid << 27) + ((u128)hi << 54);   // below 2^112
+    return reduce116((uint64_t)v, (uint64_t)(v >> 64), pr);
+  }
+};
+
 // Centred lift of x (residues mod q_0..q_{L-1}) into the residues mod b_0..b_{K-1}, K = L + 1.
 template <int L>
 __device__ __forceinline__ void ext_one(const Consts& C, const uint64_t* x, uint64_t* out,
@@ -114,13 +144,17 @@ __device__ __forceinline__ void ext_one(const Consts& C, const uint64_t* x, uint
   bool amb;
   uint64_t v = fix_round(a, L, &amb);
   if (amb) v = exact_round_q<L>(C, y, fallback);
+  Split27 ys[L];
+#pragma unroll
+  for (int i = 0; i < L; ++i) ys[i] = split27(y[i]);
 #pragma unroll
   for (int j = 0; j < K; ++j) {
     const Prime& P = C.prm[L + j];
-    u128 acc = (u128)v * (P.p - C.q_mod_b[j]);
+    Acc3 acc;
+    acc.mac(split27(v), P.p - C.q_mod_b[j]);
 #pragma unroll
-    for (int i = 0; i < L; ++i) acc += (u128)y[i] * C.qhat_mod_b[i][j];
-    out[j] = reduce116((uint64_t)acc, (uint64_t)(acc >> 64), P);
+    for (int i = 0; i < L; ++i) acc.mac(ys[i], C.qhat_mod_b[i][j]);
+    out[j] = acc.reduce(P);
   }
 }
 
@@ -297,25 +331,35 @@ __global__ void __launch_bounds__(TPB) k_scale_round(Tables T, const uint64_t* _
   // z_j = round(t d / Q) mod b_j
   uint64_t yb[K];
   FixAcc fb{0, 0};
+  Split27 yq[L];
+#pragma unroll
+  for (int i = 0; i < L; ++i) yq[i] = split27(y[i]);
 #pragma unroll
   for (int j = 0; j < K; ++j) {
     const Prime& pr = C.prm[L + j];
-    u128 acc = (u128)y[L + j] * C.tbhat_mod_b[j] + R;
+    Acc3 acc;
+    acc.mac(split27(y[L + j]), C.tbhat_mod_b[j]);
+    acc.add(R);
 #pragma unroll
-    for (int i = 0; i < L; ++i) acc += (u128)y[i] * C.omega_mod_b[i][j];
-    const uint64_t zj = reduce116((uint64_t)acc, (uint64_t)(acc >> 64), pr);
+    for (int i = 0; i < L; ++i) acc.mac(yq[i], C.omega_mod_b[i][j]);
+    const uint64_t zj = acc.reduce(pr);
     yb[j] = shoup(zj, C.bhat_inv[j], C.bhat_inv_shoup[j], pr.p);
     fix_add(fb, yb[j], C.inv_b[j]);
   }
   uint64_t v = fix_round(fb, K, &amb);
   if (amb) v = exact_round_b<K>(C, yb, fallback);
+  Split27 ybs[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) ybs[j] = split27(yb[j]);
+  const Split27 vs = split27(v);
 #pragma unroll
   for (int i = 0; i < L; ++i) {
     const Prime& pr = C.prm[i];
-    u128 acc = (u128)v * (pr.p - C.b_mod_q[i]);
+    Acc3 acc;
+    acc.mac(vs, pr.p - C.b_mod_q[i]);
 #pragma unroll
-    for (int j = 0; j < K; ++j) acc += (u128)yb[j] * C.bhat_mod_q[j][i];
-    dst[(size_t)i * N + k] = reduce116((uint64_t)acc, (uint64_t)(acc >> 64), pr);
+    for (int j = 0; j < K; ++j) acc.mac(ybs[j], C.bhat_mod_q[j][i]);
+    dst[(size_t)i * N + k] = acc.reduce(pr);
   }
 }
 

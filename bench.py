@@ -58,7 +58,7 @@ def select_sum_source_digest() -> str:
     """SHA-256 of the select-and-sum kernel's source (its constants, helper, kernel body and launcher):
     hardware byte counts taken for one version of the kernel are void for any other."""
     src = open(os.path.join(ROOT, "paper_2310_14565_amd", "csrc", "rns.hip")).read()
-    a = src.index("constexpr int IB = 8;")
+    a = src.index("constexpr int IB = ")
     z = src.index("// Select-and-sum of several queries")
     la = src.index("void select_sum(const Tables& T")
     lz = src.index("\n}\n", la) + 3
@@ -70,8 +70,11 @@ def traffic_record(kernel: str):
     path = os.path.join(ROOT, "profiles", f"{kernel}_traffic.json")
     if not os.path.exists(path):
         return None
-    rec = json.load(open(path))
-    if rec.get("source_sha256") != select_sum_source_digest():
+    try:
+        rec = json.load(open(path))
+        if rec.get("source_sha256") != select_sum_source_digest():
+            return None
+    except (OSError, ValueError):
         return None
     return rec
 

@@ -482,7 +482,7 @@ __global__ void __launch_bounds__(TPB) k_value_accumulate(Tables T, const uint64
 // lo + (ms - lo - hi) 2^27 + hi 2^54 is reduced and restarts both lo and ms (hi restarts at 0).
 // Loads of a partial group are clamped to its last batch so that every load is unconditional
 // (results of padding lanes are dropped).
-constexpr int IB = 8;
+constexpr int IB = 16;
 constexpr int FOLD = 254;
 __device__ __forceinline__ uint64_t fold3(uint64_t lo, uint64_t ms, uint64_t hi, const Prime& pr) {
   const uint64_t mid = ms - lo - hi;

@@ -34,6 +34,28 @@ PEPSI_HD uint64_t shoup_lazy(uint64_t x, uint64_t w, uint64_t wq, uint64_t p) {
   uint64_t q = mulhi64(x, wq);
   return x * w - q * p;
 }
+// As shoup_lazy, with the quotient taken from the three partial products of x wq that reach its
+// top word: the low halves of the two cross products and all of the lowest product are dropped,
+// so the quotient is at most 2 short and the result lies in [0, 4p). The product is formed mod
+// 2^64 from 32-bit halves as x w + q (2^64 - p): three 32 x 32 -> 64 multiply-adds for the low
+// word, and the high word collects the four cross products' low halves. The empty asm keeps the
+// halves of x opaque, so that the compiler does not fold them back into a 64-bit multiply.
+PEPSI_HD uint64_t shoup_lazy4(uint64_t x, uint64_t w, uint64_t wq, uint64_t p) {
+  uint32_t x0 = (uint32_t)x, x1 = (uint32_t)(x >> 32);
+#if defined(__HIP_DEVICE_COMPILE__)
+  __asm__("" : "+v"(x0), "+v"(x1));
+#endif
+  const uint32_t c0 = (uint32_t)wq, c1 = (uint32_t)(wq >> 32);
+  const uint64_t hs = (((uint64_t)x1 * c0) >> 32) + (((uint64_t)x0 * c1) >> 32);
+  const uint64_t q = (uint64_t)x1 * c1 + hs;
+  const uint64_t n = 0 - p;
+  const uint32_t w0 = (uint32_t)w, w1 = (uint32_t)(w >> 32), n0 = (uint32_t)n, n1 = (uint32_t)(n >> 32);
+  const uint32_t q0 = (uint32_t)q, q1 = (uint32_t)(q >> 32);
+  uint64_t r = (uint64_t)x0 * w0;
+  r += (uint64_t)q0 * n0;
+  const uint32_t hi = (uint32_t)(r >> 32) + x1 * w0 + x0 * w1 + q1 * n0 + q0 * n1;
+  return ((uint64_t)hi << 32) | (uint32_t)r;
+}
 PEPSI_HD uint64_t shoup(uint64_t x, uint64_t w, uint64_t wq, uint64_t p) {
   uint64_t r = shoup_lazy(x, w, wq, p);
   return r >= p ? r - p : r;

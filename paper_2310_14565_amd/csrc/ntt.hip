@@ -1,17 +1,21 @@
 // Negacyclic number-theoretic transforms for gfx950.
 //
 // NTT over an RNS prime p (2^53 < p < 2^54): one workgroup per row of N
-// residues, N/32 threads, 32 residues per thread held in registers.  The
-// log2(N) butterfly stages are done in three register passes of 5, 5 and
-// log2(N) - 10 stages; between passes the row goes through LDS (padded by
-// one word every 32 so that the strided pass patterns spread over banks).
+// residues, each thread holding E = 2^EL residues in registers.  The log2(N)
+// butterfly stages run in register passes of EL stages (the last pass takes
+// the rest); between passes the row goes through LDS (padded by one word every
+// 32 so that the strided pass patterns spread over banks).  A last pass of a
+// single stage reads or writes global memory straight from registers.
 // Forward: Cooley-Tukey with the bit-reversed power table psi^brv(k), output
 // in bit-reversed evaluation order.  Inverse: Gentleman-Sande with psi^-brv(k)
-// and a final N^-1.  One Shoup product per butterfly, whose result lies in
-// [0, 2p) for any 64-bit input.  Forward butterflies are not reduced at all:
-// (U, V) -> (U + V, U - V + 2p) with V < 2p raises the bound by 2p per stage,
-// so reduced inputs stay below (1 + 2 log2 N) p <= 29p < 2^59 and the output is
-// reduced once at the store.  Inverse butterflies keep U + V below 2p.
+// and a final N^-1.  One Shoup product per butterfly, with a quotient that may
+// be 2 short, so its result lies in [0, 4p) for any 64-bit input.  Forward
+// butterflies are not reduced at all: (U, V) -> (U + V, U - V + 4p) with
+// V < 4p raises the bound by 4p per stage, so reduced inputs stay below
+// (1 + 4 log2 N) p <= 57p < 2^60 and the output is reduced once at the store.
+// Inverse sums are not reduced inside a pass; each pass but the last brings
+// its words back below 4p at its end, the last leaves them below 2^EL 4p for
+// the final N^-1 product.
 //
 // Transforms over t = 65537 (batch encoding of slots) are cheap 32-bit
 // radix-2 loops over LDS.
@@ -20,23 +24,29 @@
 namespace pepsi {
 namespace {
 
-constexpr int E = 32;  // residues per thread
+// Each thread holds E = 2^EL residues of a row; a row's log N stages run as passes of EL stages
+// (the last pass takes what is left), with one exchange through padded LDS between passes.
+template <int LOGN>
+constexpr int ntt_el() { return 4; }
+// Whether a last pass of d stages reads or writes global memory from registers (each thread then
+// moves runs of 2^d consecutive words) instead of going through LDS.
+constexpr bool ntt_direct(int d) { return d <= 1; }
 
 __device__ __forceinline__ int lds_idx(int j) { return j + (j >> 5); }
 
-template <int LOGN, int S0, int D>
+template <int LOGN, int EL, int S0, int D>
 __device__ __forceinline__ int elem_index(int tid, int u, int m) {
-  constexpr int N = 1 << LOGN, T = N / E, LOW = N >> (S0 + D);
+  constexpr int N = 1 << LOGN, T = N >> EL, LOW = N >> (S0 + D);
   const int g = tid + T * u;
   return (g / LOW) * (N >> S0) + m * LOW + (g % LOW);
 }
 
-// Forward stages [S0, S0 + D) on 32 >> D groups of 2^D registers.
-template <int LOGN, int S0, int D>
+// Forward stages [S0, S0 + D) on 2^(EL - D) groups of 2^D registers.
+template <int LOGN, int EL, int S0, int D>
 __device__ __forceinline__ void fwd_pass(uint64_t* x, int tid, const uint64_t* __restrict__ W,
                                          const uint64_t* __restrict__ Wq, uint64_t p) {
-  constexpr int N = 1 << LOGN, T = N / E, LOW = N >> (S0 + D), G = E >> D;
-  const uint64_t two_p = 2 * p;
+  constexpr int N = 1 << LOGN, T = N >> EL, LOW = N >> (S0 + D), G = 1 << (EL - D);
+  const uint64_t four_p = 4 * p;
 #pragma unroll
   for (int u = 0; u < G; ++u) {
     const int hi = (tid + T * u) / LOW;
@@ -51,21 +61,31 @@ __device__ __forceinline__ void fwd_pass(uint64_t* x, int tid, const uint64_t* _
         for (int m = 0; m < half; ++m) {
           const int a = u * (1 << D) + blk * 2 * half + m, b = a + half;
           const uint64_t U = x[a];
-          const uint64_t V = shoup_lazy(x[b], w, wq, p);
+          const uint64_t V = shoup_lazy4(x[b], w, wq, p);
           x[a] = U + V;
-          x[b] = U - V + two_p;
+          x[b] = U - V + four_p;
         }
       }
     }
   }
 }
 
-// Inverse stages S0 + D - 1 down to S0.
-template <int LOGN, int S0, int D>
+constexpr int ilog2(int v) { return v > 1 ? 1 + ilog2(v >> 1) : 0; }
+
+// Inverse butterflies leave sums unreduced: a word is below 2^k 4p, where k counts the stages since
+// its last Shoup product. Within a group of 2^D registers this depends only on the offset m: before
+// the stage of span 2^j, k = j for m mod 2^j = 0 and otherwise j - 1 - floor(log2(m mod 2^j)).
+constexpr int inv_bound(int j, int m) {
+  return (m & ((1 << j) - 1)) == 0 ? j : j - 1 - ilog2(m & ((1 << j) - 1));
+}
+
+// Inverse stages S0 + D - 1 down to S0. With RED, every word is brought back below 4p at the end
+// (k conditional subtractions for a word of bound exponent k); without, words may reach 2^D 4p.
+template <int LOGN, int EL, int S0, int D, bool RED>
 __device__ __forceinline__ void inv_pass(uint64_t* x, int tid, const uint64_t* __restrict__ W,
                                          const uint64_t* __restrict__ Wq, uint64_t p) {
-  constexpr int N = 1 << LOGN, T = N / E, LOW = N >> (S0 + D), G = E >> D;
-  const uint64_t two_p = 2 * p;
+  constexpr int N = 1 << LOGN, T = N >> EL, LOW = N >> (S0 + D), G = 1 << (EL - D);
+  const uint64_t four_p = 4 * p;
 #pragma unroll
   for (int u = 0; u < G; ++u) {
     const int hi = (tid + T * u) / LOW;
@@ -80,31 +100,73 @@ __device__ __forceinline__ void inv_pass(uint64_t* x, int tid, const uint64_t* _
         for (int m = 0; m < half; ++m) {
           const int a = u * (1 << D) + blk * 2 * half + m, b = a + half;
           const uint64_t U = x[a], V = x[b];
-          uint64_t s = U + V;
-          if (s >= two_p) s -= two_p;
-          x[a] = s;
-          x[b] = shoup_lazy(U - V + two_p, w, wq, p);
+          x[a] = U + V;
+          x[b] = shoup_lazy4(U - V + (four_p << inv_bound(D - 1 - r, m)), w, wq, p);
         }
+      }
+    }
+    if constexpr (RED) {
+#pragma unroll
+      for (int m = 0; m < (1 << D); ++m) {
+        uint64_t v = x[u * (1 << D) + m];
+#pragma unroll
+        for (int j = inv_bound(D, m) - 1; j >= 0; --j)
+          if (v >= (four_p << j)) v -= four_p << j;
+        x[u * (1 << D) + m] = v;
       }
     }
   }
 }
 
-template <int LOGN, int S0, int D>
+// A thread writes back exactly the LDS words it read for the same pass, so a pass needs a barrier
+// only before its reads.
+template <int LOGN, int EL, int S0, int D>
 __device__ __forceinline__ void to_lds(uint64_t* lds, const uint64_t* x, int tid) {
 #pragma unroll
-  for (int u = 0; u < (E >> D); ++u)
+  for (int u = 0; u < (1 << (EL - D)); ++u)
 #pragma unroll
     for (int m = 0; m < (1 << D); ++m)
-      lds[lds_idx(elem_index<LOGN, S0, D>(tid, u, m))] = x[u * (1 << D) + m];
+      lds[lds_idx(elem_index<LOGN, EL, S0, D>(tid, u, m))] = x[u * (1 << D) + m];
 }
-template <int LOGN, int S0, int D>
+template <int LOGN, int EL, int S0, int D>
 __device__ __forceinline__ void from_lds(uint64_t* x, const uint64_t* lds, int tid) {
 #pragma unroll
-  for (int u = 0; u < (E >> D); ++u)
+  for (int u = 0; u < (1 << (EL - D)); ++u)
 #pragma unroll
     for (int m = 0; m < (1 << D); ++m)
-      x[u * (1 << D) + m] = lds[lds_idx(elem_index<LOGN, S0, D>(tid, u, m))];
+      x[u * (1 << D) + m] = lds[lds_idx(elem_index<LOGN, EL, S0, D>(tid, u, m))];
+}
+
+// Forward passes starting at stage S0 (> 0); the previous pass has left its outputs in LDS. With
+// KEEP, the last pass leaves its outputs in registers.
+template <int LOGN, int EL, int S0, bool KEEP>
+__device__ __forceinline__ void fwd_passes(uint64_t* x, uint64_t* lds, int tid,
+                                           const uint64_t* __restrict__ W,
+                                           const uint64_t* __restrict__ Wq, uint64_t p) {
+  constexpr int D = (LOGN - S0 < EL) ? LOGN - S0 : EL;
+  __syncthreads();
+  from_lds<LOGN, EL, S0, D>(x, lds, tid);
+  fwd_pass<LOGN, EL, S0, D>(x, tid, W, Wq, p);
+  if constexpr (S0 + D < LOGN) {
+    to_lds<LOGN, EL, S0, D>(lds, x, tid);
+    fwd_passes<LOGN, EL, S0 + D, KEEP>(x, lds, tid, W, Wq, p);
+  } else if constexpr (!KEEP) {
+    to_lds<LOGN, EL, S0, D>(lds, x, tid);
+  }
+}
+
+// Inverse passes from pass K (stages [K EL, K EL + D)) down to pass 1; the inputs of pass K are
+// in LDS. Pass 0 is left to the caller, which keeps its outputs in registers.
+template <int LOGN, int EL, int K>
+__device__ __forceinline__ void inv_passes(uint64_t* x, uint64_t* lds, int tid,
+                                           const uint64_t* __restrict__ W,
+                                           const uint64_t* __restrict__ Wq, uint64_t p) {
+  constexpr int S0 = K * EL, D = (LOGN - S0 < EL) ? LOGN - S0 : EL;
+  __syncthreads();
+  from_lds<LOGN, EL, S0, D>(x, lds, tid);
+  inv_pass<LOGN, EL, S0, D, true>(x, tid, W, Wq, p);
+  to_lds<LOGN, EL, S0, D>(lds, x, tid);
+  if constexpr (K > 1) inv_passes<LOGN, EL, K - 1>(x, lds, tid, W, Wq, p);
 }
 
 template <NttLoad LD>
@@ -124,10 +186,24 @@ __device__ __forceinline__ uint64_t load_elem(const void* in, size_t row, int np
   }
 }
 
-template <int LOGN, NttLoad LD, NttStore ST>
-__global__ void __launch_bounds__((1 << LOGN) / E)
+// Output word of the forward transform: reduced from [0, 29p) and stored whole or split 27/27.
+template <NttStore ST>
+__device__ __forceinline__ void store_elem(void* out, size_t at, uint64_t v, uint64_t p64, uint64_t p) {
+  v = shoup_lazy(v, 1, p64, p);   // [0, 57p) -> [0, 2p)
+  if (v >= p) v -= p;
+  if constexpr (ST == STORE_U64) {
+    static_cast<uint64_t*>(out)[at] = v;
+  } else {
+    static_cast<uint64_t*>(out)[at] = (v & ((1ull << 27) - 1)) | ((v >> 27) << 32);
+  }
+}
+
+template <int LOGN, NttLoad LD, NttStore ST, int EL = ntt_el<LOGN>()>
+__global__ void __launch_bounds__((1 << LOGN) >> EL)
 k_ntt_fwd(Tables T, const void* __restrict__ in, void* __restrict__ out, int nprimes, int first) {
-  constexpr int N = 1 << LOGN, TT = N / E, D2 = LOGN - 10;
+  constexpr int N = 1 << LOGN, E = 1 << EL, TT = N >> EL;
+  constexpr int SL = (LOGN - 1) / EL * EL, DL = LOGN - SL;   // last pass: stages [SL, LOGN)
+  constexpr bool KEEP = ntt_direct(DL);
   __shared__ uint64_t lds[N + N / 32];
   const size_t row = blockIdx.x;
   const int pidx = first + (int)(row % nprimes);
@@ -138,38 +214,33 @@ k_ntt_fwd(Tables T, const void* __restrict__ in, void* __restrict__ out, int npr
   uint64_t x[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) x[m] = load_elem<LD>(in, row, nprimes, N, m * TT + tid, p);
-  fwd_pass<LOGN, 0, 5>(x, tid, W, Wq, p);
-  to_lds<LOGN, 0, 5>(lds, x, tid);
-  __syncthreads();
-  from_lds<LOGN, 5, 5>(x, lds, tid);
-  fwd_pass<LOGN, 5, 5>(x, tid, W, Wq, p);
-  to_lds<LOGN, 5, 5>(lds, x, tid);
-  __syncthreads();
-  if constexpr (D2 > 0) {
-    from_lds<LOGN, 10, D2>(x, lds, tid);
-    fwd_pass<LOGN, 10, D2>(x, tid, W, Wq, p);
-    __syncthreads();                      // every thread has read its pass-C inputs
-    to_lds<LOGN, 10, D2>(lds, x, tid);
-    __syncthreads();
-  }
+  fwd_pass<LOGN, EL, 0, EL>(x, tid, W, Wq, p);
+  to_lds<LOGN, EL, 0, EL>(lds, x, tid);
+  fwd_passes<LOGN, EL, EL, KEEP>(x, lds, tid, W, Wq, p);
   const uint64_t p64 = T.c->prm[pidx].barrett >> 52;     // floor(2^64 / p)
+  if constexpr (KEEP) {
+    // Each thread holds runs of 2^DL consecutive outputs.
 #pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const int j = m * TT + tid;
-    uint64_t v = shoup_lazy(lds[lds_idx(j)], 1, p64, p);   // [0, 29p) -> [0, 2p)
-    if (v >= p) v -= p;
-    if constexpr (ST == STORE_U64) {
-      static_cast<uint64_t*>(out)[row * N + j] = v;
-    } else {
-      static_cast<uint64_t*>(out)[row * N + j] = (v & ((1ull << 27) - 1)) | ((v >> 27) << 32);
+    for (int u = 0; u < (1 << (EL - DL)); ++u)
+#pragma unroll
+      for (int m = 0; m < (1 << DL); ++m)
+        store_elem<ST>(out, row * N + elem_index<LOGN, EL, SL, DL>(tid, u, m), x[u * (1 << DL) + m],
+                       p64, p);
+  } else {
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int j = m * TT + tid;
+      store_elem<ST>(out, row * N + j, lds[lds_idx(j)], p64, p);
     }
   }
 }
 
-template <int LOGN>
-__global__ void __launch_bounds__((1 << LOGN) / E)
+template <int LOGN, int EL = ntt_el<LOGN>()>
+__global__ void __launch_bounds__((1 << LOGN) >> EL)
 k_ntt_inv(Tables T, const uint64_t* __restrict__ in, uint64_t* __restrict__ out, int nprimes, int first) {
-  constexpr int N = 1 << LOGN, TT = N / E, D2 = LOGN - 10;
+  constexpr int N = 1 << LOGN, E = 1 << EL, TT = N >> EL, NP = (LOGN + EL - 1) / EL;
+  constexpr int SL = (NP - 1) * EL, DL = LOGN - SL;   // first inverse pass: stages [SL, LOGN)
   __shared__ uint64_t lds[N + N / 32];
   const size_t row = blockIdx.x;
   const int pidx = first + (int)(row % nprimes);
@@ -178,26 +249,27 @@ k_ntt_inv(Tables T, const uint64_t* __restrict__ in, uint64_t* __restrict__ out,
   const uint64_t* Wq = T.ipsi_rev_shoup + (size_t)pidx * N;
   const int tid = threadIdx.x;
   uint64_t x[E];
+  if constexpr (ntt_direct(DL) && NP > 2) {
+    // Runs of 2^DL consecutive inputs go straight to registers for the first pass.
 #pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const int j = m * TT + tid;
-    lds[lds_idx(j)] = in[row * N + j];
+    for (int u = 0; u < (1 << (EL - DL)); ++u)
+#pragma unroll
+      for (int m = 0; m < (1 << DL); ++m)
+        x[u * (1 << DL) + m] = in[row * N + elem_index<LOGN, EL, SL, DL>(tid, u, m)];
+    inv_pass<LOGN, EL, SL, DL, true>(x, tid, W, Wq, p);
+    to_lds<LOGN, EL, SL, DL>(lds, x, tid);
+    inv_passes<LOGN, EL, NP - 2>(x, lds, tid, W, Wq, p);
+  } else {
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int j = m * TT + tid;
+      lds[lds_idx(j)] = in[row * N + j];
+    }
+    inv_passes<LOGN, EL, NP - 1>(x, lds, tid, W, Wq, p);
   }
   __syncthreads();
-  if constexpr (D2 > 0) {
-    from_lds<LOGN, 10, D2>(x, lds, tid);
-    inv_pass<LOGN, 10, D2>(x, tid, W, Wq, p);
-    __syncthreads();
-    to_lds<LOGN, 10, D2>(lds, x, tid);
-    __syncthreads();
-  }
-  from_lds<LOGN, 5, 5>(x, lds, tid);
-  inv_pass<LOGN, 5, 5>(x, tid, W, Wq, p);
-  __syncthreads();
-  to_lds<LOGN, 5, 5>(lds, x, tid);
-  __syncthreads();
-  from_lds<LOGN, 0, 5>(x, lds, tid);
-  inv_pass<LOGN, 0, 5>(x, tid, W, Wq, p);
+  from_lds<LOGN, EL, 0, EL>(x, lds, tid);
+  inv_pass<LOGN, EL, 0, EL, false>(x, tid, W, Wq, p);
   const uint64_t ni = T.c->n_inv[pidx], niq = T.c->n_inv_shoup[pidx];
 #pragma unroll
   for (int m = 0; m < E; ++m) {
@@ -294,7 +366,7 @@ __global__ void __launch_bounds__(256) k_encode_planes(Tables T, const uint16_t*
 template <int LOGN>
 void launch_fwd(const Tables& T, const void* in, NttLoad ld, void* out, NttStore st, int rows,
                 int nprimes, int first, hipStream_t s) {
-  const dim3 grid(rows), block((1 << LOGN) / E);
+  const dim3 grid(rows), block((1 << LOGN) >> ntt_el<LOGN>());
 #define PEPSI_FWD(L_, S_) hipLaunchKernelGGL((k_ntt_fwd<LOGN, L_, S_>), grid, block, 0, s, T, in, out, nprimes, first)
   if (st == STORE_U64) {
     switch (ld) {
@@ -330,13 +402,12 @@ void ntt_forward(const Tables& T, int logn, const void* in, NttLoad load, void* 
 void ntt_inverse(const Tables& T, int logn, const uint64_t* in, uint64_t* out, int rows, int nprimes,
                  int first, hipStream_t s) {
   if (rows <= 0) return;
-  const dim3 grid(rows), block((1 << logn) / E);
-  switch (logn) {
-    case 10: hipLaunchKernelGGL(k_ntt_inv<10>, grid, block, 0, s, T, in, out, nprimes, first); break;
-    case 11: hipLaunchKernelGGL(k_ntt_inv<11>, grid, block, 0, s, T, in, out, nprimes, first); break;
-    case 12: hipLaunchKernelGGL(k_ntt_inv<12>, grid, block, 0, s, T, in, out, nprimes, first); break;
-    case 13: hipLaunchKernelGGL(k_ntt_inv<13>, grid, block, 0, s, T, in, out, nprimes, first); break;
-    case 14: hipLaunchKernelGGL(k_ntt_inv<14>, grid, block, 0, s, T, in, out, nprimes, first); break;
+    switch (logn) {
+    case 10: hipLaunchKernelGGL(k_ntt_inv<10>, dim3(rows), dim3((1 << 10) >> ntt_el<10>()), 0, s, T, in, out, nprimes, first); break;
+    case 11: hipLaunchKernelGGL(k_ntt_inv<11>, dim3(rows), dim3((1 << 11) >> ntt_el<11>()), 0, s, T, in, out, nprimes, first); break;
+    case 12: hipLaunchKernelGGL(k_ntt_inv<12>, dim3(rows), dim3((1 << 12) >> ntt_el<12>()), 0, s, T, in, out, nprimes, first); break;
+    case 13: hipLaunchKernelGGL(k_ntt_inv<13>, dim3(rows), dim3((1 << 13) >> ntt_el<13>()), 0, s, T, in, out, nprimes, first); break;
+    case 14: hipLaunchKernelGGL(k_ntt_inv<14>, dim3(rows), dim3((1 << 14) >> ntt_el<14>()), 0, s, T, in, out, nprimes, first); break;
   }
 }
 

@@ -188,7 +188,7 @@ int build_host_params(int logn, int L, int h, int item_bits, int mu, int n_hash,
     C.qhat_mod_q[i] = mw_mod_small(qh, q[i]);
     C.qhat_inv[i] = invm(C.qhat_mod_q[i], q[i]);
     C.qhat_inv_shoup[i] = shoup_companion(C.qhat_inv[i], q[i]);
-    C.inv_q[i] = frac128(1, q[i]);
+    C.inv_q_d[i] = 1.0 / (double)q[i];
     for (int j = 0; j < K; ++j) C.qhat_mod_b[i][j] = mw_mod_small(qh, b[j]);
   }
   for (int j = 0; j < K; ++j) C.q_mod_b[j] = mw_mod_small(Qw, b[j]);
@@ -200,7 +200,7 @@ int build_host_params(int logn, int L, int h, int item_bits, int mu, int n_hash,
     C.bhat_w[j] = bh;
     C.bhat_inv[j] = invm(mw_mod_small(bh, b[j]), b[j]);
     C.bhat_inv_shoup[j] = shoup_companion(C.bhat_inv[j], b[j]);
-    C.inv_b[j] = frac128(1, b[j]);
+    C.inv_b_d[j] = 1.0 / (double)b[j];
     for (int i = 0; i < L; ++i) C.bhat_mod_q[j][i] = mw_mod_small(bh, q[i]);
   }
   for (int i = 0; i < L; ++i) C.b_mod_q[i] = mw_mod_small(Bw, q[i]);

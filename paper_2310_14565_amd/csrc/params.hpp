@@ -28,13 +28,13 @@ struct Consts {
   // Q -> B extension of the centred lift
   uint64_t qhat_inv[PEPSI_MAXL], qhat_inv_shoup[PEPSI_MAXL];   // (Q/q_i)^-1 mod q_i
   uint64_t qhat_mod_q[PEPSI_MAXL];            // (Q/q_i) mod q_i
-  Fix128 inv_q[PEPSI_MAXL];                   // floor(2^128 / q_i)
+  double inv_q_d[PEPSI_MAXL];                 // 1 / q_i in double precision
   uint64_t qhat_mod_b[PEPSI_MAXL][PEPSI_MAXK];// (Q/q_i) mod b_j
   uint64_t q_mod_b[PEPSI_MAXK];               // Q mod b_j
 
   // B -> Q extension of the centred lift
   uint64_t bhat_inv[PEPSI_MAXK], bhat_inv_shoup[PEPSI_MAXK];   // (B/b_j)^-1 mod b_j
-  Fix128 inv_b[PEPSI_MAXK];                   // floor(2^128 / b_j)
+  double inv_b_d[PEPSI_MAXK];                 // 1 / b_j in double precision
   uint64_t bhat_mod_q[PEPSI_MAXK][PEPSI_MAXL];// (B/b_j) mod q_i
   uint64_t b_mod_q[PEPSI_MAXL];               // B mod q_i
 

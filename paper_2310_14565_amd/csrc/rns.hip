@@ -3,11 +3,13 @@
 // gadget, the select-and-sum of the server computation, and elementwise steps.
 //
 // Exactness.  A centred base extension needs v = round(sum_i y_i / q_i) and
-// the rescale needs R = round(sum_i y_i theta_i).  Both are computed in
-// 64.64 fixed point with a proven error below (n + 1) 2^-64; when the
-// fraction lies that close to 1/2 the coefficient takes the exact path
-// (crt_exact: the integer is rebuilt in multiword arithmetic and compared
-// with half the modulus), so every output equals the textbook integer result.
+// the rescale needs R = round(sum_i y_i theta_i).  v is at most the number of
+// terms and is computed in double precision with a proven error below 2^-45;
+// R can be large and is computed in 64.64 fixed point with an error below
+// n 2^-41.  When the fraction lies within that bound (with margin) of 1/2 the
+// coefficient takes the exact path (crt_exact: the integer is rebuilt in
+// multiword arithmetic and compared with half the modulus), so every output
+// equals the textbook integer result.
 #include "kernels.hpp"
 
 namespace pepsi {
@@ -34,6 +36,49 @@ __device__ __forceinline__ uint64_t fix_round(const FixAcc& a, int nterms, bool*
   const uint64_t carry = f < a.frac ? 1 : 0;
   *ambiguous = f > ~0ull - 2ull * (uint64_t)(nterms + 2);
   return a.ip + carry;
+}
+
+// The theta sum of the rescale with C read to 96 bits: y = y1 2^32 + y0 (y < 2^54) and C's top
+// words t2, t1, t0 at 2^-32, 2^-64 and 2^-96.  In units of 2^-64 the product is
+//   y1 t2 2^64 + (y0 t2 + y1 t1) 2^32 + (y0 t1 + y1 t0) + y0 t0 2^-32;
+// the low half of the last term and C beyond 96 bits are dropped, so each term is less than
+// 2^22 + 2 units short.
+__device__ __forceinline__ void fix_add96(FixAcc& a, uint64_t y, const Fix128& C) {
+  const uint32_t y0 = (uint32_t)y, y1 = (uint32_t)(y >> 32);
+  const uint32_t t2 = (uint32_t)(C.hi >> 32), t1 = (uint32_t)C.hi, t0 = (uint32_t)(C.lo >> 32);
+  const u128 m1 = (u128)((uint64_t)y0 * t2) + (uint64_t)y1 * t1;
+  const u128 m0 = (u128)((uint64_t)y0 * t1) + (uint64_t)y1 * t0 + (((uint64_t)y0 * t0) >> 32);
+  const u128 tot = m0 + (m1 << 32) + ((u128)((uint64_t)y1 * t2) << 64);
+  const uint64_t f = a.frac + (uint64_t)tot;
+  a.ip += (uint64_t)(tot >> 64) + (f < a.frac ? 1 : 0);
+  a.frac = f;
+}
+// round(S) for S in [A, A + nterms (2^22 + 2) 2^-64): floor(A + 1/2), flagged when S may round
+// higher.
+__device__ __forceinline__ uint64_t fix_round96(const FixAcc& a, int nterms, bool* ambiguous) {
+  const uint64_t f = a.frac + (1ull << 63);
+  const uint64_t carry = f < a.frac ? 1 : 0;
+  *ambiguous = f > ~0ull - ((uint64_t)(nterms + 1) << 23);
+  return a.ip + carry;
+}
+
+// v = round(sum_i y_i / m_i) for y_i < m_i (the centring count of a base extension, v <= n), in
+// double precision.  y_i converts with one rounding and 1/m_i is stored correctly rounded from
+// the rounded m_i, so each product is within 3.01 2^-53 of y_i / m_i < 1; each fused addition
+// adds at most i 2^-53, and the + 1/2 at most (n + 1) 2^-53.  For n <= 9 the total is below
+// 2^-45, so outside a guard band of 2^-36 around the half-integers the rounding is the exact
+// one; inside it *ambiguous is set.
+template <int n>
+__device__ __forceinline__ uint64_t round_fp(const uint64_t* y, const double* inv, bool* ambiguous) {
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < n; ++i) {
+    const double yd = fma((double)(uint32_t)(y[i] >> 32), 0x1p32, (double)(uint32_t)y[i]);
+    s = fma(yd, inv[i], s);
+  }
+  const double r = s + 0.5, f = floor(r), fr = r - f;
+  *ambiguous = fr < 0x1p-36 || fr > 1.0 - 0x1p-36;
+  return (uint64_t)f;
 }
 
 // Exact CRT: X = sum_k y_k * hat_k reduced into [0, M) by v subtractions of M.
@@ -135,14 +180,10 @@ __device__ __forceinline__ void ext_one(const Consts& C, const uint64_t* x, uint
                                         uint32_t* fallback) {
   constexpr int K = L + 1;
   uint64_t y[L];
-  FixAcc a{0, 0};
 #pragma unroll
-  for (int i = 0; i < L; ++i) {
-    y[i] = shoup(x[i], C.qhat_inv[i], C.qhat_inv_shoup[i], C.prm[i].p);
-    fix_add(a, y[i], C.inv_q[i]);
-  }
+  for (int i = 0; i < L; ++i) y[i] = shoup(x[i], C.qhat_inv[i], C.qhat_inv_shoup[i], C.prm[i].p);
   bool amb;
-  uint64_t v = fix_round(a, L, &amb);
+  uint64_t v = round_fp<L>(y, C.inv_q_d, &amb);
   if (amb) v = exact_round_q<L>(C, y, fallback);
   Split27 ys[L];
 #pragma unroll
@@ -315,9 +356,9 @@ __global__ void __launch_bounds__(TPB) k_scale_round(Tables T, const uint64_t* _
   }
   FixAcc a{0, 0};
 #pragma unroll
-  for (int i = 0; i < L; ++i) fix_add(a, y[i], C.theta[i]);
+  for (int i = 0; i < L; ++i) fix_add96(a, y[i], C.theta[i]);
   bool amb;
-  uint64_t R = fix_round(a, L, &amb);
+  uint64_t R = fix_round96(a, L, &amb);
   if (amb) {
     // frac(sum y_i r_i / q_i) > 1/2  <=>  the integer with residues y_i r_i (Q/q_i) exceeds Q/2
     uint64_t z[L];
@@ -330,7 +371,6 @@ __global__ void __launch_bounds__(TPB) k_scale_round(Tables T, const uint64_t* _
   }
   // z_j = round(t d / Q) mod b_j
   uint64_t yb[K];
-  FixAcc fb{0, 0};
   Split27 yq[L];
 #pragma unroll
   for (int i = 0; i < L; ++i) yq[i] = split27(y[i]);
@@ -344,9 +384,8 @@ __global__ void __launch_bounds__(TPB) k_scale_round(Tables T, const uint64_t* _
     for (int i = 0; i < L; ++i) acc.mac(yq[i], C.omega_mod_b[i][j]);
     const uint64_t zj = acc.reduce(pr);
     yb[j] = shoup(zj, C.bhat_inv[j], C.bhat_inv_shoup[j], pr.p);
-    fix_add(fb, yb[j], C.inv_b[j]);
   }
-  uint64_t v = fix_round(fb, K, &amb);
+  uint64_t v = round_fp<K>(yb, C.inv_b_d, &amb);
   if (amb) v = exact_round_b<K>(C, yb, fallback);
   Split27 ybs[K];
 #pragma unroll

@@ -599,17 +599,23 @@ struct Engine {
     if (levels > 0) (void)hipMemsetAsync(accD.as<uint64_t>(slot * dtw()), 0, dtw() * 8, s);
   }
 
-  void timed_select_sum(const uint64_t* phat, int nb, int nq, const int* qslot, int single_slot, uint64_t* Sx,
+  // A run of batches in a plaintext store: batches bfirst .. of a store of groups of gs batches.
+  struct PtView { const uint64_t* p = nullptr; int gs = 0, bfirst = 0; };
+  // Group size of the resident cache of `cached` batches (space is allocated for whole groups).
+  static int cache_group(uint32_t cached) { return cached < (uint32_t)PT_GROUP ? (int)cached : PT_GROUP; }
+
+  void timed_select_sum(const PtView& pv, int nb, int nq, const int* qslot, int single_slot, uint64_t* Sx,
                         hipStream_t s) {
     const HostParams& H = P->H;
     const size_t n = H.n, L = H.L;
     hipEvent_t a = nullptr, b = nullptr;
     if (timer && timer->on) { a = timer->get(); b = timer->get(); (void)hipEventRecord(a, s); }
     if (nq == 1)
-      select_sum(P->T, H.consts, chat.as<uint64_t>((size_t)single_slot * cstride()), phat, H.ell, nb, Sx,
-                 (long)(2 * L * n), s);
+      select_sum(P->T, H.consts, chat.as<uint64_t>((size_t)single_slot * cstride()), pv.p, pv.gs, pv.bfirst,
+                 H.ell, nb, Sx, (long)(2 * L * n), s);
     else
-      select_sum_multi(P->T, H.consts, chat.as<uint64_t>(), (long)cstride(), qslot, nq, phat, H.ell, nb, Sx, s);
+      select_sum_multi(P->T, H.consts, chat.as<uint64_t>(), (long)cstride(), qslot, nq, pv.p, pv.gs, pv.bfirst,
+                       H.ell, nb, Sx, s);
     if (a) {
       (void)hipEventRecord(b, s);
       const uint64_t bytes =
@@ -619,22 +625,27 @@ struct Engine {
   }
 
   // Select-and-sum of one tile: batches [b0, b0 + nb) of nq active queries (slots qslot[0..nq), or
-  // single_slot when nq == 1) into Sout [nb * nq][2][L][N]; plaintexts from the cache (phat) or
+  // single_slot when nq == 1) into Sout [nb * nq][2][L][N]; plaintexts from the cache (pv) or
   // generated.
   void produce_s(const uint16_t* cw, int b0, int nb, int nq, const int* qslot, int single_slot,
-                 const uint64_t* phat, uint64_t* Sout, hipStream_t s) {
+                 const PtView& pv, uint64_t* Sout, hipStream_t s) {
     const HostParams& H = P->H;
     const size_t n = H.n, L = H.L;
-    if (phat) {
-      timed_select_sum(phat, nb, nq, qslot, single_slot, Sout, s);
+    if (pv.p) {
+      timed_select_sum(pv, nb, nq, qslot, single_slot, Sout, s);
       return;
     }
     for (int g0 = 0; g0 < nb; g0 += GB) {
       const int g = std::min(GB, nb - g0);
       encode_server_planes(P->T, H.logn, cw, H.h, H.ell, b0 + g0, g, gen_poly.as<uint32_t>(), s);
-      ntt_forward(P->T, H.logn, gen_poly.p, LOAD_LIFT_T, gen_p.p, STORE_SPLIT27, g * H.ell * (int)L, (int)L, 0,
-                  s);
-      timed_select_sum(gen_p.as<uint64_t>(), g, nq, qslot, single_slot, Sout + (size_t)g0 * nq * 2 * L * n, s);
+      PtLayout pl;
+      pl.ell = H.ell;
+      pl.gs = GB;
+      ntt_forward_plaintexts(P->T, H.logn, gen_poly.as<uint32_t>(), gen_p.as<uint64_t>(), g, (int)L, pl, s);
+      PtView gv;
+      gv.p = gen_p.as<uint64_t>();
+      gv.gs = GB;
+      timed_select_sum(gv, g, nq, qslot, single_slot, Sout + (size_t)g0 * nq * 2 * L * n, s);
     }
   }
 
@@ -704,8 +715,8 @@ struct Engine {
 
   // One tile on one stream.
   void run_tile(const uint16_t* cw, int b0, int nb, int nq, const int* qslot, int single_slot,
-                const uint64_t* phat, hipStream_t s) {
-    produce_s(cw, b0, nb, nq, qslot, single_slot, phat, sq.as<uint64_t>(), s);
+                const PtView& pv, hipStream_t s) {
+    produce_s(cw, b0, nb, nq, qslot, single_slot, pv, sq.as<uint64_t>(), s);
     consume_s(sq.as<uint64_t>(), b0, nb, nq, qslot, single_slot, s);
   }
 
@@ -740,8 +751,14 @@ struct Engine {
   }
 
   // Plaintexts of tile [b0, b0 + nb): the cache when it covers the tile, else generated.
-  static const uint64_t* cached_tile(const uint64_t* cache, uint32_t cached, uint32_t b0, int nb, size_t per) {
-    return (cache && b0 + (uint32_t)nb <= cached) ? cache + per * b0 : nullptr;
+  static PtView cached_tile(const uint64_t* cache, uint32_t cached, uint32_t b0, int nb) {
+    PtView v;
+    if (cache && b0 + (uint32_t)nb <= cached) {
+      v.p = cache;
+      v.gs = cache_group(cached);
+      v.bfirst = (int)b0;
+    }
+    return v;
   }
 
   // The whole computation for nq queries in slots 0..nq-1 over batches [begin, stop).  (Running
@@ -750,10 +767,9 @@ struct Engine {
   int run(const uint16_t* cw, const uint64_t* cache, uint32_t cached, uint32_t begin, uint32_t stop, int nq,
           const uint64_t* const* cts, const uint64_t* const* rlk, hipStream_t s) {
     for (int q = 0; q < nq; ++q) admit(q, cts[q], rlk[q], s);
-    const size_t per = (size_t)P->H.ell * P->H.L * P->H.n;
     for (uint32_t b0 = begin; b0 < stop; b0 += TBq) {
       const int nb = (int)std::min<uint32_t>(TBq, stop - b0);
-      run_tile(cw, (int)b0, nb, nq, nullptr, 0, cached_tile(cache, cached, b0, nb, per), s);
+      run_tile(cw, (int)b0, nb, nq, nullptr, 0, cached_tile(cache, cached, b0, nb), s);
     }
     return 0;
   }
@@ -767,7 +783,7 @@ struct pepsi_server {
   EventTimer timer;
   uint32_t max_load = 0;
   DevBuf cw;            // [mu][N][h] uint16
-  DevBuf cache;         // [cached][ell][L][N] split-27 NTT form
+  DevBuf cache;         // plaintext store of the cached batches (layout at PtLayout)
   bool cached = false;
   uint32_t cached_batches = 0;
   Engine eng;            // one query at a time (plain path)
@@ -851,7 +867,9 @@ extern "C" int pepsi_server_create_with_values(const pepsi_params* Pc, const uin
     uint32_t nc = (uint32_t)std::min<size_t>(fit, max_load);
     if (nc < max_load) nc -= nc % 16;
     if (nc > 0) {
-      if ((rc = sv->cache.ensure(per * nc * 8))) { delete sv; return rc; }
+      const int gs = Engine::cache_group(nc);
+      const size_t alloc_b = (nc + gs - 1) / gs * gs;
+      if ((rc = sv->cache.ensure(per * alloc_b * 8))) { delete sv; return rc; }
       DevBuf poly;
       const int G = 8;
       if ((rc = poly.ensure((size_t)G * H.ell * H.n * 4))) { delete sv; return rc; }
@@ -859,8 +877,11 @@ extern "C" int pepsi_server_create_with_values(const pepsi_params* Pc, const uin
       for (uint32_t b0 = 0; b0 < nc; b0 += G) {
         const int g = (int)std::min<uint32_t>(G, nc - b0);
         encode_server_planes(P->T, H.logn, sv->cw.as<uint16_t>(), H.h, H.ell, (int)b0, g, poly.as<uint32_t>(), s);
-        ntt_forward(P->T, H.logn, poly.p, LOAD_LIFT_T, sv->cache.as<uint64_t>(per * b0), STORE_SPLIT27,
-                    g * H.ell * H.L, H.L, 0, s);
+        PtLayout pl;
+        pl.ell = H.ell;
+        pl.gs = gs;
+        pl.bbase = (int)b0;
+        ntt_forward_plaintexts(P->T, H.logn, poly.as<uint32_t>(), sv->cache.as<uint64_t>(), g, H.L, pl, s);
       }
       if (hipStreamSynchronize(s) != hipSuccess) { poly.release(); delete sv; return fail(PEPSI_E_DEVICE, "cache build failed"); }
       poly.release();
@@ -907,7 +928,7 @@ extern "C" int pepsi_server_eval_range(pepsi_server* sv, const uint64_t* cts, co
   if (begin > end || end > (uint32_t)H.mu) return fail(PEPSI_E_ARG, "bad batch range");
   hipStream_t s = S(stream);
   if (!sv->ready) {
-    const int tb = std::min<int>(128, std::max<int>(1, (int)sv->max_load));
+    const int tb = std::min<int>(256, std::max<int>(1, (int)sv->max_load));
     int rc = sv->eng.setup(sv->P, tb, 1, sv->cached_batches < sv->max_load, sv->values_hat());
     if (rc) return rc;
     sv->eng.timer = &sv->timer;
@@ -1036,7 +1057,6 @@ struct pepsi_serve {
 
   void loop() {
     (void)hipSetDevice(sv->P->device);
-    const size_t per = (size_t)sv->P->H.ell * sv->P->H.L * sv->P->H.n;
     for (;;) {
       std::vector<Req*> admitted;
       {
@@ -1075,7 +1095,7 @@ struct pepsi_serve {
         const int nb = (int)std::min<uint32_t>(eng.TBq, stop_b - b0);
         eng.run_tile(sv->cw.as<uint16_t>(), (int)b0, nb, na, qslot_dev.as<int>(), live[0],
                      Engine::cached_tile(sv->cached ? sv->cache.as<uint64_t>() : nullptr, sv->cached_batches, b0,
-                                         nb, per),
+                                         nb),
                      stream);
         cursor = (cursor + 1) % T;
         ++steps;
@@ -1288,8 +1308,11 @@ extern "C" int pepsi_select_sum(const pepsi_params* Pc, const uint64_t* cts, con
   hipStream_t s = S(stream);
   ntt_forward(P->T, H.logn, cts, LOAD_U64, ch, STORE_U64, (int)(ell * 2 * L), (int)L, 0, s);
   encode_server_planes(P->T, H.logn, cw, H.h, (int)ell, 0, 1, poly, s);
-  ntt_forward(P->T, H.logn, poly, LOAD_LIFT_T, ph, STORE_SPLIT27, (int)(ell * L), (int)L, 0, s);
-  select_sum(P->T, H.consts, ch, ph, (int)ell, 1, Sx, (long)(2 * L * n), s);
+  PtLayout pl;
+  pl.ell = (int)ell;
+  pl.gs = 1;
+  ntt_forward_plaintexts(P->T, H.logn, poly, ph, 1, (int)L, pl, s);
+  select_sum(P->T, H.consts, ch, ph, 1, 0, (int)ell, 1, Sx, (long)(2 * L * n), s);
   ntt_inverse(P->T, H.logn, Sx, out, (int)(2 * L), (int)L, 0, s);
   HIPCHK(hipGetLastError());
   return PEPSI_OK;

@@ -11,13 +11,28 @@ namespace pepsi {
 // Forward: coefficient order in, bit-reversed evaluation order out:
 //   out[k] = a(psi^(2 brv(k) + 1)).   Inverse: the exact inverse.
 enum NttLoad { LOAD_U64 = 0, LOAD_LIFT_T = 1, LOAD_I8 = 2, LOAD_I32 = 3 };
-enum NttStore { STORE_U64 = 0, STORE_SPLIT27 = 1 };
+enum NttStore { STORE_U64 = 0, STORE_PLAINTEXT = 1 };
+
+// Server plaintexts in NTT form (STORE_PLAINTEXT).  Each residue is split into 27-bit halves (low
+// half in the low, high half in the high 32-bit word).  A store holds groups of gs batches; within
+// a group the batches are interleaved per block of 256 positions: the word of batch b = G gs + g,
+// code position j, limb l and position k is at
+//   ((((G ell + j) L + l) (N / 256) + k / 256) gs + g) 256 + k % 256,
+// so that one block of a group's batches is one contiguous run, and a group is one contiguous
+// region (space for whole groups is allocated).  A launch over rows (i ell + j) L + l writes
+// batch bbase + i.
+constexpr int PT_BLOCK = 256, PT_GROUP = 16;
+struct PtLayout { int ell = 0, gs = 0, bbase = 0; };
 
 // in: LOAD_U64 -> const uint64_t[rows][N]; LOAD_LIFT_T -> const uint32_t[rows / nprimes][N]
 // (a plaintext mod t, lifted to its centred representative); LOAD_I8 / LOAD_I32 -> small
 // signed integers [rows / nprimes][N].
 void ntt_forward(const Tables& T, int logn, const void* in, NttLoad load, void* out,
                  NttStore store, int rows, int nprimes, int first, hipStream_t s);
+// Plaintext rows mod t ([nb][ell][N] u32) lifted, transformed over q_0..q_{L-1} and stored into a
+// plaintext store of groups of pl.gs batches as batches pl.bbase .. pl.bbase + nb - 1.
+void ntt_forward_plaintexts(const Tables& T, int logn, const uint32_t* in, uint64_t* out, int nb, int L,
+                            const PtLayout& pl, hipStream_t s);
 void ntt_inverse(const Tables& T, int logn, const uint64_t* in, uint64_t* out, int rows,
                  int nprimes, int first, hipStream_t s);
 
@@ -92,14 +107,16 @@ void expand_uniform(const Tables& T, const Consts& hc, const ChaChaKey& key, int
 // Response compression: out [2][N] = [round(q_0 X / Q)]_{q_0} of every coefficient X of ct [2][L][N].
 void mod_switch(const Tables& T, const Consts& hc, const uint64_t* ct, uint64_t* out, hipStream_t s);
 // select-and-sum: S[b][c][l][k] = sum_j C[j][c][l][k] * P[b][j][l][k] mod q_l.
-// C: NTT form [ell][2][L][N]; P: split-27 NTT form [nb][ell][L][N]; S rows of stride sstride.
-void select_sum(const Tables& T, const Consts& hc, const uint64_t* C, const uint64_t* P, int ell,
-                int nb, uint64_t* S, long sstride, hipStream_t s);
+// C: NTT form [ell][2][L][N]; P: a plaintext store of groups of gs batches, of which batches
+// bfirst .. bfirst + nb - 1 are summed; S rows of stride sstride.
+void select_sum(const Tables& T, const Consts& hc, const uint64_t* C, const uint64_t* P, int gs, int bfirst,
+                int ell, int nb, uint64_t* S, long sstride, hipStream_t s);
 
 // select-and-sum of nq queries (client values Cq + q * cq_stride, NTT form [ell][2][L][N]) against
 // nb plaintext batches; S entry of (batch b, query q) at (b * nq + q) * 2 L N.
 void select_sum_multi(const Tables& T, const Consts& hc, const uint64_t* Cq, long cq_stride, const int* qslot,
-                      int nq, const uint64_t* P, int ell, int nb, uint64_t* S, hipStream_t s);
+                      int nq, const uint64_t* P, int gs, int bfirst, int ell, int nb, uint64_t* S,
+                      hipStream_t s);
 
 // ---------------- elementwise helpers ----------------
 // out = a * b pointwise (both [rows][L][N] NTT form, b broadcast over rows if bcast)

@@ -186,21 +186,27 @@ __device__ __forceinline__ uint64_t load_elem(const void* in, size_t row, int np
   }
 }
 
-// Output word of the forward transform: reduced from [0, 29p) and stored whole or split 27/27.
+// Output word j of row `row` of the forward transform: reduced from [0, 57p) and stored whole, or
+// split 27/27 at its place in a plaintext store.
 template <NttStore ST>
-__device__ __forceinline__ void store_elem(void* out, size_t at, uint64_t v, uint64_t p64, uint64_t p) {
+__device__ __forceinline__ void store_elem(void* out, size_t row, int N, int nprimes, const PtLayout& pl, int j,
+                                           uint64_t v, uint64_t p64, uint64_t p) {
   v = shoup_lazy(v, 1, p64, p);   // [0, 57p) -> [0, 2p)
   if (v >= p) v -= p;
   if constexpr (ST == STORE_U64) {
-    static_cast<uint64_t*>(out)[at] = v;
+    static_cast<uint64_t*>(out)[row * N + j] = v;
   } else {
+    const size_t l = row % nprimes, jb = row / nprimes, cj = jb % pl.ell, b = jb / pl.ell + pl.bbase;
+    const size_t G = b / pl.gs, g = b % pl.gs;
+    const size_t at = ((((G * pl.ell + cj) * nprimes + l) * (N / PT_BLOCK) + j / PT_BLOCK) * pl.gs + g) * PT_BLOCK +
+                      j % PT_BLOCK;
     static_cast<uint64_t*>(out)[at] = (v & ((1ull << 27) - 1)) | ((v >> 27) << 32);
   }
 }
 
 template <int LOGN, NttLoad LD, NttStore ST, int EL = ntt_el<LOGN>()>
 __global__ void __launch_bounds__((1 << LOGN) >> EL)
-k_ntt_fwd(Tables T, const void* __restrict__ in, void* __restrict__ out, int nprimes, int first) {
+k_ntt_fwd(Tables T, const void* __restrict__ in, void* __restrict__ out, int nprimes, int first, PtLayout pl) {
   constexpr int N = 1 << LOGN, E = 1 << EL, TT = N >> EL;
   constexpr int SL = (LOGN - 1) / EL * EL, DL = LOGN - SL;   // last pass: stages [SL, LOGN)
   constexpr bool KEEP = ntt_direct(DL);
@@ -224,14 +230,14 @@ k_ntt_fwd(Tables T, const void* __restrict__ in, void* __restrict__ out, int npr
     for (int u = 0; u < (1 << (EL - DL)); ++u)
 #pragma unroll
       for (int m = 0; m < (1 << DL); ++m)
-        store_elem<ST>(out, row * N + elem_index<LOGN, EL, SL, DL>(tid, u, m), x[u * (1 << DL) + m],
+        store_elem<ST>(out, row, N, nprimes, pl, elem_index<LOGN, EL, SL, DL>(tid, u, m), x[u * (1 << DL) + m],
                        p64, p);
   } else {
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < E; ++m) {
       const int j = m * TT + tid;
-      store_elem<ST>(out, row * N + j, lds[lds_idx(j)], p64, p);
+      store_elem<ST>(out, row, N, nprimes, pl, j, lds[lds_idx(j)], p64, p);
     }
   }
 }
@@ -365,9 +371,9 @@ __global__ void __launch_bounds__(256) k_encode_planes(Tables T, const uint16_t*
 
 template <int LOGN>
 void launch_fwd(const Tables& T, const void* in, NttLoad ld, void* out, NttStore st, int rows,
-                int nprimes, int first, hipStream_t s) {
+                int nprimes, int first, const PtLayout& pl, hipStream_t s) {
   const dim3 grid(rows), block((1 << LOGN) >> ntt_el<LOGN>());
-#define PEPSI_FWD(L_, S_) hipLaunchKernelGGL((k_ntt_fwd<LOGN, L_, S_>), grid, block, 0, s, T, in, out, nprimes, first)
+#define PEPSI_FWD(L_, S_) hipLaunchKernelGGL((k_ntt_fwd<LOGN, L_, S_>), grid, block, 0, s, T, in, out, nprimes, first, pl)
   if (st == STORE_U64) {
     switch (ld) {
       case LOAD_U64: PEPSI_FWD(LOAD_U64, STORE_U64); break;
@@ -376,11 +382,7 @@ void launch_fwd(const Tables& T, const void* in, NttLoad ld, void* out, NttStore
       case LOAD_I32: PEPSI_FWD(LOAD_I32, STORE_U64); break;
     }
   } else {
-    switch (ld) {
-      case LOAD_U64: PEPSI_FWD(LOAD_U64, STORE_SPLIT27); break;
-      case LOAD_LIFT_T: PEPSI_FWD(LOAD_LIFT_T, STORE_SPLIT27); break;
-      default: break;
-    }
+    if (ld == LOAD_LIFT_T) PEPSI_FWD(LOAD_LIFT_T, STORE_PLAINTEXT);
   }
 #undef PEPSI_FWD
 }
@@ -391,11 +393,24 @@ void ntt_forward(const Tables& T, int logn, const void* in, NttLoad load, void* 
                  int rows, int nprimes, int first, hipStream_t s) {
   if (rows <= 0) return;
   switch (logn) {
-    case 10: launch_fwd<10>(T, in, load, out, store, rows, nprimes, first, s); break;
-    case 11: launch_fwd<11>(T, in, load, out, store, rows, nprimes, first, s); break;
-    case 12: launch_fwd<12>(T, in, load, out, store, rows, nprimes, first, s); break;
-    case 13: launch_fwd<13>(T, in, load, out, store, rows, nprimes, first, s); break;
-    case 14: launch_fwd<14>(T, in, load, out, store, rows, nprimes, first, s); break;
+    case 10: launch_fwd<10>(T, in, load, out, store, rows, nprimes, first, PtLayout{}, s); break;
+    case 11: launch_fwd<11>(T, in, load, out, store, rows, nprimes, first, PtLayout{}, s); break;
+    case 12: launch_fwd<12>(T, in, load, out, store, rows, nprimes, first, PtLayout{}, s); break;
+    case 13: launch_fwd<13>(T, in, load, out, store, rows, nprimes, first, PtLayout{}, s); break;
+    case 14: launch_fwd<14>(T, in, load, out, store, rows, nprimes, first, PtLayout{}, s); break;
+  }
+}
+
+void ntt_forward_plaintexts(const Tables& T, int logn, const uint32_t* in, uint64_t* out, int nb, int L,
+                            const PtLayout& pl, hipStream_t s) {
+  const int rows = nb * pl.ell * L;
+  if (rows <= 0) return;
+  switch (logn) {
+    case 10: launch_fwd<10>(T, in, LOAD_LIFT_T, out, STORE_PLAINTEXT, rows, L, 0, pl, s); break;
+    case 11: launch_fwd<11>(T, in, LOAD_LIFT_T, out, STORE_PLAINTEXT, rows, L, 0, pl, s); break;
+    case 12: launch_fwd<12>(T, in, LOAD_LIFT_T, out, STORE_PLAINTEXT, rows, L, 0, pl, s); break;
+    case 13: launch_fwd<13>(T, in, LOAD_LIFT_T, out, STORE_PLAINTEXT, rows, L, 0, pl, s); break;
+    case 14: launch_fwd<14>(T, in, LOAD_LIFT_T, out, STORE_PLAINTEXT, rows, L, 0, pl, s); break;
   }
 }
 

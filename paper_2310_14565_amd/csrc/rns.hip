@@ -520,8 +520,10 @@ __global__ void __launch_bounds__(TPB) k_value_accumulate(Tables T, const uint64
 // FOLD = 254 terms (plus a restart value below 2^54) fit in 64 bits; every FOLD terms the value
 // lo + (ms - lo - hi) 2^27 + hi 2^54 is reduced and restarts both lo and ms (hi restarts at 0).
 // Loads of a partial group are clamped to its last batch so that every load is unconditional
-// (results of padding lanes are dropped).
+// (results of padding lanes are dropped).  A workgroup's slice is one 256-position block of the
+// plaintext store, where the IB batches of a group are one contiguous run per code position.
 constexpr int IB = 16;
+static_assert(TPB == PT_BLOCK, "a select-and-sum slice is one plaintext-store block");
 constexpr int FOLD = 254;
 __device__ __forceinline__ uint64_t fold3(uint64_t lo, uint64_t ms, uint64_t hi, const Prime& pr) {
   const uint64_t mid = ms - lo - hi;
@@ -534,8 +536,8 @@ __device__ __forceinline__ uint64_t fold3(uint64_t lo, uint64_t ms, uint64_t hi,
 // b & 7; the zg groups of a slice get consecutive numbers on one XCD, are resident together and
 // share the client values through that XCD's L2.
 __global__ void __launch_bounds__(TPB) k_select_sum(Tables T, const uint64_t* __restrict__ Cn,
-                                                   const uint64_t* __restrict__ Pc, int ell, int nb,
-                                                   uint64_t* __restrict__ S, long sstride, int slices, int zg) {
+                                                   const uint64_t* __restrict__ Pc, int gs, int bfirst, int ell,
+                                                   int nb, uint64_t* __restrict__ S, long sstride, int slices, int zg) {
   const Consts& C = *T.c;
   const int N = C.n, L = C.L;
   const int bid = blockIdx.x, local = bid >> 3;
@@ -555,11 +557,14 @@ __global__ void __launch_bounds__(TPB) k_select_sum(Tables T, const uint64_t* __
   for (int c = 0; c < 2; ++c)
 #pragma unroll
     for (int b = 0; b < IB; ++b) lo[c][b] = ms[c][b] = hi[c][b] = 0;
-  const size_t pstep = (size_t)L * N, cstep = (size_t)2 * L * N;
-  // wave-uniform row bases; each lane adds its position (scalar base + 32-bit lane offset)
+  const size_t pstep = (size_t)L * N * gs, cstep = (size_t)2 * L * N;
+  // wave-uniform block bases; each lane adds its position (scalar base + 32-bit lane offset)
   const uint64_t* pb[IB];
 #pragma unroll
-  for (int b = 0; b < IB; ++b) pb[b] = Pc + ((size_t)(b0 + min(b, nbl - 1)) * ell * L + l) * N + k0;
+  for (int b = 0; b < IB; ++b) {
+    const int bb = bfirst + b0 + min(b, nbl - 1), G = bb / gs, g = bb % gs;
+    pb[b] = Pc + ((((size_t)G * ell * L + l) * kchunks + k0 / PT_BLOCK) * gs + g) * PT_BLOCK;
+  }
   const uint64_t* cb = Cn + (size_t)l * N + k0;
   int fold = 0;
   for (int j = 0; j < ell; ++j) {
@@ -605,16 +610,21 @@ __global__ void __launch_bounds__(TPB) k_select_sum(Tables T, const uint64_t* __
 // three accumulators each as in k_select_sum), loading the next code position's values while
 // it multiplies the current ones.  The waves of a workgroup read the same client values (L1),
 // and blocks are numbered so that all query groups of one (positions, limb, batch group)
-// region are dispatched consecutively to the same XCD and share its L2 for the plaintexts.
+// region are dispatched consecutively to the same XCD and share its L2 for the plaintexts; the
+// four regions that cover one 256-position block of the plaintext store follow each other there,
+// so that the block's contiguous run is read at about the same time.
 constexpr int MQ = 2, MB = 16, MBB = 4, MTPB = 64 * (MB / MBB);
+constexpr int MRQ = PT_BLOCK / 64;   // regions per plaintext-store block
 __global__ void __launch_bounds__(MTPB) k_select_sum_multi(Tables T, const uint64_t* __restrict__ Cq,
                                                           long cq_stride, const int* __restrict__ qslot, int nq,
-                                                          const uint64_t* __restrict__ Pc, int ell, int nb,
-                                                          uint64_t* __restrict__ S, int regions, int qgroups) {
+                                                          const uint64_t* __restrict__ Pc, int gs, int bfirst,
+                                                          int ell, int nb, uint64_t* __restrict__ S, int regions,
+                                                          int qgroups) {
   const Consts& C = *T.c;
   const int N = C.n, L = C.L;
   const int bid = blockIdx.x, xcd = bid & 7, w8 = bid >> 3;
-  const int qg = w8 % qgroups, region = (w8 / qgroups) * 8 + xcd;
+  const int qg = w8 % qgroups, r8 = w8 / qgroups;
+  const int region = ((r8 / MRQ) * 8 + xcd) * MRQ + r8 % MRQ;
   if (region >= regions) return;
   const int kchunks = N / 64;
   const int kc = region % kchunks, l = (region / kchunks) % L, bg = region / (kchunks * L);
@@ -624,7 +634,7 @@ __global__ void __launch_bounds__(MTPB) k_select_sum_multi(Tables T, const uint6
   if (nbl <= 0) return;
   const Prime& pr = C.prm[l];
   constexpr uint64_t M27 = (1ull << 27) - 1;
-  const size_t cjs = (size_t)2 * L * N, pjs = (size_t)L * N;
+  const size_t cjs = (size_t)2 * L * N, pjs = (size_t)L * N * gs;
   const uint64_t* cp[MQ][2];
   const uint64_t* pp[MBB];
 #pragma unroll
@@ -634,8 +644,11 @@ __global__ void __launch_bounds__(MTPB) k_select_sum_multi(Tables T, const uint6
       cp[a][c] = Cq + (size_t)(qslot ? qslot[q0 + min(a, nql - 1)] : q0 + min(a, nql - 1)) * cq_stride +
                  ((size_t)c * L + l) * N + kbase + lane;
 #pragma unroll
-  for (int b = 0; b < MBB; ++b)
-    pp[b] = Pc + ((size_t)(b0 + min(b, nbl - 1)) * ell * L + l) * N + kbase + lane;
+  for (int b = 0; b < MBB; ++b) {
+    const int bb = bfirst + b0 + min(b, nbl - 1), G = bb / gs, g = bb % gs;
+    pp[b] = Pc + ((((size_t)G * ell * L + l) * (N / PT_BLOCK) + kbase / PT_BLOCK) * gs + g) * PT_BLOCK +
+            kbase % PT_BLOCK + lane;
+  }
   uint64_t lo[MQ][2][MBB], ms[MQ][2][MBB], hi[MQ][2][MBB];
 #pragma unroll
   for (int a = 0; a < MQ; ++a)
@@ -1053,21 +1066,22 @@ void expand_uniform(const Tables& T, const Consts& hc, const ChaChaKey& key, int
 void mod_switch(const Tables& T, const Consts& hc, const uint64_t* ct, uint64_t* out, hipStream_t s) {
   PEPSI_L_LAUNCH(k_mod_switch, hc.L, grid_for(hc.n, 2), dim3(TPB), s, T, ct, out);
 }
-void select_sum(const Tables& T, const Consts& hc, const uint64_t* Cn, const uint64_t* P, int ell,
-                int nb, uint64_t* S, long sstride, hipStream_t s) {
+void select_sum(const Tables& T, const Consts& hc, const uint64_t* Cn, const uint64_t* P, int gs, int bfirst,
+                int ell, int nb, uint64_t* S, long sstride, hipStream_t s) {
   if (nb <= 0) return;
   const int slices = hc.n / TPB * hc.L, zg = (nb + IB - 1) / IB;
-  hipLaunchKernelGGL(k_select_sum, dim3((slices + 7) / 8 * 8 * zg), dim3(TPB), 0, s, T, Cn, P, ell, nb, S,
-                     sstride, slices, zg);
+  hipLaunchKernelGGL(k_select_sum, dim3((slices + 7) / 8 * 8 * zg), dim3(TPB), 0, s, T, Cn, P, gs, bfirst, ell,
+                     nb, S, sstride, slices, zg);
 }
 void select_sum_multi(const Tables& T, const Consts& hc, const uint64_t* Cq, long cq_stride, const int* qslot,
-                      int nq, const uint64_t* P, int ell, int nb, uint64_t* S, hipStream_t s) {
+                      int nq, const uint64_t* P, int gs, int bfirst, int ell, int nb, uint64_t* S,
+                      hipStream_t s) {
   if (nb <= 0 || nq <= 0) return;
   const int regions = (hc.n / 64) * hc.L * ((nb + MB - 1) / MB);
   const int qgroups = (nq + MQ - 1) / MQ;
-  const int blocks = ((regions + 7) / 8) * 8 * qgroups;
-  hipLaunchKernelGGL(k_select_sum_multi, dim3(blocks), dim3(MTPB), 0, s, T, Cq, cq_stride, qslot, nq, P, ell,
-                     nb, S, regions, qgroups);
+  const int blocks = ((regions + 8 * MRQ - 1) / (8 * MRQ)) * 8 * MRQ * qgroups;
+  hipLaunchKernelGGL(k_select_sum_multi, dim3(blocks), dim3(MTPB), 0, s, T, Cq, cq_stride, qslot, nq, P, gs,
+                     bfirst, ell, nb, S, regions, qgroups);
 }
 void pointwise_mul(const Tables& T, const Consts& hc, const uint64_t* a, const uint64_t* b,
                    uint64_t* out, int rows, int nprimes, bool bcast, hipStream_t s) {

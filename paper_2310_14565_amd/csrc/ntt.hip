@@ -120,16 +120,16 @@ __device__ __forceinline__ void inv_pass(uint64_t* x, int tid, const uint64_t* _
 
 // A thread writes back exactly the LDS words it read for the same pass, so a pass needs a barrier
 // only before its reads.
-template <int LOGN, int EL, int S0, int D>
-__device__ __forceinline__ void to_lds(uint64_t* lds, const uint64_t* x, int tid) {
+template <int LOGN, int EL, int S0, int D, class V>
+__device__ __forceinline__ void to_lds(V* lds, const V* x, int tid) {
 #pragma unroll
   for (int u = 0; u < (1 << (EL - D)); ++u)
 #pragma unroll
     for (int m = 0; m < (1 << D); ++m)
       lds[lds_idx(elem_index<LOGN, EL, S0, D>(tid, u, m))] = x[u * (1 << D) + m];
 }
-template <int LOGN, int EL, int S0, int D>
-__device__ __forceinline__ void from_lds(uint64_t* x, const uint64_t* lds, int tid) {
+template <int LOGN, int EL, int S0, int D, class V>
+__device__ __forceinline__ void from_lds(V* x, const V* lds, int tid) {
 #pragma unroll
   for (int u = 0; u < (1 << (EL - D)); ++u)
 #pragma unroll
@@ -349,24 +349,79 @@ __global__ void __launch_bounds__(256) k_decode(Tables T, const uint32_t* __rest
   for (int k = threadIdx.x; k < N; k += blockDim.x) slots[row * N + brv(k, LOGN)] = a[k];
 }
 
-// Row (b, j): slot k is 1 iff position j is one of the h codeword positions of bin k.
-template <int LOGN>
-__global__ void __launch_bounds__(256) k_encode_planes(Tables T, const uint16_t* __restrict__ cw, int h,
-                                                      int ell, int b0, uint32_t* __restrict__ poly) {
-  constexpr int N = 1 << LOGN;
-  __shared__ uint32_t a[N];
+// a b mod t for t = 2^16 + 1 and a, b <= 2^16: with a b = xh 2^16 + xl and 2^16 = -1 mod t, the
+// residue is xl - xh.
+__device__ __forceinline__ uint32_t mulmod_t16(uint32_t a, uint32_t b) {
+  const uint64_t x = (uint64_t)a * b;   // <= 2^32
+  const uint32_t xl = (uint32_t)x & 0xffffu, xh = (uint32_t)(x >> 16);
+  return xl >= xh ? xl - xh : xl + PEPSI_T - xh;
+}
+
+// Inverse stages S0 + D - 1 down to S0 over Z_t (Gentleman-Sande, residues kept reduced), with the
+// register layout of inv_pass.
+template <int LOGN, int EL, int S0, int D>
+__device__ __forceinline__ void inv_pass_t(uint32_t* x, int tid, const uint32_t* __restrict__ W) {
+  constexpr int N = 1 << LOGN, T = N >> EL, LOW = N >> (S0 + D), G = 1 << (EL - D);
+#pragma unroll
+  for (int u = 0; u < G; ++u) {
+    const int hi = (tid + T * u) / LOW;
+#pragma unroll
+    for (int r = D - 1; r >= 0; --r) {
+      const int half = 1 << (D - 1 - r);
+#pragma unroll
+      for (int blk = 0; blk < (1 << r); ++blk) {
+        const uint32_t w = W[(1 << (S0 + r)) + ((hi << r) | blk)];
+#pragma unroll
+        for (int m = 0; m < half; ++m) {
+          const int a = u * (1 << D) + blk * 2 * half + m, b = a + half;
+          const uint32_t U = x[a], V = x[b];
+          x[a] = addmod_t(U, V);
+          x[b] = mulmod_t16(submod_t(U, V), w);
+        }
+      }
+    }
+  }
+}
+template <int LOGN, int EL, int K>
+__device__ __forceinline__ void inv_passes_t(uint32_t* x, uint32_t* lds, int tid, const uint32_t* __restrict__ W) {
+  constexpr int S0 = K * EL, D = (LOGN - S0 < EL) ? LOGN - S0 : EL;
+  __syncthreads();
+  from_lds<LOGN, EL, S0, D>(x, lds, tid);
+  inv_pass_t<LOGN, EL, S0, D>(x, tid, W);
+  to_lds<LOGN, EL, S0, D>(lds, x, tid);
+  if constexpr (K > 1) inv_passes_t<LOGN, EL, K - 1>(x, lds, tid, W);
+}
+
+// Row (b, j): slot s is 1 iff position j is one of the h codeword positions of bin s; the row is
+// then inverse-transformed over t (bit-reversed slots in, coefficients out) and scaled by N^-1.
+// Same register passes as k_ntt_inv: each thread reads the codewords of E slots (coalesced) and
+// places their bits at the bit-reversed LDS positions; the last pass leaves coefficient m TT + tid
+// in register m.
+template <int LOGN, int EL = ntt_el<LOGN>()>
+__global__ void __launch_bounds__((1 << LOGN) >> EL)
+k_encode_planes(Tables T, const uint16_t* __restrict__ cw, int h, int ell, int b0, uint32_t* __restrict__ poly) {
+  constexpr int N = 1 << LOGN, E = 1 << EL, TT = N >> EL, NP = (LOGN + EL - 1) / EL;
+  static_assert(NP >= 2, "at least two passes");
+  __shared__ uint32_t lt[N + N / 32];
   const size_t row = blockIdx.x;
   const int b = (int)(row / ell) + b0, j = (int)(row % ell);
   const uint16_t* base = cw + (size_t)b * N * h;
-  for (int k = threadIdx.x; k < N; k += blockDim.x) {
-    const int slot = brv(k, LOGN);
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int s = m * TT + tid;
     uint32_t y = 0;
-    for (int r = 0; r < h; ++r) y |= (base[(size_t)slot * h + r] == j) ? 1u : 0u;
-    a[k] = y;
+    for (int r = 0; r < h; ++r) y |= (base[(size_t)s * h + r] == j) ? 1u : 0u;
+    lt[lds_idx(brv(s, LOGN))] = y;
   }
+  uint32_t x[E];
+  inv_passes_t<LOGN, EL, NP - 1>(x, lt, tid, T.ipsit_rev);
   __syncthreads();
-  intt_t_lds<LOGN>(a, T.ipsit_rev, T.c->n_inv_t);
-  for (int k = threadIdx.x; k < N; k += blockDim.x) poly[row * N + k] = a[k];
+  from_lds<LOGN, EL, 0, EL>(x, lt, tid);
+  inv_pass_t<LOGN, EL, 0, EL>(x, tid, T.ipsit_rev);
+  const uint32_t ninv = T.c->n_inv_t;
+#pragma unroll
+  for (int m = 0; m < E; ++m) poly[row * N + m * TT + tid] = mulmod_t16(x[m], ninv);
 }
 
 template <int LOGN>
@@ -449,7 +504,16 @@ void encode_server_planes(const Tables& T, int logn, const uint16_t* cw, int h, 
                           int nb, uint32_t* poly, hipStream_t s) {
   const int rows = nb * ell;
   if (rows <= 0) return;
-  PEPSI_T_DISPATCH(k_encode_planes, T, cw, h, ell, b0, poly)
+#define PEPSI_ENC(LL) hipLaunchKernelGGL(k_encode_planes<LL>, dim3(rows), dim3((1 << LL) >> ntt_el<LL>()), 0, s, T, \
+                                         cw, h, ell, b0, poly)
+  switch (logn) {
+    case 10: PEPSI_ENC(10); break;
+    case 11: PEPSI_ENC(11); break;
+    case 12: PEPSI_ENC(12); break;
+    case 13: PEPSI_ENC(13); break;
+    case 14: PEPSI_ENC(14); break;
+  }
+#undef PEPSI_ENC
 }
 
 }  // namespace pepsi

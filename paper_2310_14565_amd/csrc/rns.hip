@@ -460,12 +460,15 @@ __global__ void __launch_bounds__(TPB) k_relin_inner(Tables T, const uint64_t* _
 
 // acc[slot(q)] += sum over batches b of x[b * nq + q]: entries of `rows` rows of N residues,
 // row r modulo q_(r mod L), xstride words apart in x and astride words apart in acc.
-__global__ void __launch_bounds__(TPB) k_accumulate(Tables T, const uint64_t* __restrict__ x,
-                                                   long xstride, int nb, int nq, const int* __restrict__ qslot,
-                                                   uint64_t* __restrict__ acc, long astride) {
+// Accumulations run a thread per coefficient down the batches: small workgroups (more of them
+// in flight) and AU loads issued together per thread keep enough reads outstanding.
+constexpr int ATPB = 64, AU = 8;
+__global__ void __launch_bounds__(ATPB) k_accumulate(Tables T, const uint64_t* __restrict__ x,
+                                                    long xstride, int nb, int nq, const int* __restrict__ qslot,
+                                                    uint64_t* __restrict__ acc, long astride) {
   const Consts& C = *T.c;
   const int N = C.n, L = C.L;
-  const int k = blockIdx.x * TPB + threadIdx.x;
+  const int k = blockIdx.x * ATPB + threadIdx.x;
   const int cl = blockIdx.y;
   const int q = blockIdx.z;
   if (k >= N) return;
@@ -476,6 +479,13 @@ __global__ void __launch_bounds__(TPB) k_accumulate(Tables T, const uint64_t* __
   while (b < nb) {
     u128 t = s;
     const int end = min(nb, b + 1000);             // 1000 * 2^54 stays below 2^116
+    for (; b + AU <= end; b += AU) {
+      uint64_t v[AU];
+#pragma unroll
+      for (int i = 0; i < AU; ++i) v[i] = x[((size_t)(b + i) * nq + q) * xstride + (size_t)cl * N + k];
+#pragma unroll
+      for (int i = 0; i < AU; ++i) t += v[i];
+    }
     for (; b < end; ++b) t += x[((size_t)b * nq + q) * xstride + (size_t)cl * N + k];
     s = reduce116((uint64_t)t, (uint64_t)(t >> 64), pr);
   }
@@ -485,13 +495,13 @@ __global__ void __launch_bounds__(TPB) k_accumulate(Tables T, const uint64_t* __
 // acc[slot(q)] += sum over batches b of x[b * nq + q] (.) vhat[b]: the server values of each
 // batch (NTT form [L][N], one plaintext per batch) times that batch's equality ciphertexts
 // (NTT form [2][L][N], xstride words apart), accumulated per query (NTT form).
-__global__ void __launch_bounds__(TPB) k_value_accumulate(Tables T, const uint64_t* __restrict__ x,
-                                                         long xstride, const uint64_t* __restrict__ vhat,
-                                                         int nb, int nq, const int* __restrict__ qslot,
-                                                         uint64_t* __restrict__ acc, long astride) {
+__global__ void __launch_bounds__(ATPB) k_value_accumulate(Tables T, const uint64_t* __restrict__ x,
+                                                          long xstride, const uint64_t* __restrict__ vhat,
+                                                          int nb, int nq, const int* __restrict__ qslot,
+                                                          uint64_t* __restrict__ acc, long astride) {
   const Consts& C = *T.c;
   const int N = C.n, L = C.L;
-  const int k = blockIdx.x * TPB + threadIdx.x;
+  const int k = blockIdx.x * ATPB + threadIdx.x;
   const int cl = blockIdx.y;                       // component * L + limb
   const int q = blockIdx.z;
   if (k >= N) return;
@@ -503,6 +513,16 @@ __global__ void __launch_bounds__(TPB) k_value_accumulate(Tables T, const uint64
   while (b < nb) {
     u128 t = s;
     const int end = min(nb, b + 200);              // 200 products below 2^108 stay below 2^116
+    for (; b + AU <= end; b += AU) {
+      uint64_t v[AU], w[AU];
+#pragma unroll
+      for (int i = 0; i < AU; ++i) {
+        v[i] = x[((size_t)(b + i) * nq + q) * xstride + (size_t)cl * N + k];
+        w[i] = vhat[((size_t)(b + i) * L + l) * N + k];
+      }
+#pragma unroll
+      for (int i = 0; i < AU; ++i) t += (u128)v[i] * w[i];
+    }
     for (; b < end; ++b)
       t += (u128)x[((size_t)b * nq + q) * xstride + (size_t)cl * N + k] * vhat[((size_t)b * L + l) * N + k];
     s = reduce116((uint64_t)t, (uint64_t)(t >> 64), pr);
@@ -1048,14 +1068,14 @@ void relin_inner(const Tables& T, const Consts& hc, const uint64_t* c01h, const 
 void accumulate(const Tables& T, const Consts& hc, const uint64_t* x, long xstride, int nb, int nq,
                 int rows, const int* qslot, uint64_t* acc, long astride, hipStream_t s) {
   if (nb <= 0 || nq <= 0 || rows <= 0) return;
-  hipLaunchKernelGGL(k_accumulate, grid_for(hc.n, rows, nq), dim3(TPB), 0, s, T, x, xstride, nb, nq, qslot,
-                     acc, astride);
+  hipLaunchKernelGGL(k_accumulate, dim3((hc.n + ATPB - 1) / ATPB, rows, nq), dim3(ATPB), 0, s, T, x, xstride, nb,
+                     nq, qslot, acc, astride);
 }
 void value_accumulate(const Tables& T, const Consts& hc, const uint64_t* x, long xstride, const uint64_t* vhat,
                       int nb, int nq, const int* qslot, uint64_t* acc, long astride, hipStream_t s) {
   if (nb <= 0 || nq <= 0) return;
-  hipLaunchKernelGGL(k_value_accumulate, grid_for(hc.n, 2 * hc.L, nq), dim3(TPB), 0, s, T, x, xstride, vhat, nb,
-                     nq, qslot, acc, astride);
+  hipLaunchKernelGGL(k_value_accumulate, dim3((hc.n + ATPB - 1) / ATPB, 2 * hc.L, nq), dim3(ATPB), 0, s, T, x,
+                     xstride, vhat, nb, nq, qslot, acc, astride);
 }
 void expand_uniform(const Tables& T, const Consts& hc, const ChaChaKey& key, int first, int count,
                     uint64_t* out, long stride, hipStream_t s) {

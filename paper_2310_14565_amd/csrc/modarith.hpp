@@ -2,8 +2,9 @@
 //
 // Every prime p used on the GPU lies in (2^53, 2^54) and satisfies
 // p = 1 mod 2N (negacyclic NTT-friendly); t = 65537 is handled separately.
-// Residues are kept as uint64 in [0, p) at kernel boundaries and lazily in
-// [0, 4p) inside the NTT butterflies (4p < 2^56).
+// Residues are kept as uint64 in [0, p) at kernel boundaries; inside the NTT
+// butterflies they are lazy (below 57p in the forward transform, below
+// 2^4 4p within an inverse pass), always below 2^61.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>

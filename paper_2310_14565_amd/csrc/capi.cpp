@@ -928,7 +928,7 @@ extern "C" int pepsi_server_eval_range(pepsi_server* sv, const uint64_t* cts, co
   if (begin > end || end > (uint32_t)H.mu) return fail(PEPSI_E_ARG, "bad batch range");
   hipStream_t s = S(stream);
   if (!sv->ready) {
-    const int tb = std::min<int>(256, std::max<int>(1, (int)sv->max_load));
+    const int tb = std::min<int>(512, std::max<int>(1, (int)sv->max_load));
     int rc = sv->eng.setup(sv->P, tb, 1, sv->cached_batches < sv->max_load, sv->values_hat());
     if (rc) return rc;
     sv->eng.timer = &sv->timer;

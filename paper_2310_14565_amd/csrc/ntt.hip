@@ -17,8 +17,9 @@
 // its words back below 4p at its end, the last leaves them below 2^EL 4p for
 // the final N^-1 product.
 //
-// Transforms over t = 65537 (batch encoding of slots) are cheap 32-bit
-// radix-2 loops over LDS.
+// Transforms over t = 65537 (batch encoding of slots and of the server bit
+// planes) use the same register passes with 32-bit residues; decoding, which
+// is not on the server path, is a radix-2 loop over LDS.
 #include "kernels.hpp"
 
 namespace pepsi {
@@ -288,26 +289,6 @@ k_ntt_inv(Tables T, const uint64_t* __restrict__ in, uint64_t* __restrict__ out,
 
 __device__ __forceinline__ int brv(int k, int logn) { return (int)(__brev((unsigned)k) >> (32 - logn)); }
 
-// Gentleman-Sande inverse over Z_t on an LDS row; the row holds bit-reversed evaluations.
-template <int LOGN>
-__device__ void intt_t_lds(uint32_t* a, const uint32_t* __restrict__ iw, uint32_t n_inv) {
-  constexpr int N = 1 << LOGN;
-  for (int s = LOGN - 1; s >= 0; --s) {
-    const int t = N >> (s + 1);
-    for (int bi = threadIdx.x; bi < N / 2; bi += blockDim.x) {
-      const int i = bi / t, off = bi % t;
-      const int x = i * 2 * t + off, y = x + t;
-      const uint32_t w = iw[(1 << s) + i];
-      const uint32_t U = a[x], V = a[y];
-      a[x] = addmod_t(U, V);
-      a[y] = mulmod_t(submod_t(U, V), w);
-    }
-    __syncthreads();
-  }
-  for (int k = threadIdx.x; k < N; k += blockDim.x) a[k] = mulmod_t(a[k], n_inv);
-  __syncthreads();
-}
-
 template <int LOGN>
 __device__ void ntt_t_lds(uint32_t* a, const uint32_t* __restrict__ w_rev) {
   constexpr int N = 1 << LOGN;
@@ -323,18 +304,6 @@ __device__ void ntt_t_lds(uint32_t* a, const uint32_t* __restrict__ w_rev) {
     }
     __syncthreads();
   }
-}
-
-template <int LOGN>
-__global__ void __launch_bounds__(256) k_encode(Tables T, const uint32_t* __restrict__ slots,
-                                               uint32_t* __restrict__ poly) {
-  constexpr int N = 1 << LOGN;
-  __shared__ uint32_t a[N];
-  const size_t row = blockIdx.x;
-  for (int k = threadIdx.x; k < N; k += blockDim.x) a[k] = slots[row * N + brv(k, LOGN)] % PEPSI_T;
-  __syncthreads();
-  intt_t_lds<LOGN>(a, T.ipsit_rev, T.c->n_inv_t);
-  for (int k = threadIdx.x; k < N; k += blockDim.x) poly[row * N + k] = a[k];
 }
 
 template <int LOGN>
@@ -392,6 +361,21 @@ __device__ __forceinline__ void inv_passes_t(uint32_t* x, uint32_t* lds, int tid
   if constexpr (K > 1) inv_passes_t<LOGN, EL, K - 1>(x, lds, tid, W);
 }
 
+// Inverse transform over t of a row whose bit-reversed evaluations are in LDS (at lds_idx
+// positions), scaled by N^-1: coefficient m TT + tid ends in x[m].
+template <int LOGN, int EL>
+__device__ __forceinline__ void intt_t_row(uint32_t* x, uint32_t* lt, int tid, const Tables& T) {
+  constexpr int E = 1 << EL, NP = (LOGN + EL - 1) / EL;
+  static_assert(NP >= 2, "at least two passes");
+  inv_passes_t<LOGN, EL, NP - 1>(x, lt, tid, T.ipsit_rev);
+  __syncthreads();
+  from_lds<LOGN, EL, 0, EL>(x, lt, tid);
+  inv_pass_t<LOGN, EL, 0, EL>(x, tid, T.ipsit_rev);
+  const uint32_t ninv = T.c->n_inv_t;
+#pragma unroll
+  for (int m = 0; m < E; ++m) x[m] = mulmod_t16(x[m], ninv);
+}
+
 // Row (b, j): slot s is 1 iff position j is one of the h codeword positions of bin s; the row is
 // then inverse-transformed over t (bit-reversed slots in, coefficients out) and scaled by N^-1.
 // Same register passes as k_ntt_inv: each thread reads the codewords of E slots (coalesced) and
@@ -400,8 +384,7 @@ __device__ __forceinline__ void inv_passes_t(uint32_t* x, uint32_t* lds, int tid
 template <int LOGN, int EL = ntt_el<LOGN>()>
 __global__ void __launch_bounds__((1 << LOGN) >> EL)
 k_encode_planes(Tables T, const uint16_t* __restrict__ cw, int h, int ell, int b0, uint32_t* __restrict__ poly) {
-  constexpr int N = 1 << LOGN, E = 1 << EL, TT = N >> EL, NP = (LOGN + EL - 1) / EL;
-  static_assert(NP >= 2, "at least two passes");
+  constexpr int N = 1 << LOGN, E = 1 << EL, TT = N >> EL;
   __shared__ uint32_t lt[N + N / 32];
   const size_t row = blockIdx.x;
   const int b = (int)(row / ell) + b0, j = (int)(row % ell);
@@ -415,13 +398,29 @@ k_encode_planes(Tables T, const uint16_t* __restrict__ cw, int h, int ell, int b
     lt[lds_idx(brv(s, LOGN))] = y;
   }
   uint32_t x[E];
-  inv_passes_t<LOGN, EL, NP - 1>(x, lt, tid, T.ipsit_rev);
-  __syncthreads();
-  from_lds<LOGN, EL, 0, EL>(x, lt, tid);
-  inv_pass_t<LOGN, EL, 0, EL>(x, tid, T.ipsit_rev);
-  const uint32_t ninv = T.c->n_inv_t;
+  intt_t_row<LOGN, EL>(x, lt, tid, T);
 #pragma unroll
-  for (int m = 0; m < E; ++m) poly[row * N + m * TT + tid] = mulmod_t16(x[m], ninv);
+  for (int m = 0; m < E; ++m) poly[row * N + m * TT + tid] = x[m];
+}
+
+// Batch encoding of slot rows (slot s of row r at slots[r N + s]): the bit-reversed slots are
+// inverse-transformed over t like the bit planes of k_encode_planes.
+template <int LOGN, int EL = ntt_el<LOGN>()>
+__global__ void __launch_bounds__((1 << LOGN) >> EL)
+k_encode(Tables T, const uint32_t* __restrict__ slots, uint32_t* __restrict__ poly) {
+  constexpr int N = 1 << LOGN, E = 1 << EL, TT = N >> EL;
+  __shared__ uint32_t lt[N + N / 32];
+  const size_t row = blockIdx.x;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int s = m * TT + tid;
+    lt[lds_idx(brv(s, LOGN))] = slots[row * N + s] % PEPSI_T;
+  }
+  uint32_t x[E];
+  intt_t_row<LOGN, EL>(x, lt, tid, T);
+#pragma unroll
+  for (int m = 0; m < E; ++m) poly[row * N + m * TT + tid] = x[m];
 }
 
 template <int LOGN>
@@ -493,7 +492,16 @@ void ntt_inverse(const Tables& T, int logn, const uint64_t* in, uint64_t* out, i
 void encode_slots(const Tables& T, int logn, const uint32_t* slots, uint32_t* poly, int rows,
                   hipStream_t s) {
   if (rows <= 0) return;
-  PEPSI_T_DISPATCH(k_encode, T, slots, poly)
+#define PEPSI_ENC1(LL) hipLaunchKernelGGL(k_encode<LL>, dim3(rows), dim3((1 << LL) >> ntt_el<LL>()), 0, s, T, slots, \
+                                          poly)
+  switch (logn) {
+    case 10: PEPSI_ENC1(10); break;
+    case 11: PEPSI_ENC1(11); break;
+    case 12: PEPSI_ENC1(12); break;
+    case 13: PEPSI_ENC1(13); break;
+    case 14: PEPSI_ENC1(14); break;
+  }
+#undef PEPSI_ENC1
 }
 void decode_slots(const Tables& T, int logn, const uint32_t* poly, uint32_t* slots, int rows,
                   hipStream_t s) {

@@ -429,7 +429,7 @@ struct Engine {
   int TBq = 0, Qmax = 0, levels = 0;
   std::vector<int> jobs_at;            // tensor jobs per pair at each tree level
   DevBuf chat, rlkhat, acc, accD;      // per query: request and key in NTT form, running sums
-  DevBuf sq, scoef, sb, sbh, alpha, e; // per pair: S over Q (NTT, coefficients), over B (both), ...
+  DevBuf sq, scoef, sb, sbh, alpha, pconst, e; // per pair: S over Q (NTT, coefficients), over B (both), ...
   DevBuf d, c01, c01h, c2, D, rcoef;   // per tensor job
   std::vector<DevBuf> rq, rb;          // per tree level outputs
   DevBuf jobs;                         // device TensorJob arrays, all levels
@@ -439,7 +439,7 @@ struct Engine {
   const uint64_t* vhat = nullptr;      // server-value plaintexts [max_load][L][N] (NTT form) or null
 
   ~Engine() {
-    for (DevBuf* b : {&chat, &rlkhat, &acc, &accD, &sq, &scoef, &sb, &sbh, &alpha, &e, &d, &c01, &c01h, &c2, &D,
+    for (DevBuf* b : {&chat, &rlkhat, &acc, &accD, &sq, &scoef, &sb, &sbh, &alpha, &pconst, &e, &d, &c01, &c01h, &c2, &D,
                       &rcoef, &jobs, &gen_poly, &gen_p})
       b->release();
     for (auto& b : rq) b.release();
@@ -476,6 +476,7 @@ struct Engine {
       if ((rc = sb.ensure(PC * 2 * K * n * 8))) return rc;
       if ((rc = sbh.ensure(PC * 2 * K * n * 8))) return rc;
       if ((rc = alpha.ensure(PC * H.h * Pn * 8))) return rc;
+      if ((rc = pconst.ensure(PC * std::max(1, H.h / 2) * Pn * 2 * 8))) return rc;
       if ((rc = d.ensure(J * 3 * Pn * n * 8))) return rc;
       if ((rc = c01.ensure(J * 2 * L * n * 8))) return rc;
       if ((rc = c01h.ensure(J * 2 * L * n * 8))) return rc;
@@ -574,8 +575,9 @@ struct Engine {
     uint64_t* dd = d.as<uint64_t>();
     square_products(P->T, H.consts, Sq, sbh.as<uint64_t>(), dd, npairs, s);
     ntt_inverse(P->T, H.logn, dd, dd, npairs * 3 * Pn, Pn, 0, s);
-    scale_round_first(P->T, H.consts, dd, scoef.as<uint64_t>(), sb.as<uint64_t>(), alpha.as<uint64_t>(), H.h,
-                      npairs, c01.as<uint64_t>(), c2.as<uint64_t>(), P->fallback.as<uint32_t>(), s);
+    scale_round_first(P->T, H.consts, dd, scoef.as<uint64_t>(), sb.as<uint64_t>(), alpha.as<uint64_t>(),
+                      pconst.as<uint64_t>(), H.h, npairs, c01.as<uint64_t>(), c2.as<uint64_t>(),
+                      P->fallback.as<uint32_t>(), s);
   }
 
   // A later tree level: njobs independent products (TensorJob operands) into c01 / c2.
@@ -677,7 +679,7 @@ struct Engine {
     ext_q_to_b(P->T, H.consts, scoef.as<uint64_t>(), sb.as<uint64_t>(), (long)(K * n), npairs * 2,
                P->fallback.as<uint32_t>(), s);
     ntt_forward(P->T, H.logn, sb.p, LOAD_U64, sbh.p, STORE_U64, npairs * 2 * (int)K, (int)K, (int)L, s);
-    factor_constants(P->T, H.consts, scoef.as<uint64_t>(), npairs, H.h, alpha.as<uint64_t>(),
+    factor_constants(P->T, H.consts, scoef.as<uint64_t>(), npairs, H.h, alpha.as<uint64_t>(), pconst.as<uint64_t>(),
                      P->fallback.as<uint32_t>(), s);
     // the key of a single active query: shift the key base to its slot
     const int* rslot = nq == 1 ? nullptr : qslot;

@@ -55,8 +55,10 @@ void ext_q_to_b(const Tables& T, const Consts& hc, const uint64_t* in, uint64_t*
 // The h factor constants of one select-and-sum ciphertext per batch: alpha[b][r][p] is
 // added to every NTT position of c0's limb p for f_r = S + Delta * [-r]_t.
 // scoef: coefficient form [nb][2][L][N] (only coefficient 0 of c0 is read).
+// Also, for every pair and first-level job u (factors 2u, 2u + 1), the sum s = delta_2u +
+// delta_2u+1 mod every prime of Q u B and its Shoup companion: pconst [nb][h / 2][L + K][2].
 void factor_constants(const Tables& T, const Consts& hc, const uint64_t* scoef, int nb, int h,
-                      uint64_t* alpha, uint32_t* fallback_count, hipStream_t s);
+                      uint64_t* alpha, uint64_t* pconst, uint32_t* fallback_count, hipStream_t s);
 // Tensor of two extended ciphertexts in NTT form, each given as its Q part [2][L][N] and
 // its B part [2][K][N], with optional constants (per limb of Q u B, may be null) added to
 // every position of c0: d = [3][L+K][N] (limb p of Q u B at row p).
@@ -78,8 +80,8 @@ void scale_round(const Tables& T, const Consts& hc, const uint64_t* d, uint64_t*
 // alpha [pairs][h][L+K] = delta_r mod each prime.  c01 [pairs * h/2][2][L][N], c2 [pairs][L][N]
 // (component 2 is X1^2 for every product of a pair).
 void scale_round_first(const Tables& T, const Consts& hc, const uint64_t* d, const uint64_t* xq,
-                       const uint64_t* xb, const uint64_t* alpha, int h, int pairs, uint64_t* c01, uint64_t* c2,
-                       uint32_t* fallback_count, hipStream_t s);
+                       const uint64_t* xb, const uint64_t* alpha, const uint64_t* pconst, int h, int pairs,
+                       uint64_t* c01, uint64_t* c2, uint32_t* fallback_count, hipStream_t s);
 // relinearisation digits: c2 [units][L][N] coefficient form -> D [units][L][L][N]
 void relin_digits(const Tables& T, const Consts& hc, const uint64_t* c2, uint64_t* D, int units,
                   hipStream_t s);

@@ -67,10 +67,14 @@ PEPSI_HD uint64_t shoup_companion(uint64_t w, uint64_t p) {
 
 // x mod p for x = hi:lo < 2^116 (Barrett with the quotient estimated from
 // x >> 52; the estimate is at most 2 short, so two corrections suffice).
-PEPSI_HD uint64_t reduce116(uint64_t lo, uint64_t hi, const Prime& P) {
+// The same without the corrections: congruent to x and below 3p.
+PEPSI_HD uint64_t reduce116_lazy(uint64_t lo, uint64_t hi, const Prime& P) {
   uint64_t top = (lo >> 52) | (hi << 12);          // floor(x / 2^52) < 2^64
   uint64_t q = mulhi64(top, P.barrett);            // ~ floor(x / p)
-  uint64_t r = lo - q * P.p;                       // true remainder + k p, k in {0,1,2}
+  return lo - q * P.p;                             // true remainder + k p, k in {0,1,2}
+}
+PEPSI_HD uint64_t reduce116(uint64_t lo, uint64_t hi, const Prime& P) {
+  uint64_t r = reduce116_lazy(lo, hi, P);
   if (r >= P.p) r -= P.p;
   if (r >= P.p) r -= P.p;
   return r;

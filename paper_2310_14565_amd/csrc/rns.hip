@@ -172,6 +172,12 @@ struct Acc3 {
     const u128 v = (u128)lo + ((u128)mid << 27) + ((u128)hi << 54);   // below 2^112
     return reduce116((uint64_t)v, (uint64_t)(v >> 64), pr);
   }
+  // congruent and below 3p, for a value that goes straight into a Shoup product
+  __device__ __forceinline__ uint64_t reduce_lazy(const Prime& pr) const {
+    const uint64_t mid = ms - lo - hi;
+    const u128 v = (u128)lo + ((u128)mid << 27) + ((u128)hi << 54);
+    return reduce116_lazy((uint64_t)v, (uint64_t)(v >> 64), pr);
+  }
 };
 
 // Centred lift of x (residues mod q_0..q_{L-1}) into the residues mod b_0..b_{K-1}, K = L + 1.
@@ -244,6 +250,20 @@ __global__ void k_factor_constants(Tables T, const uint64_t* __restrict__ scoef,
   for (int j = 0; j < K; ++j) out[L + j] = submod(er[j], e0[j], C.prm[L + j].p);
 }
 
+// s = delta_2u + delta_2u+1 mod p and floor(s 2^64 / p) for every (pair, job u, prime p).
+__global__ void __launch_bounds__(TPB) k_pair_constants(Tables T, const uint64_t* __restrict__ alpha, int npairs,
+                                                       int h, uint64_t* __restrict__ pconst) {
+  const Consts& C = *T.c;
+  const int P = C.L + C.K, J0 = h / 2;
+  const int idx = blockIdx.x * TPB + threadIdx.x;
+  if (idx >= npairs * J0 * P) return;
+  const int p = idx % P, u = (idx / P) % J0, pair = idx / (P * J0);
+  const uint64_t q = C.prm[p].p;
+  const uint64_t s = addmod(alpha[((size_t)pair * h + 2 * u) * P + p], alpha[((size_t)pair * h + 2 * u + 1) * P + p], q);
+  pconst[2 * (size_t)idx] = s;
+  pconst[2 * (size_t)idx + 1] = shoup_companion(s, q);
+}
+
 __global__ void __launch_bounds__(TPB) k_tensor(Tables T, const TensorJob* __restrict__ jobs) {
   const Consts& C = *T.c;
   const int N = C.n, L = C.L, K = C.K, P = L + K;
@@ -305,7 +325,8 @@ template <int L, bool FIRST>
 __global__ void __launch_bounds__(TPB) k_scale_round(Tables T, const uint64_t* __restrict__ d,
                                                     const uint64_t* __restrict__ xq,
                                                     const uint64_t* __restrict__ xb,
-                                                    const uint64_t* __restrict__ alpha, int h, int J0,
+                                                    const uint64_t* __restrict__ alpha,
+                                                    const uint64_t* __restrict__ pconst, int h, int J0,
                                                     uint64_t* __restrict__ c01, uint64_t* __restrict__ c2,
                                                     uint32_t* fallback) {
   const Consts& C = *T.c;
@@ -320,9 +341,9 @@ __global__ void __launch_bounds__(TPB) k_scale_round(Tables T, const uint64_t* _
   int u = 0, comp;
   bool lin = false;
   if (FIRST) {
-    const int per = 2 * J0 + 1;
-    pair = poly / per;
-    const int e = (int)(poly % per);
+    const int per = 2 * J0 + 1, pi = (int)blockIdx.y;   // 32-bit division: far cheaper than 64-bit
+    pair = (size_t)(pi / per);
+    const int e = pi % per;
     if (e < 2 * J0) {
       u = e >> 1;
       comp = e & 1;
@@ -340,17 +361,24 @@ __global__ void __launch_bounds__(TPB) k_scale_round(Tables T, const uint64_t* _
     src = d + poly * P * N;
     dst = comp < 2 ? c01 + (job * 2 + comp) * L * N : c2 + job * L * N;
   }
+  // per-limb row bases, formed once (uniform)
+  const uint64_t* srck = src + k;
+  const uint64_t *xqk = nullptr, *xbk = nullptr, *scb = nullptr, *al = nullptr;
+  if (FIRST && lin) {
+    xqk = xq + (pair * 2 + comp) * L * N + k;
+    xbk = xb + (pair * 2 + comp) * K * N + k;
+    scb = pconst + (pair * J0 + u) * P * 2;     // per limb: s = delta_a + delta_b, its companion
+    al = alpha + (pair * h + 2 * u) * P;         // delta_a; delta_b follows P words later
+  }
   uint64_t y[P];
 #pragma unroll
   for (int p = 0; p < P; ++p) {
-    uint64_t v = src[(size_t)p * N + k];
+    uint64_t v = srck[(size_t)p * N];
     if (FIRST && lin) {
       const Prime& pr = C.prm[p];
-      const uint64_t da = alpha[(pair * h + 2 * u) * P + p], db = alpha[(pair * h + 2 * u + 1) * P + p];
-      const uint64_t xv = p < L ? xq[((pair * 2 + comp) * L + p) * N + k]
-                                : xb[((pair * 2 + comp) * K + p - L) * N + k];
-      v = addmod(v, mulmod(addmod(da, db, pr.p), xv, pr), pr.p);
-      if (comp == 0 && k == 0) v = addmod(v, mulmod(da, db, pr), pr.p);
+      const uint64_t xv = p < L ? xqk[(size_t)p * N] : xbk[(size_t)(p - L) * N];
+      v = addmod(v, shoup(xv, scb[2 * p], scb[2 * p + 1], pr.p), pr.p);
+      if (comp == 0 && k == 0) v = addmod(v, mulmod(al[p], al[P + p], pr), pr.p);
     }
     y[p] = shoup(v, C.phat_inv[p], C.phat_inv_shoup[p], C.prm[p].p);
   }
@@ -382,7 +410,7 @@ __global__ void __launch_bounds__(TPB) k_scale_round(Tables T, const uint64_t* _
     acc.add(R);
 #pragma unroll
     for (int i = 0; i < L; ++i) acc.mac(yq[i], C.omega_mod_b[i][j]);
-    const uint64_t zj = acc.reduce(pr);
+    const uint64_t zj = acc.reduce_lazy(pr);
     yb[j] = shoup(zj, C.bhat_inv[j], C.bhat_inv_shoup[j], pr.p);
   }
   uint64_t v = round_fp<K>(yb, C.inv_b_d, &amb);
@@ -1017,10 +1045,12 @@ void ext_q_to_b(const Tables& T, const Consts& hc, const uint64_t* in, uint64_t*
   PEPSI_L_LAUNCH(k_ext_q_to_b, hc.L, grid_for(hc.n, rows), dim3(TPB), s, T, in, out, ostride, fb);
 }
 void factor_constants(const Tables& T, const Consts& hc, const uint64_t* scoef, int nb, int h,
-                      uint64_t* alpha, uint32_t* fb, hipStream_t s) {
+                      uint64_t* alpha, uint64_t* pconst, uint32_t* fb, hipStream_t s) {
   const int n = nb * h;
   if (n <= 0) return;
   PEPSI_L_LAUNCH(k_factor_constants, hc.L, dim3((n + 63) / 64), dim3(64), s, T, scoef, nb, h, alpha, fb);
+  const int np = nb * (h / 2) * (hc.L + hc.K);
+  if (np > 0) hipLaunchKernelGGL(k_pair_constants, dim3((np + TPB - 1) / TPB), dim3(TPB), 0, s, T, alpha, nb, h, pconst);
 }
 void tensor(const Tables& T, const Consts& hc, const TensorJob* jobs, int njobs, hipStream_t s) {
   if (njobs <= 0) return;
@@ -1036,19 +1066,21 @@ void scale_round(const Tables& T, const Consts& hc, const uint64_t* d, uint64_t*
   if (jobs <= 0) return;
   switch (hc.L) {
 #define PEPSI_SR(LL) case LL: hipLaunchKernelGGL((k_scale_round<LL, false>), grid_for(hc.n, jobs * 3), dim3(TPB), \
-                                                 0, s, T, d, nullptr, nullptr, nullptr, 0, 0, c01, c2, fb); break;
+                                                 0, s, T, d, nullptr, nullptr, nullptr, nullptr, 0, 0, c01, c2, fb); \
+    break;
     PEPSI_SR(1) PEPSI_SR(2) PEPSI_SR(3) PEPSI_SR(4) PEPSI_SR(5) PEPSI_SR(6) PEPSI_SR(7) PEPSI_SR(8)
 #undef PEPSI_SR
   }
 }
 void scale_round_first(const Tables& T, const Consts& hc, const uint64_t* d, const uint64_t* xq,
-                       const uint64_t* xb, const uint64_t* alpha, int h, int pairs, uint64_t* c01, uint64_t* c2,
-                       uint32_t* fb, hipStream_t s) {
+                       const uint64_t* xb, const uint64_t* alpha, const uint64_t* pconst, int h, int pairs,
+                       uint64_t* c01, uint64_t* c2, uint32_t* fb, hipStream_t s) {
   if (pairs <= 0 || h < 2) return;
   const int J0 = h / 2;
   switch (hc.L) {
 #define PEPSI_SR(LL) case LL: hipLaunchKernelGGL((k_scale_round<LL, true>), grid_for(hc.n, pairs * (2 * J0 + 1)), \
-                                                 dim3(TPB), 0, s, T, d, xq, xb, alpha, h, J0, c01, c2, fb); break;
+                                                 dim3(TPB), 0, s, T, d, xq, xb, alpha, pconst, h, J0, c01, c2, fb); \
+    break;
     PEPSI_SR(1) PEPSI_SR(2) PEPSI_SR(3) PEPSI_SR(4) PEPSI_SR(5) PEPSI_SR(6) PEPSI_SR(7) PEPSI_SR(8)
 #undef PEPSI_SR
   }

@@ -6,7 +6,7 @@ random and extreme inputs, for primes of the kind the library uses (p = 1 mod 2^
 - shoup_lazy4, the NTT butterfly product with a quotient from three partial products: congruent to
   x w mod p and below 4p for every 64-bit x;
 - shoup_lazy: congruent and below 2p; shoup: fully reduced;
-- reduce116: exact for every value below 2^116.
+- reduce116: exact for every value below 2^116; reduce116_lazy: congruent and below 3p.
 """
 import os
 import shutil
@@ -68,6 +68,8 @@ int main() {
       if (r1 != want) ++bad;
       const u128 v = ((u128)(g() >> 12) << 64 | g()) >> (g() % 40);   // below 2^116
       if (reduce116((uint64_t)v, (uint64_t)(v >> 64), P) != (uint64_t)(v % p)) ++bad;
+      const uint64_t rl = reduce116_lazy((uint64_t)v, (uint64_t)(v >> 64), P);
+      if (rl >= 3 * p || rl % p != (uint64_t)(v % p)) ++bad;
     }
   }
   printf("checked %ld bad %ld\n", n, bad);

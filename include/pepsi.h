@@ -210,6 +210,17 @@ int pepsi_server_create(const pepsi_params* params, const uint32_t* items, uint6
 int pepsi_server_create_with_values(const pepsi_params* params, const uint32_t* items,
                                     const uint32_t* values, uint64_t n, uint32_t flags, void* stream,
                                     pepsi_server** out);
+/* Server preparation with a bound on the plaintext cache: as
+ * pepsi_server_create_with_values (values may be NULL), where with
+ * PEPSI_SERVER_CACHE_PLAINTEXTS at most max_cached server batches are cached (0: as many as
+ * fit).  The count is then rounded down to whole 16-batch tiles unless it covers every batch
+ * that holds items, and evaluations regenerate the batches past it, so results are the same
+ * for every bound; the bound trades HBM held by the handle against evaluation time (the
+ * server's preprocessing, reused over many queries, Sec. 4.1).  pepsi_server_info.cached_batches reports the count kept.  Errors:
+ * as pepsi_server_create_with_values. */
+int pepsi_server_create_ex(const pepsi_params* params, const uint32_t* items, const uint32_t* values,
+                           uint64_t n, uint32_t flags, uint32_t max_cached, void* stream,
+                           pepsi_server** out);
 int pepsi_server_get_info(const pepsi_server* server, pepsi_server_info* out);
 /* Copy of the codeword-position table uint16 [mu][N][h] to host memory. */
 int pepsi_server_codewords(const pepsi_server* server, uint16_t* out);

@@ -81,6 +81,8 @@ _SIGS = {
                                       C.POINTER(C.c_void_p)]),
     "pepsi_server_create_with_values": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_uint32,
                                                   C.c_void_p, C.POINTER(C.c_void_p)]),
+    "pepsi_server_create_ex": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_uint32,
+                                         C.c_uint32, C.c_void_p, C.POINTER(C.c_void_p)]),
     "pepsi_server_get_info": (C.c_int, [C.c_void_p, C.POINTER(ServerInfo)]),
     "pepsi_server_codewords": (C.c_int, [C.c_void_p, C.c_void_p]),
     "pepsi_server_destroy": (None, [C.c_void_p]),
@@ -270,21 +272,23 @@ class Server:
     """The server's prepared set on the device (pepsi_server_*)."""
 
     def __init__(self, params: Params, items: np.ndarray, cache_plaintexts: bool = False, stream=None,
-                 values: np.ndarray | None = None):
+                 values: np.ndarray | None = None, max_cached: int = 0):
         """values (one per item, < t) make every evaluation PSI-Sum (with a mask) or labelled
-        PSI (without); None is PSI-cardinality / the indicator."""
+        PSI (without); None is PSI-cardinality / the indicator.  max_cached bounds the cached
+        batches (0: as many as fit)."""
         items = np.ascontiguousarray(items, dtype=np.uint32)
         h_ = C.c_void_p()
         flags = PEPSI_SERVER_CACHE_PLAINTEXTS if cache_plaintexts else 0
-        if values is None:
-            _check(lib().pepsi_server_create(params.handle, _host(items), items.shape[0], flags,
-                                             _stream(stream), C.byref(h_)))
-        else:
+        vp = None
+        if values is not None:
             values = np.ascontiguousarray(values, dtype=np.uint32)
             if values.shape != items.shape:
                 raise ValueError("one value per item")
-            _check(lib().pepsi_server_create_with_values(params.handle, _host(items), _host(values),
-                                                         items.shape[0], flags, _stream(stream), C.byref(h_)))
+            vp = _host(values)
+        if not 0 <= max_cached < 2**32:
+            raise ValueError("max_cached out of range")
+        _check(lib().pepsi_server_create_ex(params.handle, _host(items), vp, items.shape[0], flags, max_cached,
+                                            _stream(stream), C.byref(h_)))
         self._h = h_
         self.params = params
         info = ServerInfo()

@@ -805,6 +805,12 @@ extern "C" int pepsi_server_create(const pepsi_params* Pc, const uint32_t* items
 extern "C" int pepsi_server_create_with_values(const pepsi_params* Pc, const uint32_t* items,
                                                const uint32_t* values, uint64_t n, uint32_t flags, void* stream,
                                                pepsi_server** out) {
+  return pepsi_server_create_ex(Pc, items, values, n, flags, 0, stream, out);
+}
+
+extern "C" int pepsi_server_create_ex(const pepsi_params* Pc, const uint32_t* items, const uint32_t* values,
+                                      uint64_t n, uint32_t flags, uint32_t max_cached, void* stream,
+                                      pepsi_server** out) {
   pepsi_params* P = const_cast<pepsi_params*>(Pc);
   if (!P || (!items && n) || !out) return fail(PEPSI_E_ARG, "null argument");
   *out = nullptr;
@@ -867,7 +873,8 @@ extern "C" int pepsi_server_create_with_values(const pepsi_params* Pc, const uin
     const size_t reserve = (size_t)48 << 30;
     size_t fit = free_b > reserve ? (free_b - reserve) / (per * 8) : 0;
     uint32_t nc = (uint32_t)std::min<size_t>(fit, max_load);
-    if (nc < max_load) nc -= nc % 16;
+    if (max_cached > 0) nc = std::min(nc, max_cached);
+    if (nc < max_load) nc -= nc % PT_GROUP;
     if (nc > 0) {
       const int gs = Engine::cache_group(nc);
       const size_t alloc_b = (nc + gs - 1) / gs * gs;

@@ -103,7 +103,7 @@ def server_bin_bound(n_items: int, n_bins: int, n_hash: int = 3, log2_fail: int 
     log-space floating point, which is ample to place the crossing."""
     trials = n_hash * n_items
     mean = trials / n_bins
-    hi = int(mean + 60 * math.sqrt(mean + 1) + 60)
+    hi = min(trials, int(mean + 60 * math.sqrt(mean + 1) + 60))   # the pmf vanishes above `trials`
 
     def log_pmf(j: int) -> float:
         return (math.lgamma(trials + 1) - math.lgamma(j + 1) - math.lgamma(trials - j + 1)

@@ -90,3 +90,17 @@ def test_server_bin_bound_and_paper_rows(golden):
         assert P.server_mu(n, b) == mu
         # the paper's loads sit above the mean load 3n/b and at or below the 2^-40 union bound
         assert 3 * n / b < mu <= P.server_bin_bound(n, b)
+
+
+@pytest.mark.parametrize("n_items,n_bins", [(0, 1024), (1, 1024), (2, 64), (5, 16), (9, 8)])
+def test_server_bin_bound_small_sets_exact(n_items, n_bins):
+    """Tiny sets, where the load can reach every trial: the bound equals the least mu whose
+    exact binomial tail (rational arithmetic over all 3 n outcomes) passes the 2^-40 test."""
+    from fractions import Fraction
+    trials, p = 3 * n_items, Fraction(1, n_bins)
+    pmf = [math.comb(trials, j) * p ** j * (1 - p) ** (trials - j) for j in range(trials + 1)]
+    mu = 0
+    while n_bins * sum(pmf[mu:]) > Fraction(1, 2 ** 40):
+        mu += 1
+    assert P.server_bin_bound(n_items, n_bins) == mu
+    assert mu >= (1 if n_items == 0 else 2)

@@ -181,6 +181,7 @@ typedef struct {
   uint32_t cached;         /* 1 if a plaintext cache is resident                       */
   uint32_t cached_batches; /* server batches whose plaintexts are cached (the first ones) */
   uint64_t device_bytes;   /* device memory held by the handle                         */
+  uint32_t plane_groups;   /* cached 16-batch groups also held as int8 digit planes     */
 } pepsi_server_info;
 
 /* Server preparation: each of the n distinct items (< 2^item_bits) is appended to
@@ -192,6 +193,11 @@ typedef struct {
  * (ell * L * N * 8 bytes of HBM per server batch), for the first batches that fit
  * beside a 48 GiB working reserve (whole 16-batch tiles unless all fit; batches
  * holding only dummies are never stored); every evaluation regenerates the rest.
+ * When the cache is kept in 16-batch groups and a second copy fits beside the same
+ * reserve, the cached groups are also stored as int8 digit planes (seven balanced
+ * base-256 digits per residue, about 7/8 of the cache's bytes), which the batched and
+ * served evaluations contract on the matrix cores; pepsi_server_info.plane_groups
+ * gives their number.  Results are identical either way.
  * Synchronises the stream.  Errors: PEPSI_E_RANGE, PEPSI_E_BIN_OVERFLOW,
  * PEPSI_E_NOMEM. */
 int pepsi_server_create(const pepsi_params* params, const uint32_t* items, uint64_t n,
@@ -216,8 +222,8 @@ int pepsi_server_create_with_values(const pepsi_params* params, const uint32_t* 
  * fit).  The count is then rounded down to whole 16-batch tiles unless it covers every batch
  * that holds items, and evaluations regenerate the batches past it, so results are the same
  * for every bound; the bound trades HBM held by the handle against evaluation time (the
- * server's preprocessing, reused over many queries, Sec. 4.1).  pepsi_server_info.cached_batches reports the count kept.  Errors:
- * as pepsi_server_create_with_values. */
+ * server's preprocessing, reused over many queries, Sec. 4.1).  pepsi_server_info.cached_batches
+ * reports the count kept.  Errors: as pepsi_server_create_with_values. */
 int pepsi_server_create_ex(const pepsi_params* params, const uint32_t* items, const uint32_t* values,
                            uint64_t n, uint32_t flags, uint32_t max_cached, void* stream,
                            pepsi_server** out);

@@ -47,7 +47,8 @@ class ParamsInfo(C.Structure):
 
 class ServerInfo(C.Structure):
     _fields_ = [("mu", C.c_uint32), ("max_load", C.c_uint32), ("cached", C.c_uint32),
-                ("cached_batches", C.c_uint32), ("device_bytes", C.c_uint64)]
+                ("cached_batches", C.c_uint32), ("device_bytes", C.c_uint64),
+                ("plane_groups", C.c_uint32)]
 
 
 class ReqStats(C.Structure):
@@ -295,6 +296,7 @@ class Server:
         _check(lib().pepsi_server_get_info(self._h, C.byref(info)))
         self.max_load, self.cached, self.device_bytes = info.max_load, bool(info.cached), info.device_bytes
         self.cached_batches = info.cached_batches
+        self.plane_groups = info.plane_groups
 
     def close(self):
         if getattr(self, "_h", None):

@@ -434,13 +434,15 @@ struct Engine {
   std::vector<DevBuf> rq, rb;          // per tree level outputs
   DevBuf jobs;                         // device TensorJob arrays, all levels
   DevBuf gen_poly, gen_p;              // on-the-fly plaintext generation
+  DevBuf cplanes;                      // per query: request digit planes (matrix-core select-and-sum)
+  bool planes_on = false;
   int GB = 0;
   EventTimer* timer = nullptr;
   const uint64_t* vhat = nullptr;      // server-value plaintexts [max_load][L][N] (NTT form) or null
 
   ~Engine() {
     for (DevBuf* b : {&chat, &rlkhat, &acc, &accD, &sq, &scoef, &sb, &sbh, &alpha, &pconst, &e, &d, &c01, &c01h, &c2, &D,
-                      &rcoef, &jobs, &gen_poly, &gen_p})
+                      &rcoef, &jobs, &gen_poly, &gen_p, &cplanes})
       b->release();
     for (auto& b : rq) b.release();
     for (auto& b : rb) b.release();
@@ -453,6 +455,7 @@ struct Engine {
 
   int setup(pepsi_params* params, int tbq, int qmax, bool need_gen, const uint64_t* values_hat = nullptr) {
     vhat = values_hat;
+    planes_on = false;
     P = params;
     const HostParams& H = P->H;
     const size_t n = H.n, L = H.L, K = H.K, Pn = L + K;
@@ -590,19 +593,42 @@ struct Engine {
     scale_round(P->T, H.consts, dd, c01.as<uint64_t>(), c2.as<uint64_t>(), njobs, P->fallback.as<uint32_t>(), s);
   }
 
-  // A query enters slot `slot`: request and key to NTT form, running sum to zero.
+  size_t cpstride() const { return request_plane_bytes(P->H.consts, P->H.ell); }
+  // Request digit planes for every query slot, so that tiles whose plaintext planes are resident
+  // take the matrix-core select-and-sum; left off (no error) when they would not fit beside an
+  // 8 GiB working reserve.
+  int enable_planes() {
+    planes_on = false;
+    if (P->H.ell > PL_MAX_ELL || Qmax < 2) return 0;
+    const size_t need = (size_t)Qmax * cpstride();
+    if (need > cplanes.cap) {
+      size_t free_b = 0, total_b = 0;
+      if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return fail(PEPSI_E_DEVICE, "hipMemGetInfo failed");
+      if (free_b < need + ((size_t)8 << 30)) return 0;
+      int rc = cplanes.ensure(need);
+      if (rc) return rc;
+    }
+    planes_on = true;
+    return 0;
+  }
+
+  // A query enters slot `slot`: request and key to NTT form (and digit planes), running sum to zero.
   void admit(int slot, const uint64_t* cts, const uint64_t* rlk, hipStream_t s) {
     const HostParams& H = P->H;
     const int L = H.L;
     ntt_forward(P->T, H.logn, cts, LOAD_U64, chat.as<uint64_t>(slot * cstride()), STORE_U64, H.ell * 2 * L, L,
                 0, s);
+    if (planes_on)
+      request_planes(P->T, H.consts, chat.as<uint64_t>(slot * cstride()), H.ell,
+                     cplanes.as<int8_t>((size_t)slot * cpstride()), s);
     ntt_forward(P->T, H.logn, rlk, LOAD_U64, rlkhat.as<uint64_t>(slot * rstride()), STORE_U64, L * 2 * L, L, 0, s);
     (void)hipMemsetAsync(acc.as<uint64_t>(slot * ctw()), 0, ctw() * 8, s);
     if (levels > 0) (void)hipMemsetAsync(accD.as<uint64_t>(slot * dtw()), 0, dtw() * 8, s);
   }
 
   // A run of batches in a plaintext store: batches bfirst .. of a store of groups of gs batches.
-  struct PtView { const uint64_t* p = nullptr; int gs = 0, bfirst = 0; };
+  // planes: the digit planes of the tile's 16-batch group, when resident.
+  struct PtView { const uint64_t* p = nullptr; int gs = 0, bfirst = 0; const int8_t* planes = nullptr; };
   // Group size of the resident cache of `cached` batches (space is allocated for whole groups).
   static int cache_group(uint32_t cached) { return cached < (uint32_t)PT_GROUP ? (int)cached : PT_GROUP; }
 
@@ -615,6 +641,9 @@ struct Engine {
     if (nq == 1)
       select_sum(P->T, H.consts, chat.as<uint64_t>((size_t)single_slot * cstride()), pv.p, pv.gs, pv.bfirst,
                  H.ell, nb, Sx, (long)(2 * L * n), s);
+    else if (pv.planes && planes_on)
+      select_sum_planes(P->T, H.consts, pv.planes, cplanes.as<int8_t>(), (long)cpstride(), qslot, nq, nb, H.ell, Sx,
+                        s);
     else
       select_sum_multi(P->T, H.consts, chat.as<uint64_t>(), (long)cstride(), qslot, nq, pv.p, pv.gs, pv.bfirst,
                        H.ell, nb, Sx, s);
@@ -753,12 +782,17 @@ struct Engine {
   }
 
   // Plaintexts of tile [b0, b0 + nb): the cache when it covers the tile, else generated.
-  static PtView cached_tile(const uint64_t* cache, uint32_t cached, uint32_t b0, int nb) {
+  // With digit planes of the cache's groups (planes, group_bytes each), a tile that is one whole
+  // or final 16-batch group also gets its group's planes.
+  static PtView cached_tile(const uint64_t* cache, uint32_t cached, uint32_t b0, int nb,
+                            const int8_t* planes = nullptr, size_t group_bytes = 0) {
     PtView v;
     if (cache && b0 + (uint32_t)nb <= cached) {
       v.p = cache;
       v.gs = cache_group(cached);
       v.bfirst = (int)b0;
+      if (planes && v.gs == PT_GROUP && b0 % PT_GROUP == 0 && nb <= PT_GROUP)
+        v.planes = planes + (size_t)(b0 / PT_GROUP) * group_bytes;
     }
     return v;
   }
@@ -767,11 +801,12 @@ struct Engine {
   // the HBM-bound select-and-sum of the next tile on a second stream beside the product tree
   // was measured slower: the select-and-sum needs nearly full occupancy to cover HBM latency.)
   int run(const uint16_t* cw, const uint64_t* cache, uint32_t cached, uint32_t begin, uint32_t stop, int nq,
-          const uint64_t* const* cts, const uint64_t* const* rlk, hipStream_t s) {
+          const uint64_t* const* cts, const uint64_t* const* rlk, hipStream_t s, const int8_t* planes = nullptr,
+          size_t group_bytes = 0) {
     for (int q = 0; q < nq; ++q) admit(q, cts[q], rlk[q], s);
     for (uint32_t b0 = begin; b0 < stop; b0 += TBq) {
       const int nb = (int)std::min<uint32_t>(TBq, stop - b0);
-      run_tile(cw, (int)b0, nb, nq, nullptr, 0, cached_tile(cache, cached, b0, nb), s);
+      run_tile(cw, (int)b0, nb, nq, nullptr, 0, cached_tile(cache, cached, b0, nb, planes, group_bytes), s);
     }
     return 0;
   }
@@ -788,6 +823,9 @@ struct pepsi_server {
   DevBuf cache;         // plaintext store of the cached batches (layout at PtLayout)
   bool cached = false;
   uint32_t cached_batches = 0;
+  DevBuf planes;        // digit planes of the cached 16-batch groups (matrix-core select-and-sum)
+  uint32_t plane_groups = 0;
+  size_t plane_group_bytes = 0;
   Engine eng;            // one query at a time (plain path)
   bool ready = false;
   Engine beng;           // many queries per launch (batched path)
@@ -896,6 +934,21 @@ extern "C" int pepsi_server_create_ex(const pepsi_params* Pc, const uint32_t* it
       poly.release();
       sv->cached = true;
       sv->cached_batches = nc;
+      // digit planes of the cached groups for the batched path, when they fit beside the reserve
+      const uint32_t groups = (nc + PT_GROUP - 1) / PT_GROUP;
+      const size_t gb = plaintext_plane_group_bytes(H.consts, H.ell);
+      if (gs == PT_GROUP && H.ell <= PL_MAX_ELL) {
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) { delete sv; return fail(PEPSI_E_DEVICE, "hipMemGetInfo failed"); }
+        if (free_b > reserve && (free_b - reserve) / gb >= groups) {
+          if ((rc = sv->planes.ensure(gb * groups))) { delete sv; return rc; }
+          for (uint32_t G = 0; G < groups; ++G)
+            plaintext_planes(P->T, H.consts, sv->cache.as<uint64_t>(), gs, (int)G, H.ell,
+                             sv->planes.as<int8_t>((size_t)G * gb), s);
+          if (hipStreamSynchronize(s) != hipSuccess) { delete sv; return fail(PEPSI_E_DEVICE, "plane build failed"); }
+          sv->plane_groups = groups;
+          sv->plane_group_bytes = gb;
+        }
+      }
     }
   }
   *out = sv;
@@ -909,7 +962,8 @@ extern "C" int pepsi_server_get_info(const pepsi_server* sv, pepsi_server_info* 
   o->max_load = sv->max_load;
   o->cached = sv->cached ? 1 : 0;
   o->cached_batches = sv->cached_batches;
-  o->device_bytes = sv->cw.cap + sv->cache.cap + sv->vhat.cap;
+  o->device_bytes = sv->cw.cap + sv->cache.cap + sv->vhat.cap + sv->planes.cap;
+  o->plane_groups = sv->plane_groups;
   return PEPSI_OK;
 }
 
@@ -926,6 +980,7 @@ extern "C" void pepsi_server_destroy(pepsi_server* sv) {
   sv->cw.release();
   sv->cache.release();
   sv->vhat.release();
+  sv->planes.release();
   delete sv;
 }
 
@@ -985,14 +1040,15 @@ extern "C" int pepsi_server_eval_batch(pepsi_server* sv, uint32_t nq, const uint
     if (rc) return rc;
     sv->beng.timer = &sv->timer;
     sv->bqmax = (int)nq;
+    if (sv->plane_groups > 0 && (rc = sv->beng.enable_planes())) return rc;
   }
   Engine& E = sv->beng;
   hipEvent_t ea = nullptr, eb = nullptr;
   if (sv->timer.on) { ea = sv->timer.get(); eb = sv->timer.get(); (void)hipEventRecord(ea, s); }
   const uint32_t stop = std::min<uint32_t>(H.mu, sv->max_load);
   int rc = E.run(sv->cw.as<uint16_t>(), sv->cached ? sv->cache.as<uint64_t>() : nullptr, sv->cached_batches, 0,
-                 stop, (int)nq,
-                 cts, rlk, s);
+                 stop, (int)nq, cts, rlk, s, sv->plane_groups ? sv->planes.as<int8_t>() : nullptr,
+                 sv->plane_group_bytes);
   if (rc) return rc;
   for (uint32_t q = 0; q < nq; ++q) E.finish((int)q, true, masks ? masks[q] : nullptr, out[q], s);
   if (ea) {
@@ -1104,7 +1160,8 @@ struct pepsi_serve {
         const int nb = (int)std::min<uint32_t>(eng.TBq, stop_b - b0);
         eng.run_tile(sv->cw.as<uint16_t>(), (int)b0, nb, na, qslot_dev.as<int>(), live[0],
                      Engine::cached_tile(sv->cached ? sv->cache.as<uint64_t>() : nullptr, sv->cached_batches, b0,
-                                         nb),
+                                         nb, sv->plane_groups ? sv->planes.as<int8_t>() : nullptr,
+                                         sv->plane_group_bytes),
                      stream);
         cursor = (cursor + 1) % T;
         ++steps;
@@ -1144,7 +1201,9 @@ extern "C" int pepsi_serve_create(pepsi_server* sv, uint32_t max_active, uint64_
   const size_t n = H.n, L = H.L, K = H.K, Pn = L + K;
   const size_t jobs0 = (size_t)(H.h / 2 > 0 ? H.h / 2 : 1);
   const size_t per_pair = 8 * n * (2 * L * 3 + 4 * K + jobs0 * (3 * Pn + 5 * L + L * L + 2 * L + 2 * L + 2 * K));
-  const size_t per_slot = 8 * ((size_t)H.ell * 2 * L * n + L * 2 * L * n + 2 * L * n) + tbq * per_pair;
+  // (and the request's digit planes when the server holds plaintext planes)
+  const size_t per_slot = 8 * ((size_t)H.ell * 2 * L * n + L * 2 * L * n + 2 * L * n) + tbq * per_pair +
+                          (sv->plane_groups ? request_plane_bytes(H.consts, H.ell) : 0);
   uint32_t slots = max_active ? max_active : PEPSI_MAX_BATCH;
   if (hbm_budget) slots = (uint32_t)std::min<uint64_t>(slots, hbm_budget / per_slot);
   slots = std::min<uint32_t>(slots, PEPSI_MAX_BATCH);
@@ -1155,6 +1214,7 @@ extern "C" int pepsi_serve_create(pepsi_server* sv, uint32_t max_active, uint64_
   sr->stop_b = std::min<uint32_t>(H.mu, sv->max_load);
   sr->T = (int)((sr->stop_b + tbq - 1) / tbq);
   int rc = sr->eng.setup(sv->P, tbq, (int)slots, sv->cached_batches < sv->max_load, sv->values_hat());
+  if (!rc && sv->plane_groups) rc = sr->eng.enable_planes();
   if (!rc) rc = sr->qslot_dev.ensure(sizeof(int) * slots);
   if (!rc && hipHostMalloc((void**)&sr->qslot_host, sizeof(int) * slots, hipHostMallocDefault) != hipSuccess)
     rc = fail(PEPSI_E_NOMEM, "pinned slot buffer");

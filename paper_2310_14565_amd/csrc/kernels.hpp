@@ -120,6 +120,23 @@ void select_sum_multi(const Tables& T, const Consts& hc, const uint64_t* Cq, lon
                       int nq, const uint64_t* P, int gs, int bfirst, int ell, int nb, uint64_t* S,
                       hipStream_t s);
 
+// The same on the int8 matrix cores, from digit planes (seven balanced base-256 digits per
+// residue, code positions innermost in blocks of PL_K).  Plaintext planes of a 16-batch group:
+// [L][N][kblocks][PL_DG][16][PL_K] int8; request planes of a query: [L][N][kblocks][PL_DG][2][PL_K]
+// int8, query q's at Cp + qslot[q] * cps.  Valid for ell <= PL_MAX_ELL (exact int32 and 64-bit
+// sums); rows b >= nb of the group are read but not written.
+constexpr int PL_DG = 7, PL_K = 64, PL_MAX_ELL = 4096;
+inline int plane_kblocks(int ell) { return (ell + PL_K - 1) / PL_K; }
+size_t plaintext_plane_group_bytes(const Consts& hc, int ell);
+size_t request_plane_bytes(const Consts& hc, int ell);
+// group G (batches 16 G .. 16 G + 15) of a plaintext store with group size gs = 16
+void plaintext_planes(const Tables& T, const Consts& hc, const uint64_t* P, int gs, int G, int ell, int8_t* out,
+                      hipStream_t s);
+// one query's NTT-form request [ell][2][L][N]
+void request_planes(const Tables& T, const Consts& hc, const uint64_t* ch, int ell, int8_t* out, hipStream_t s);
+void select_sum_planes(const Tables& T, const Consts& hc, const int8_t* Pp, const int8_t* Cp, long cps,
+                       const int* qslot, int nq, int nb, int ell, uint64_t* S, hipStream_t s);
+
 // ---------------- elementwise helpers ----------------
 // out = a * b pointwise (both [rows][L][N] NTT form, b broadcast over rows if bcast)
 void pointwise_mul(const Tables& T, const Consts& hc, const uint64_t* a, const uint64_t* b,

@@ -768,6 +768,151 @@ __global__ void __launch_bounds__(MTPB) k_select_sum_multi(Tables T, const uint6
               fold3(lo[a][c][b], ms[a][c][b], hi[a][c][b], pr);
 }
 
+// Select-and-sum of many queries on the int8 matrix cores.  For one slot position k and prime
+// q_l the batched select-and-sum is a matrix product: rows are the 16 batches of a tile, columns
+// the (query, part) pairs, and the contraction runs over the ell code positions.  Every residue
+// (< 2^54) is written as seven balanced base-256 digits x = sum_i d_i 256^i, d_i in [-128, 127],
+// stored as int8 planes with the code positions innermost in blocks of PL_K = 64.  The 49 digit
+// products of a block accumulate exactly in int32 (|T_s| <= 7 ell 2^14) into 13 sums T_s, one
+// per weight 256^s, and the exact value sum_s T_s 256^s is recovered in four 64-bit groups of
+// four weights (|V_g| < 2^53 <= q_l for ell <= PL_MAX_ELL), each brought into [0, 2 q_l) and
+// multiplied by 2^(32 g) mod q_l, with one reduction of the 128-bit total.
+typedef int v4i __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void balanced_digits(uint64_t x, int8_t (&d)[PL_DG]) {
+#pragma unroll
+  for (int i = 0; i < PL_DG - 1; ++i) {
+    int v = (int)(x & 255);
+    v -= v >= 128 ? 256 : 0;
+    d[i] = (int8_t)v;
+    x = (x - (uint64_t)(int64_t)v) >> 8;
+  }
+  d[PL_DG - 1] = (int8_t)x;     // below 65 for x < 2^54
+}
+// Plaintext planes of one group of 16 batches of a cache store (group size gs = 16), layout
+// [l][k][kb][digit][batch][64].  Wave = one (l, k, kb); lane = (batch, 16-position quarter).
+__global__ void __launch_bounds__(TPB) k_plaintext_planes(Tables T, const uint64_t* __restrict__ Pc, int gs,
+                                                         int G, int ell, int kbs, int8_t* __restrict__ out) {
+  const Consts& C = *T.c;
+  const int N = C.n, L = C.L;
+  const size_t w = (size_t)blockIdx.x * (TPB / 64) + (threadIdx.x >> 6);
+  if (w >= (size_t)L * N * kbs) return;
+  const int lane = threadIdx.x & 63, b = lane & 15, g4 = lane >> 4;
+  const int kb = (int)(w % kbs);
+  const size_t lk = w / kbs;
+  const int k = (int)(lk % N), l = (int)(lk / N);
+  const uint64_t p = C.prm[l].p;
+  constexpr uint64_t M27 = (1ull << 27) - 1;
+  const size_t jstep = (size_t)L * N * gs;
+  const uint64_t* src = Pc + (size_t)G * ell * jstep + (size_t)l * N * gs + (size_t)(k / PT_BLOCK) * gs * PT_BLOCK +
+                        (size_t)b * PT_BLOCK + k % PT_BLOCK;
+  int8_t o[PL_DG][16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int j = kb * PL_K + g4 * 16 + e;
+    uint64_t x = 0;
+    if (j < ell) {
+      const uint64_t wd = src[(size_t)j * jstep];
+      x = (wd & M27) + (((wd >> 32) & M27) << 27);
+      x -= x >= p ? p : 0;
+    }
+    int8_t d[PL_DG];
+    balanced_digits(x, d);
+#pragma unroll
+    for (int v = 0; v < PL_DG; ++v) o[v][e] = d[v];
+  }
+#pragma unroll
+  for (int v = 0; v < PL_DG; ++v)
+    __builtin_memcpy(out + ((w * PL_DG + v) * 16 + b) * PL_K + 16 * g4, o[v], 16);
+}
+// Request planes of one query, layout [l][k][kb][digit][part][64], from its NTT form
+// [ell][2][L][N].  Wave = one (l, 8 positions, kb); lane = (position, part, quarter).
+__global__ void __launch_bounds__(TPB) k_request_planes(Tables T, const uint64_t* __restrict__ ch, int ell, int kbs,
+                                                       int8_t* __restrict__ out) {
+  const Consts& C = *T.c;
+  const int N = C.n, L = C.L;
+  const size_t w = (size_t)blockIdx.x * (TPB / 64) + (threadIdx.x >> 6);
+  if (w >= (size_t)L * (N / 8) * kbs) return;
+  const int lane = threadIdx.x & 63;
+  const int kb = (int)(w % kbs);
+  const size_t r = w / kbs;
+  const int k = (int)(r % (N / 8)) * 8 + (lane & 7), l = (int)(r / (N / 8));
+  const int c = (lane >> 3) & 1, g4 = lane >> 4;
+  const uint64_t p = C.prm[l].p;
+  int8_t o[PL_DG][16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int j = kb * PL_K + g4 * 16 + e;
+    uint64_t x = 0;
+    if (j < ell) {
+      x = ch[(((size_t)j * 2 + c) * L + l) * N + k];
+      x -= x >= p ? p : 0;
+    }
+    int8_t d[PL_DG];
+    balanced_digits(x, d);
+#pragma unroll
+    for (int u = 0; u < PL_DG; ++u) o[u][e] = d[u];
+  }
+#pragma unroll
+  for (int u = 0; u < PL_DG; ++u)
+    __builtin_memcpy(out + (((((size_t)l * N + k) * kbs + kb) * PL_DG + u) * 2 + c) * PL_K + 16 * g4, o[u], 16);
+}
+// The contraction.  Workgroup = 4 waves on one (l, k); wave = 8 queries (16 columns).  The
+// workgroups of one (l, k) are numbered consecutively on one XCD, so that they share its
+// plaintext planes through L2.  S entry of (batch b, query q) at (b * nq + q) * 2 L N, as in
+// k_select_sum_multi.
+__global__ void __launch_bounds__(TPB) k_select_sum_planes(Tables T, const int8_t* __restrict__ Pp,
+                                                          const int8_t* __restrict__ Cp, long cps,
+                                                          const int* __restrict__ qslot, int nq, int nb, int kbs,
+                                                          uint64_t* __restrict__ S, int oblocks) {
+  const Consts& C = *T.c;
+  const int N = C.n, L = C.L;
+  const int bid = blockIdx.x, local = bid >> 3;
+  const int ob = local % oblocks, lk = (local / oblocks) * 8 + (bid & 7);
+  const int l = lk / N, k = lk % N;
+  const int lane = threadIdx.x & 63, m = lane & 15, g4 = lane >> 4;
+  const int oct = ob * (TPB / 64) + (threadIdx.x >> 6);
+  if (oct * 8 >= nq) return;
+  const int q = oct * 8 + (m >> 1), c = m & 1;
+  const bool live = q < nq;
+  const int8_t* pa = Pp + ((size_t)lk * kbs * PL_DG * 16 + m) * PL_K + 16 * g4;
+  const int8_t* pb = Cp + (size_t)(live ? (qslot ? qslot[q] : q) : 0) * cps +
+                     ((size_t)lk * kbs * PL_DG * 2 + c) * PL_K + 16 * g4;
+  v4i acc[2 * PL_DG - 1];
+#pragma unroll
+  for (int s2 = 0; s2 < 2 * PL_DG - 1; ++s2) acc[s2] = v4i{0, 0, 0, 0};
+  for (int kb = 0; kb < kbs; ++kb) {
+    v4i a[PL_DG], bb[PL_DG];
+#pragma unroll
+    for (int v = 0; v < PL_DG; ++v) a[v] = *reinterpret_cast<const v4i*>(pa + ((size_t)kb * PL_DG + v) * 16 * PL_K);
+#pragma unroll
+    for (int u = 0; u < PL_DG; ++u)
+      bb[u] = live ? *reinterpret_cast<const v4i*>(pb + ((size_t)kb * PL_DG + u) * 2 * PL_K) : v4i{0, 0, 0, 0};
+#pragma unroll
+    for (int v = 0; v < PL_DG; ++v)
+#pragma unroll
+      for (int u = 0; u < PL_DG; ++u)
+        acc[u + v] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[v], bb[u], acc[u + v], 0, 0, 0);
+  }
+  if (!live) return;
+  const Prime& pr = C.prm[l];
+  const uint64_t p = pr.p;
+  const uint64_t wgt[4] = {1, 1ull << 32, pr.r64, mulmod(pr.r64, 1ull << 32, pr)};   // 2^(32 g) mod p
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int b = 4 * g4 + i;   // output row of this lane
+    if (b >= nb) continue;
+    u128 tot = 0;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      int64_t V = 0;
+#pragma unroll
+      for (int s2 = 4 * g; s2 < 4 * g + 4 && s2 < 2 * PL_DG - 1; ++s2) V += (int64_t)acc[s2][i] << (8 * (s2 - 4 * g));
+      tot += (u128)(uint64_t)(V + (int64_t)p) * wgt[g];
+    }
+    S[(((size_t)b * nq + q) * 2 + c) * L * N + (size_t)l * N + k] = reduce128((uint64_t)tot, (uint64_t)(tot >> 64), pr);
+  }
+}
+
 // Seeded uniform polynomials (request compression): a_{j,l}[k] = W mod q_l, W the 16 bytes
 // of the ChaCha20 keystream (RFC 8439; key = the seed, nonce = (j, l, 0)) at 16 k, little-
 // endian.  Thread = one 64-byte block = 4 coefficients.
@@ -1134,6 +1279,33 @@ void select_sum_multi(const Tables& T, const Consts& hc, const uint64_t* Cq, lon
   const int blocks = ((regions + 8 * MRQ - 1) / (8 * MRQ)) * 8 * MRQ * qgroups;
   hipLaunchKernelGGL(k_select_sum_multi, dim3(blocks), dim3(MTPB), 0, s, T, Cq, cq_stride, qslot, nq, P, gs,
                      bfirst, ell, nb, S, regions, qgroups);
+}
+size_t plaintext_plane_group_bytes(const Consts& hc, int ell) {
+  return (size_t)hc.L * hc.n * plane_kblocks(ell) * PL_DG * 16 * PL_K;
+}
+size_t request_plane_bytes(const Consts& hc, int ell) {
+  return (size_t)hc.L * hc.n * plane_kblocks(ell) * PL_DG * 2 * PL_K;
+}
+void plaintext_planes(const Tables& T, const Consts& hc, const uint64_t* P, int gs, int G, int ell, int8_t* out,
+                      hipStream_t s) {
+  const int kbs = plane_kblocks(ell);
+  const size_t waves = (size_t)hc.L * hc.n * kbs;
+  hipLaunchKernelGGL(k_plaintext_planes, dim3((unsigned)((waves + TPB / 64 - 1) / (TPB / 64))), dim3(TPB), 0, s, T, P,
+                     gs, G, ell, kbs, out);
+}
+void request_planes(const Tables& T, const Consts& hc, const uint64_t* ch, int ell, int8_t* out, hipStream_t s) {
+  const int kbs = plane_kblocks(ell);
+  const size_t waves = (size_t)hc.L * (hc.n / 8) * kbs;
+  hipLaunchKernelGGL(k_request_planes, dim3((unsigned)((waves + TPB / 64 - 1) / (TPB / 64))), dim3(TPB), 0, s, T, ch,
+                     ell, kbs, out);
+}
+void select_sum_planes(const Tables& T, const Consts& hc, const int8_t* Pp, const int8_t* Cp, long cps,
+                       const int* qslot, int nq, int nb, int ell, uint64_t* S, hipStream_t s) {
+  if (nb <= 0 || nq <= 0) return;
+  const int octets = (nq + 7) / 8, oblocks = (octets + TPB / 64 - 1) / (TPB / 64);
+  const int lks = hc.L * hc.n;   // a multiple of 8
+  hipLaunchKernelGGL(k_select_sum_planes, dim3(lks * oblocks), dim3(TPB), 0, s, T, Pp, Cp, cps, qslot, nq, nb,
+                     plane_kblocks(ell), S, oblocks);
 }
 void pointwise_mul(const Tables& T, const Consts& hc, const uint64_t* a, const uint64_t* b,
                    uint64_t* out, int rows, int nprimes, bool bcast, hipStream_t s) {

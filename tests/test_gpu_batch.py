@@ -50,7 +50,10 @@ def test_batch_equals_alone(h, nq, cache, n_server):
     server = W.server_items(n_server, bits, 70 + h)
     sv = pk.Server(gp, server, cache_plaintexts=cache)
     qs = make_queries(ctx, cfg, server, nq, 100 * h + nq)
-    say(f"batch h={h} nq={nq} cache={cache} ell={cfg.ell} max_load={sv.max_load}")
+    say(f"batch h={h} nq={nq} cache={cache} ell={cfg.ell} max_load={sv.max_load} planes={sv.plane_groups}")
+    if cache and sv.max_load >= 16:
+        # whole 16-batch groups cached: the tiles take the matrix-core select-and-sum
+        assert sv.plane_groups == -(-sv.cached_batches // 16) > 0
     d_cts = [to_dev(q["cts"]) for q in qs]
     d_rlk = [to_dev(q["rlk"]) for q in qs]
     d_mask = [None if q["mask"] is None else to_dev(q["mask"]) for q in qs]

@@ -35,7 +35,8 @@ def test_serving_mix_equals_alone(h, cache):
     server = W.server_items(n_server, bits, 90 + h)
     sv = pk.Server(gp, server, cache_plaintexts=cache)
     qs = make_queries(ctx, cfg, server, 11, 500 + h)
-    say(f"serve h={h} max_load={sv.max_load} queries={len(qs)}")
+    say(f"serve h={h} max_load={sv.max_load} queries={len(qs)} planes={sv.plane_groups}")
+    assert (sv.plane_groups > 0) == cache          # cached groups take the matrix-core path
     dev = [dict(cts=to_dev(q["cts"]), rlk=to_dev(q["rlk"]), mask=None if q["mask"] is None else to_dev(q["mask"]),
                 out=empty((2, L, n), np.uint64)) for q in qs]
     alone = []

@@ -782,8 +782,8 @@ struct Engine {
   }
 
   // Plaintexts of tile [b0, b0 + nb): the cache when it covers the tile, else generated.
-  // With digit planes of the cache's groups (planes, group_bytes each), a tile that is one whole
-  // or final 16-batch group also gets its group's planes.
+  // With digit planes of the cache's groups (planes, group_bytes each), a tile that starts a
+  // 16-batch group and spans at most two groups also gets their planes.
   static PtView cached_tile(const uint64_t* cache, uint32_t cached, uint32_t b0, int nb,
                             const int8_t* planes = nullptr, size_t group_bytes = 0) {
     PtView v;
@@ -791,7 +791,7 @@ struct Engine {
       v.p = cache;
       v.gs = cache_group(cached);
       v.bfirst = (int)b0;
-      if (planes && v.gs == PT_GROUP && b0 % PT_GROUP == 0 && nb <= PT_GROUP)
+      if (planes && v.gs == PT_GROUP && b0 % PT_GROUP == 0 && nb <= 2 * PT_GROUP)
         v.planes = planes + (size_t)(b0 / PT_GROUP) * group_bytes;
     }
     return v;
@@ -1034,8 +1034,10 @@ extern "C" int pepsi_server_eval_batch(pepsi_server* sv, uint32_t nq, const uint
   const HostParams& H = sv->P->H;
   hipStream_t s = S(stream);
   if ((int)nq > sv->bqmax) {
-    // batches per tile: one batch group of the multi-query select-and-sum (16)
-    int rc = sv->beng.setup(sv->P, std::min<int>(16, std::max<int>(1, (int)sv->max_load)), (int)nq,
+    // batches per tile: one batch group of the multi-query select-and-sum (16), or two with
+    // digit planes for up to 64 queries (the request planes are then read once per 32 batches)
+    const int tb = sv->plane_groups > 0 && nq <= 64 ? 32 : 16;
+    int rc = sv->beng.setup(sv->P, std::min<int>(tb, std::max<int>(1, (int)sv->max_load)), (int)nq,
                             sv->cached_batches < sv->max_load, sv->values_hat());
     if (rc) return rc;
     sv->beng.timer = &sv->timer;

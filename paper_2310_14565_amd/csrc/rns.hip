@@ -856,11 +856,13 @@ __global__ void __launch_bounds__(TPB) k_request_planes(Tables T, const uint64_t
   for (int u = 0; u < PL_DG; ++u)
     __builtin_memcpy(out + (((((size_t)l * N + k) * kbs + kb) * PL_DG + u) * 2 + c) * PL_K + 16 * g4, o[u], 16);
 }
-// The contraction.  Workgroup = 4 waves on one (l, k); wave = 8 queries (16 columns).  The
-// workgroups of one (l, k) are numbered consecutively on one XCD, so that they share its
-// plaintext planes through L2.  S entry of (batch b, query q) at (b * nq + q) * 2 L N, as in
-// k_select_sum_multi.
-__global__ void __launch_bounds__(TPB) k_select_sum_planes(Tables T, const int8_t* __restrict__ Pp,
+// The contraction over a tile of up to 32 batches (two consecutive 16-batch groups of planes,
+// gbytes apart).  Workgroup = 4 waves on one (l, k): two query octets (16 columns each) x the
+// two 16-batch halves, so that the two waves of an octet read its request planes once from L2
+// and share them in L1.  The workgroups of one (l, k) are numbered consecutively on one XCD and
+// share its plaintext planes through L2.  S entry of (batch b, query q) at (b * nq + q) * 2 L N,
+// as in k_select_sum_multi.
+__global__ void __launch_bounds__(TPB) k_select_sum_planes(Tables T, const int8_t* __restrict__ Pp, long gbytes,
                                                           const int8_t* __restrict__ Cp, long cps,
                                                           const int* __restrict__ qslot, int nq, int nb, int kbs,
                                                           uint64_t* __restrict__ S, int oblocks) {
@@ -870,11 +872,11 @@ __global__ void __launch_bounds__(TPB) k_select_sum_planes(Tables T, const int8_
   const int ob = local % oblocks, lk = (local / oblocks) * 8 + (bid & 7);
   const int l = lk / N, k = lk % N;
   const int lane = threadIdx.x & 63, m = lane & 15, g4 = lane >> 4;
-  const int oct = ob * (TPB / 64) + (threadIdx.x >> 6);
-  if (oct * 8 >= nq) return;
+  const int wv = threadIdx.x >> 6, half = wv & 1, oct = ob * 2 + (wv >> 1);
+  if (oct * 8 >= nq || 16 * half >= nb) return;
   const int q = oct * 8 + (m >> 1), c = m & 1;
   const bool live = q < nq;
-  const int8_t* pa = Pp + ((size_t)lk * kbs * PL_DG * 16 + m) * PL_K + 16 * g4;
+  const int8_t* pa = Pp + half * gbytes + ((size_t)lk * kbs * PL_DG * 16 + m) * PL_K + 16 * g4;
   const int8_t* pb = Cp + (size_t)(live ? (qslot ? qslot[q] : q) : 0) * cps +
                      ((size_t)lk * kbs * PL_DG * 2 + c) * PL_K + 16 * g4;
   v4i acc[2 * PL_DG - 1];
@@ -899,7 +901,7 @@ __global__ void __launch_bounds__(TPB) k_select_sum_planes(Tables T, const int8_
   const uint64_t wgt[4] = {1, 1ull << 32, pr.r64, mulmod(pr.r64, 1ull << 32, pr)};   // 2^(32 g) mod p
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int b = 4 * g4 + i;   // output row of this lane
+    const int b = 16 * half + 4 * g4 + i;   // output row of this lane
     if (b >= nb) continue;
     u128 tot = 0;
 #pragma unroll
@@ -1302,10 +1304,11 @@ void request_planes(const Tables& T, const Consts& hc, const uint64_t* ch, int e
 void select_sum_planes(const Tables& T, const Consts& hc, const int8_t* Pp, const int8_t* Cp, long cps,
                        const int* qslot, int nq, int nb, int ell, uint64_t* S, hipStream_t s) {
   if (nb <= 0 || nq <= 0) return;
-  const int octets = (nq + 7) / 8, oblocks = (octets + TPB / 64 - 1) / (TPB / 64);
+  const int octets = (nq + 7) / 8, oblocks = (octets + 1) / 2;
   const int lks = hc.L * hc.n;   // a multiple of 8
-  hipLaunchKernelGGL(k_select_sum_planes, dim3(lks * oblocks), dim3(TPB), 0, s, T, Pp, Cp, cps, qslot, nq, nb,
-                     plane_kblocks(ell), S, oblocks);
+  hipLaunchKernelGGL(k_select_sum_planes, dim3(lks * oblocks), dim3(TPB), 0, s, T, Pp,
+                     (long)plaintext_plane_group_bytes(hc, ell), Cp, cps, qslot, nq, nb, plane_kblocks(ell), S,
+                     oblocks);
 }
 void pointwise_mul(const Tables& T, const Consts& hc, const uint64_t* a, const uint64_t* b,
                    uint64_t* out, int rows, int nprimes, bool bcast, hipStream_t s) {

@@ -783,7 +783,7 @@ struct Engine {
 
   // Plaintexts of tile [b0, b0 + nb): the cache when it covers the tile, else generated.
   // With digit planes of the cache's groups (planes, group_bytes each), a tile that starts a
-  // 16-batch group and spans at most two groups also gets their planes.
+  // 16-batch group and spans at most four groups also gets their planes.
   static PtView cached_tile(const uint64_t* cache, uint32_t cached, uint32_t b0, int nb,
                             const int8_t* planes = nullptr, size_t group_bytes = 0) {
     PtView v;
@@ -791,7 +791,7 @@ struct Engine {
       v.p = cache;
       v.gs = cache_group(cached);
       v.bfirst = (int)b0;
-      if (planes && v.gs == PT_GROUP && b0 % PT_GROUP == 0 && nb <= 2 * PT_GROUP)
+      if (planes && v.gs == PT_GROUP && b0 % PT_GROUP == 0 && nb <= 4 * PT_GROUP)
         v.planes = planes + (size_t)(b0 / PT_GROUP) * group_bytes;
     }
     return v;
@@ -813,6 +813,18 @@ struct Engine {
 };
 
 }  // namespace
+
+// Engine device memory: per (batch, query) pair of tile buffers, and per query slot (request,
+// key and sums in NTT form).
+static size_t engine_pair_bytes(const HostParams& H) {
+  const size_t n = H.n, L = H.L, K = H.K, Pn = L + K;
+  const size_t jobs0 = (size_t)(H.h / 2 > 0 ? H.h / 2 : 1);
+  return 8 * n * (2 * L * 3 + 4 * K + jobs0 * (3 * Pn + 5 * L + L * L + 2 * L + 2 * L + 2 * K));
+}
+static size_t engine_slot_bytes(const HostParams& H) {
+  const size_t n = H.n, L = H.L;
+  return 8 * ((size_t)H.ell * 2 * L * n + L * 2 * L * n + 2 * L * n);
+}
 
 // ------------------------------------------------------------------ server
 struct pepsi_server {
@@ -1034,9 +1046,18 @@ extern "C" int pepsi_server_eval_batch(pepsi_server* sv, uint32_t nq, const uint
   const HostParams& H = sv->P->H;
   hipStream_t s = S(stream);
   if ((int)nq > sv->bqmax) {
-    // batches per tile: one batch group of the multi-query select-and-sum (16), or two with
-    // digit planes for up to 64 queries (the request planes are then read once per 32 batches)
-    const int tb = sv->plane_groups > 0 && nq <= 64 ? 32 : 16;
+    // batches per tile: one batch group of the multi-query select-and-sum (16); with digit
+    // planes and up to 64 queries, four or two groups (the request planes are then read once
+    // per 64 or 32 batches) when their tile buffers fit beside an 8 GiB reserve
+    int tb = 16;
+    if (sv->plane_groups > 0 && nq <= 64) {
+      size_t free_b = 0, total_b = 0;
+      if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return fail(PEPSI_E_DEVICE, "hipMemGetInfo failed");
+      const size_t fixed = (size_t)nq * (engine_slot_bytes(H) + request_plane_bytes(H.consts, H.ell)) +
+                           ((size_t)8 << 30);
+      for (int cand : {64, 32})
+        if (free_b > fixed + (size_t)cand * nq * engine_pair_bytes(H)) { tb = cand; break; }
+    }
     int rc = sv->beng.setup(sv->P, std::min<int>(tb, std::max<int>(1, (int)sv->max_load)), (int)nq,
                             sv->cached_batches < sv->max_load, sv->values_hat());
     if (rc) return rc;
@@ -1200,11 +1221,8 @@ extern "C" int pepsi_serve_create(pepsi_server* sv, uint32_t max_active, uint64_
   const HostParams& H = sv->P->H;
   const int tbq = std::min<int>(16, std::max<int>(1, (int)sv->max_load));
   // device memory per slot: request + key + sum in NTT form, and tbq pairs of tile buffers
-  const size_t n = H.n, L = H.L, K = H.K, Pn = L + K;
-  const size_t jobs0 = (size_t)(H.h / 2 > 0 ? H.h / 2 : 1);
-  const size_t per_pair = 8 * n * (2 * L * 3 + 4 * K + jobs0 * (3 * Pn + 5 * L + L * L + 2 * L + 2 * L + 2 * K));
   // (and the request's digit planes when the server holds plaintext planes)
-  const size_t per_slot = 8 * ((size_t)H.ell * 2 * L * n + L * 2 * L * n + 2 * L * n) + tbq * per_pair +
+  const size_t per_slot = engine_slot_bytes(H) + tbq * engine_pair_bytes(H) +
                           (sv->plane_groups ? request_plane_bytes(H.consts, H.ell) : 0);
   uint32_t slots = max_active ? max_active : PEPSI_MAX_BATCH;
   if (hbm_budget) slots = (uint32_t)std::min<uint64_t>(slots, hbm_budget / per_slot);

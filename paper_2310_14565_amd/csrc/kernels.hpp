@@ -123,8 +123,8 @@ void select_sum_multi(const Tables& T, const Consts& hc, const uint64_t* Cq, lon
 // The same on the int8 matrix cores, from digit planes (seven balanced base-256 digits per
 // residue, code positions innermost in blocks of PL_K).  Plaintext planes of a 16-batch group:
 // [L][N][kblocks][PL_DG][16][PL_K] int8; request planes of a query: [L][N][kblocks][PL_DG][2][PL_K]
-// int8, query q's at Cp + qslot[q] * cps.  A tile is nb <= 32 batches: the group at Pp and, for
-// nb > 16, the next one.  Valid for ell <= PL_MAX_ELL (exact int32 and 64-bit sums); rows
+// int8, query q's at Cp + qslot[q] * cps.  A tile is nb <= 64 batches: the group at Pp and the
+// ones after it.  Valid for ell <= PL_MAX_ELL (exact int32 and 64-bit sums); rows
 // b >= nb of a group are read but not written.
 constexpr int PL_DG = 7, PL_K = 64, PL_MAX_ELL = 4096;
 inline int plane_kblocks(int ell) { return (ell + PL_K - 1) / PL_K; }

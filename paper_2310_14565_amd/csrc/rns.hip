@@ -856,12 +856,13 @@ __global__ void __launch_bounds__(TPB) k_request_planes(Tables T, const uint64_t
   for (int u = 0; u < PL_DG; ++u)
     __builtin_memcpy(out + (((((size_t)l * N + k) * kbs + kb) * PL_DG + u) * 2 + c) * PL_K + 16 * g4, o[u], 16);
 }
-// The contraction over a tile of up to 32 batches (two consecutive 16-batch groups of planes,
-// gbytes apart).  Workgroup = 4 waves on one (l, k): two query octets (16 columns each) x the
-// two 16-batch halves, so that the two waves of an octet read its request planes once from L2
-// and share them in L1.  The workgroups of one (l, k) are numbered consecutively on one XCD and
+// The contraction over a tile of up to 16 HT batches (HT consecutive 16-batch groups of planes,
+// gbytes apart).  Workgroup = 4 waves on one (l, k): 4 / HT query octets (16 columns each) x
+// the HT groups, so that the HT waves of an octet read its request planes once from L2 and
+// share them in L1.  The workgroups of one (l, k) are numbered consecutively on one XCD and
 // share its plaintext planes through L2.  S entry of (batch b, query q) at (b * nq + q) * 2 L N,
 // as in k_select_sum_multi.
+template <int HT>
 __global__ void __launch_bounds__(TPB) k_select_sum_planes(Tables T, const int8_t* __restrict__ Pp, long gbytes,
                                                           const int8_t* __restrict__ Cp, long cps,
                                                           const int* __restrict__ qslot, int nq, int nb, int kbs,
@@ -872,7 +873,7 @@ __global__ void __launch_bounds__(TPB) k_select_sum_planes(Tables T, const int8_
   const int ob = local % oblocks, lk = (local / oblocks) * 8 + (bid & 7);
   const int l = lk / N, k = lk % N;
   const int lane = threadIdx.x & 63, m = lane & 15, g4 = lane >> 4;
-  const int wv = threadIdx.x >> 6, half = wv & 1, oct = ob * 2 + (wv >> 1);
+  const int wv = threadIdx.x >> 6, half = wv % HT, oct = ob * (TPB / 64 / HT) + wv / HT;
   if (oct * 8 >= nq || 16 * half >= nb) return;
   const int q = oct * 8 + (m >> 1), c = m & 1;
   const bool live = q < nq;
@@ -1303,12 +1304,21 @@ void request_planes(const Tables& T, const Consts& hc, const uint64_t* ch, int e
 }
 void select_sum_planes(const Tables& T, const Consts& hc, const int8_t* Pp, const int8_t* Cp, long cps,
                        const int* qslot, int nq, int nb, int ell, uint64_t* S, hipStream_t s) {
-  if (nb <= 0 || nq <= 0) return;
-  const int octets = (nq + 7) / 8, oblocks = (octets + 1) / 2;
+  if (nb <= 0 || nq <= 0 || nb > 4 * PT_GROUP) return;
+  const int ht = nb > 2 * PT_GROUP ? 4 : nb > PT_GROUP ? 2 : 1;
+  const int octets = (nq + 7) / 8, per = TPB / 64 / ht, oblocks = (octets + per - 1) / per;
   const int lks = hc.L * hc.n;   // a multiple of 8
-  hipLaunchKernelGGL(k_select_sum_planes, dim3(lks * oblocks), dim3(TPB), 0, s, T, Pp,
-                     (long)plaintext_plane_group_bytes(hc, ell), Cp, cps, qslot, nq, nb, plane_kblocks(ell), S,
-                     oblocks);
+  const long gb = (long)plaintext_plane_group_bytes(hc, ell);
+  const int kbs = plane_kblocks(ell);
+  if (ht == 4)
+    hipLaunchKernelGGL(k_select_sum_planes<4>, dim3(lks * oblocks), dim3(TPB), 0, s, T, Pp, gb, Cp, cps, qslot, nq,
+                       nb, kbs, S, oblocks);
+  else if (ht == 2)
+    hipLaunchKernelGGL(k_select_sum_planes<2>, dim3(lks * oblocks), dim3(TPB), 0, s, T, Pp, gb, Cp, cps, qslot, nq,
+                       nb, kbs, S, oblocks);
+  else
+    hipLaunchKernelGGL(k_select_sum_planes<1>, dim3(lks * oblocks), dim3(TPB), 0, s, T, Pp, gb, Cp, cps, qslot, nq,
+                       nb, kbs, S, oblocks);
 }
 void pointwise_mul(const Tables& T, const Consts& hc, const uint64_t* a, const uint64_t* b,
                    uint64_t* out, int rows, int nprimes, bool bcast, hipStream_t s) {

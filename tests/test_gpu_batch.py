@@ -36,9 +36,11 @@ def make_queries(ctx, cfg, server, nq, seed):
 
 
 @pytest.mark.parametrize("h,nq,cache,n_server", [(2, 1, False, 400), (2, 3, True, 400), (4, 9, True, 400),
-                                                 (3, 17, False, 400), (2, 5, True, 12000), (4, 3, False, 12000)])
+                                                 (3, 17, False, 400), (2, 5, True, 12000), (4, 3, False, 12000),
+                                                 (3, 70, True, 12000)])
 def test_batch_equals_alone(h, nq, cache, n_server):
-    """Small sets give tiles of a few batches; 12000 items give full 16-batch tiles."""
+    """Small sets give tiles of a few batches; 12000 items give full 16-batch groups (one 54-batch
+    tile with digit planes for up to 64 queries, 16-batch tiles beyond)."""
     import paper_2310_14565_amd as pk
     log_n, L = 10, 3
     bits = 16 if n_server > 1000 else {2: 10, 3: 12, 4: 12}[h]

@@ -98,4 +98,18 @@ def test_full_size(name, capsys):
     budget = gp.noise_budget(q["sk"], res)
     _progress(capsys, f"{name}: cardinality {card}, noise budget {budget} bits")
     assert card == c["planted"] and budget > 0
+
+    if c["cache"]:
+        # the batched path at full size: digit planes of every cached group, tiles of up to 64
+        # batches on the matrix cores; each query's result equals its single-query result
+        assert sv.plane_groups == -(-sv.cached_batches // 16) > 0
+        q2 = bench.make_query(gp, items, {"item_bits": c["bits"]}, c["m"] // 2, c["planted"] // 2, 35)
+        alone2 = torch.zeros_like(res)
+        sv.eval(q2["cts"], q2["rlk"], q2["mask"], alone2)
+        qs = [q, q2, q]
+        outs = [torch.zeros_like(res) for _ in qs]
+        _progress(capsys, f"{name}: batched path, {len(qs)} queries")
+        sv.eval_batch([x["cts"] for x in qs], [x["rlk"] for x in qs], [x["mask"] for x in qs], outs)
+        torch.cuda.synchronize()
+        assert torch.equal(outs[0], res) and torch.equal(outs[2], res) and torch.equal(outs[1], alone2)
     sv.close()

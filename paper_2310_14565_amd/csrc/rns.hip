@@ -825,36 +825,46 @@ __global__ void __launch_bounds__(TPB) k_plaintext_planes(Tables T, const uint64
     __builtin_memcpy(out + ((w * PL_DG + v) * 16 + b) * PL_K + 16 * g4, o[v], 16);
 }
 // Request planes of one query, layout [l][k][kb][digit][part][64], from its NTT form
-// [ell][2][L][N].  Wave = one (l, 8 positions, kb); lane = (position, part, quarter).
+// [ell][2][L][N].  Workgroup = one (l, 64 positions, kb): wave w reads code positions
+// 16 w .. 16 w + 15 of both parts for its 64 positions (one 512-byte row per load) and writes
+// their digits byte by byte to LDS as [position][digit][part][64]; the workgroup then copies
+// each position's 896 contiguous bytes out.
+constexpr int RP_ROW = PL_DG * 2 * PL_K + 16;   // LDS bytes per position (padded)
 __global__ void __launch_bounds__(TPB) k_request_planes(Tables T, const uint64_t* __restrict__ ch, int ell, int kbs,
                                                        int8_t* __restrict__ out) {
+  __shared__ __align__(16) int8_t sm[64 * RP_ROW];
   const Consts& C = *T.c;
   const int N = C.n, L = C.L;
-  const size_t w = (size_t)blockIdx.x * (TPB / 64) + (threadIdx.x >> 6);
-  if (w >= (size_t)L * (N / 8) * kbs) return;
-  const int lane = threadIdx.x & 63;
-  const int kb = (int)(w % kbs);
-  const size_t r = w / kbs;
-  const int k = (int)(r % (N / 8)) * 8 + (lane & 7), l = (int)(r / (N / 8));
-  const int c = (lane >> 3) & 1, g4 = lane >> 4;
+  const int kb = (int)(blockIdx.x % kbs);
+  const int blk = (int)(blockIdx.x / kbs);            // (l, 64-position block)
+  const int k0 = (blk % (N / 64)) * 64, l = blk / (N / 64);
+  const int kk = threadIdx.x & 63, jq = threadIdx.x >> 6;
   const uint64_t p = C.prm[l].p;
-  int8_t o[PL_DG][16];
+  int8_t* row = sm + kk * RP_ROW + jq * 16;
+  for (int c = 0; c < 2; ++c)
 #pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const int j = kb * PL_K + g4 * 16 + e;
-    uint64_t x = 0;
-    if (j < ell) {
-      x = ch[(((size_t)j * 2 + c) * L + l) * N + k];
-      x -= x >= p ? p : 0;
+    for (int e = 0; e < 16; ++e) {
+      const int j = kb * PL_K + jq * 16 + e;
+      uint64_t x = 0;
+      if (j < ell) {
+        x = ch[(((size_t)j * 2 + c) * L + l) * N + k0 + kk];
+        x -= x >= p ? p : 0;
+      }
+      int8_t d[PL_DG];
+      balanced_digits(x, d);
+#pragma unroll
+      for (int u = 0; u < PL_DG; ++u) row[(u * 2 + c) * PL_K + e] = d[u];
     }
-    int8_t d[PL_DG];
-    balanced_digits(x, d);
-#pragma unroll
-    for (int u = 0; u < PL_DG; ++u) o[u][e] = d[u];
+  __syncthreads();
+  constexpr int CH = PL_DG * 2 * PL_K / 16;             // 16-byte chunks per position
+  int8_t* dst = out + ((((size_t)l * N + k0) * kbs + kb) * PL_DG * 2) * PL_K;
+  const size_t kstride = (size_t)kbs * PL_DG * 2 * PL_K;
+  for (int x = threadIdx.x; x < 64 * CH; x += TPB) {
+    const int pos = x / CH, r = x % CH;
+    uint4 v;
+    __builtin_memcpy(&v, sm + pos * RP_ROW + r * 16, 16);
+    __builtin_memcpy(dst + pos * kstride + r * 16, &v, 16);
   }
-#pragma unroll
-  for (int u = 0; u < PL_DG; ++u)
-    __builtin_memcpy(out + (((((size_t)l * N + k) * kbs + kb) * PL_DG + u) * 2 + c) * PL_K + 16 * g4, o[u], 16);
 }
 // The contraction over a tile of up to 16 HT batches (HT consecutive 16-batch groups of planes,
 // gbytes apart).  Workgroup = 4 waves on one (l, k): 4 / HT query octets (16 columns each) x
@@ -1298,8 +1308,7 @@ void plaintext_planes(const Tables& T, const Consts& hc, const uint64_t* P, int 
 }
 void request_planes(const Tables& T, const Consts& hc, const uint64_t* ch, int ell, int8_t* out, hipStream_t s) {
   const int kbs = plane_kblocks(ell);
-  const size_t waves = (size_t)hc.L * (hc.n / 8) * kbs;
-  hipLaunchKernelGGL(k_request_planes, dim3((unsigned)((waves + TPB / 64 - 1) / (TPB / 64))), dim3(TPB), 0, s, T, ch,
+  hipLaunchKernelGGL(k_request_planes, dim3((unsigned)((size_t)hc.L * (hc.n / 64) * kbs)), dim3(TPB), 0, s, T, ch,
                      ell, kbs, out);
 }
 void select_sum_planes(const Tables& T, const Consts& hc, const int8_t* Pp, const int8_t* Cp, long cps,

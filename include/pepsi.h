@@ -174,6 +174,9 @@ int pepsi_noise_budget(const pepsi_params* params, const int8_t* d_sk, const uin
 typedef struct pepsi_server pepsi_server;
 
 #define PEPSI_SERVER_CACHE_PLAINTEXTS 1u  /* keep every server plaintext in NTT form in HBM */
+#define PEPSI_SERVER_PLANES_ONLY 2u       /* with CACHE_PLAINTEXTS: keep them only as int8 digit
+                                             planes (7/8 of the bytes), for servers that mostly
+                                             batch or serve many queries                         */
 
 typedef struct {
   uint32_t mu;             /* batches of the table                                     */
@@ -197,7 +200,14 @@ typedef struct {
  * reserve, the cached groups are also stored as int8 digit planes (seven balanced
  * base-256 digits per residue, about 7/8 of the cache's bytes), which the batched and
  * served evaluations contract on the matrix cores; pepsi_server_info.plane_groups
- * gives their number.  Results are identical either way.
+ * gives their number.  With PEPSI_SERVER_PLANES_ONLY as well, the NTT-form cache is not
+ * kept: each 16-batch group is generated into a one-group staging store, converted to
+ * digit planes and dropped, for as many groups as fit beside the reserve (so more batches
+ * fit).  Every evaluation then also takes single queries through the planes, except
+ * ranges that do not start at a multiple of 16 batches, which regenerate their plaintexts;
+ * an evaluation fails with PEPSI_E_NOMEM if the request planes of its queries do not fit.
+ * Results are identical in every mode.  Unknown flags, or PLANES_ONLY without
+ * CACHE_PLAINTEXTS: PEPSI_E_ARG.
  * Synchronises the stream.  Errors: PEPSI_E_RANGE, PEPSI_E_BIN_OVERFLOW,
  * PEPSI_E_NOMEM. */
 int pepsi_server_create(const pepsi_params* params, const uint32_t* items, uint64_t n,

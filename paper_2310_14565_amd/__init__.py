@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libpepsi.so")
 
 PEPSI_PARAMS_PBH = 1
 PEPSI_SERVER_CACHE_PLAINTEXTS = 1
+PEPSI_SERVER_PLANES_ONLY = 2
 MAX_PRIMES = 17
 
 
@@ -273,13 +274,15 @@ class Server:
     """The server's prepared set on the device (pepsi_server_*)."""
 
     def __init__(self, params: Params, items: np.ndarray, cache_plaintexts: bool = False, stream=None,
-                 values: np.ndarray | None = None, max_cached: int = 0):
+                 values: np.ndarray | None = None, max_cached: int = 0, planes_only: bool = False):
         """values (one per item, < t) make every evaluation PSI-Sum (with a mask) or labelled
         PSI (without); None is PSI-cardinality / the indicator.  max_cached bounds the cached
-        batches (0: as many as fit)."""
+        batches (0: as many as fit); planes_only keeps the cache only as int8 digit planes."""
         items = np.ascontiguousarray(items, dtype=np.uint32)
         h_ = C.c_void_p()
         flags = PEPSI_SERVER_CACHE_PLAINTEXTS if cache_plaintexts else 0
+        if planes_only:
+            flags |= PEPSI_SERVER_PLANES_ONLY
         vp = None
         if values is not None:
             values = np.ascontiguousarray(values, dtype=np.uint32)

@@ -595,16 +595,17 @@ struct Engine {
 
   size_t cpstride() const { return request_plane_bytes(P->H.consts, P->H.ell); }
   // Request digit planes for every query slot, so that tiles whose plaintext planes are resident
-  // take the matrix-core select-and-sum; left off (no error) when they would not fit beside an
-  // 8 GiB working reserve.
-  int enable_planes() {
+  // take the matrix-core select-and-sum.  When they would not fit beside a 2 GiB reserve they
+  // stay off, which is an error if the server holds its plaintexts only as planes (required).
+  int enable_planes(bool required) {
     planes_on = false;
-    if (P->H.ell > PL_MAX_ELL || Qmax < 2) return 0;
+    if (P->H.ell > PL_MAX_ELL) return 0;
     const size_t need = (size_t)Qmax * cpstride();
     if (need > cplanes.cap) {
       size_t free_b = 0, total_b = 0;
       if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return fail(PEPSI_E_DEVICE, "hipMemGetInfo failed");
-      if (free_b < need + ((size_t)8 << 30)) return 0;
+      if (free_b < need + ((size_t)2 << 30))
+        return required ? fail(PEPSI_E_NOMEM, "no room for request digit planes (%zu bytes)", need) : 0;
       int rc = cplanes.ensure(need);
       if (rc) return rc;
     }
@@ -638,13 +639,22 @@ struct Engine {
     const size_t n = H.n, L = H.L;
     hipEvent_t a = nullptr, b = nullptr;
     if (timer && timer->on) { a = timer->get(); b = timer->get(); (void)hipEventRecord(a, s); }
-    if (nq == 1)
+    if (nq == 1 && pv.p) {
       select_sum(P->T, H.consts, chat.as<uint64_t>((size_t)single_slot * cstride()), pv.p, pv.gs, pv.bfirst,
                  H.ell, nb, Sx, (long)(2 * L * n), s);
-    else if (pv.planes && planes_on)
-      select_sum_planes(P->T, H.consts, pv.planes, cplanes.as<int8_t>(), (long)cpstride(), qslot, nq, nb, H.ell, Sx,
-                        s);
-    else
+    } else if (pv.planes && planes_on) {
+      // at most 4 groups per launch; a single query reads its planes from its own slot
+      const size_t gbytes = plaintext_plane_group_bytes(H.consts, H.ell);
+      const int one = single_slot;
+      for (int c0 = 0; c0 < nb; c0 += 4 * PT_GROUP)
+        select_sum_planes(P->T, H.consts, pv.planes + (size_t)(c0 / PT_GROUP) * gbytes,
+                          cplanes.as<int8_t>(nq == 1 ? (size_t)one * cpstride() : 0), (long)cpstride(),
+                          nq == 1 ? nullptr : qslot, nq, std::min(4 * PT_GROUP, nb - c0), H.ell,
+                          Sx + (size_t)c0 * nq * 2 * L * n, s);
+    } else if (nq == 1) {
+      select_sum(P->T, H.consts, chat.as<uint64_t>((size_t)single_slot * cstride()), pv.p, pv.gs, pv.bfirst,
+                 H.ell, nb, Sx, (long)(2 * L * n), s);
+    } else
       select_sum_multi(P->T, H.consts, chat.as<uint64_t>(), (long)cstride(), qslot, nq, pv.p, pv.gs, pv.bfirst,
                        H.ell, nb, Sx, s);
     if (a) {
@@ -662,7 +672,7 @@ struct Engine {
                  const PtView& pv, uint64_t* Sout, hipStream_t s) {
     const HostParams& H = P->H;
     const size_t n = H.n, L = H.L;
-    if (pv.p) {
+    if (pv.p || (pv.planes && planes_on)) {
       timed_select_sum(pv, nb, nq, qslot, single_slot, Sout, s);
       return;
     }
@@ -782,18 +792,18 @@ struct Engine {
   }
 
   // Plaintexts of tile [b0, b0 + nb): the cache when it covers the tile, else generated.
-  // With digit planes of the cache's groups (planes, group_bytes each), a tile that starts a
-  // 16-batch group and spans at most four groups also gets their planes.
+  // With digit planes of the first plane_batches batches (groups of 16, group_bytes each), a
+  // tile that starts a group and lies inside them also gets its planes.
   static PtView cached_tile(const uint64_t* cache, uint32_t cached, uint32_t b0, int nb,
-                            const int8_t* planes = nullptr, size_t group_bytes = 0) {
+                            const int8_t* planes = nullptr, size_t group_bytes = 0, uint32_t plane_batches = 0) {
     PtView v;
     if (cache && b0 + (uint32_t)nb <= cached) {
       v.p = cache;
       v.gs = cache_group(cached);
       v.bfirst = (int)b0;
-      if (planes && v.gs == PT_GROUP && b0 % PT_GROUP == 0 && nb <= 4 * PT_GROUP)
-        v.planes = planes + (size_t)(b0 / PT_GROUP) * group_bytes;
     }
+    if (planes && b0 % PT_GROUP == 0 && b0 + (uint32_t)nb <= plane_batches)
+      v.planes = planes + (size_t)(b0 / PT_GROUP) * group_bytes;
     return v;
   }
 
@@ -802,11 +812,12 @@ struct Engine {
   // was measured slower: the select-and-sum needs nearly full occupancy to cover HBM latency.)
   int run(const uint16_t* cw, const uint64_t* cache, uint32_t cached, uint32_t begin, uint32_t stop, int nq,
           const uint64_t* const* cts, const uint64_t* const* rlk, hipStream_t s, const int8_t* planes = nullptr,
-          size_t group_bytes = 0) {
+          size_t group_bytes = 0, uint32_t plane_batches = 0) {
     for (int q = 0; q < nq; ++q) admit(q, cts[q], rlk[q], s);
     for (uint32_t b0 = begin; b0 < stop; b0 += TBq) {
       const int nb = (int)std::min<uint32_t>(TBq, stop - b0);
-      run_tile(cw, (int)b0, nb, nq, nullptr, 0, cached_tile(cache, cached, b0, nb, planes, group_bytes), s);
+      run_tile(cw, (int)b0, nb, nq, nullptr, 0,
+               cached_tile(cache, cached, b0, nb, planes, group_bytes, plane_batches), s);
     }
     return 0;
   }
@@ -837,7 +848,15 @@ struct pepsi_server {
   uint32_t cached_batches = 0;
   DevBuf planes;        // digit planes of the cached 16-batch groups (matrix-core select-and-sum)
   uint32_t plane_groups = 0;
+  uint32_t plane_batches = 0;  // batches covered by the planes (the first ones)
   size_t plane_group_bytes = 0;
+  bool planes_only = false;    // plaintexts kept only as digit planes
+  const int8_t* planes_p() const { return plane_groups ? planes.as<int8_t>() : nullptr; }
+  // On-the-fly generation: the single-query engine needs it unless the NTT-form cache covers
+  // every batch holding items (its ranges may start anywhere); the many-query engines walk
+  // group-aligned tiles, which the planes cover too.
+  bool need_gen_single() const { return cached_batches < max_load; }
+  bool need_gen_multi() const { return cached_batches < max_load && plane_batches < max_load; }
   Engine eng;            // one query at a time (plain path)
   bool ready = false;
   Engine beng;           // many queries per launch (batched path)
@@ -864,6 +883,9 @@ extern "C" int pepsi_server_create_ex(const pepsi_params* Pc, const uint32_t* it
   pepsi_params* P = const_cast<pepsi_params*>(Pc);
   if (!P || (!items && n) || !out) return fail(PEPSI_E_ARG, "null argument");
   *out = nullptr;
+  if (flags & ~(PEPSI_SERVER_CACHE_PLAINTEXTS | PEPSI_SERVER_PLANES_ONLY)) return fail(PEPSI_E_ARG, "unknown flags");
+  if ((flags & PEPSI_SERVER_PLANES_ONLY) && !(flags & PEPSI_SERVER_CACHE_PLAINTEXTS))
+    return fail(PEPSI_E_ARG, "PEPSI_SERVER_PLANES_ONLY needs PEPSI_SERVER_CACHE_PLAINTEXTS");
   const HostParams& H = P->H;
   {
     std::unordered_set<uint32_t> seen;
@@ -915,7 +937,47 @@ extern "C" int pepsi_server_create_ex(const pepsi_params* Pc, const uint32_t* it
     if (hipStreamSynchronize(s) != hipSuccess) { delete sv; return fail(PEPSI_E_DEVICE, "value encoding failed"); }
     sv->valued = true;
   }
-  if ((flags & PEPSI_SERVER_CACHE_PLAINTEXTS) && max_load > 0) {
+  if ((flags & PEPSI_SERVER_PLANES_ONLY) && max_load > 0 && H.ell <= PL_MAX_ELL) {
+    // digit planes only, as many 16-batch groups as fit beside the working reserve (and the
+    // one-group staging store they are generated in)
+    const size_t gb = plaintext_plane_group_bytes(H.consts, H.ell);
+    const size_t stage = (size_t)PT_GROUP * H.ell * H.L * H.n * 8;
+    const size_t reserve = (size_t)48 << 30;
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) { delete sv; return fail(PEPSI_E_DEVICE, "hipMemGetInfo failed"); }
+    const uint32_t all = (max_load + PT_GROUP - 1) / PT_GROUP;
+    uint32_t groups = (uint32_t)std::min<size_t>(free_b > reserve + stage ? (free_b - reserve - stage) / gb : 0, all);
+    if (max_cached > 0 && max_cached < max_load) groups = std::min(groups, max_cached / PT_GROUP);
+    if (groups > 0) {
+      DevBuf stg, poly;
+      const int G8 = 8;
+      if ((rc = sv->planes.ensure(gb * groups)) || (rc = stg.ensure(stage)) ||
+          (rc = poly.ensure((size_t)G8 * H.ell * H.n * 4))) {
+        delete sv;
+        return rc;
+      }
+      hipStream_t s = S(stream);
+      for (uint32_t G = 0; G < groups; ++G) {
+        const uint32_t gend = std::min<uint32_t>((G + 1) * PT_GROUP, max_load);
+        for (uint32_t b0 = G * PT_GROUP; b0 < gend; b0 += G8) {
+          const int g = (int)std::min<uint32_t>(G8, gend - b0);
+          encode_server_planes(P->T, H.logn, sv->cw.as<uint16_t>(), H.h, H.ell, (int)b0, g, poly.as<uint32_t>(), s);
+          PtLayout pl;
+          pl.ell = H.ell;
+          pl.gs = PT_GROUP;
+          pl.bbase = (int)(b0 - G * PT_GROUP);
+          ntt_forward_plaintexts(P->T, H.logn, poly.as<uint32_t>(), stg.as<uint64_t>(), g, H.L, pl, s);
+        }
+        plaintext_planes(P->T, H.consts, stg.as<uint64_t>(), PT_GROUP, 0, H.ell, sv->planes.as<int8_t>((size_t)G * gb),
+                         s);
+      }
+      if (hipStreamSynchronize(s) != hipSuccess) { delete sv; return fail(PEPSI_E_DEVICE, "plane build failed"); }
+      sv->plane_groups = groups;
+      sv->plane_batches = std::min<uint32_t>(groups * PT_GROUP, max_load);
+      sv->plane_group_bytes = gb;
+      sv->planes_only = true;
+    }
+  } else if ((flags & PEPSI_SERVER_CACHE_PLAINTEXTS) && max_load > 0) {
     // as many batches as fit beside a working reserve, in whole 16-batch tiles unless all fit
     const size_t per = (size_t)H.ell * H.L * H.n;
     size_t free_b = 0, total_b = 0;
@@ -958,6 +1020,7 @@ extern "C" int pepsi_server_create_ex(const pepsi_params* Pc, const uint32_t* it
                              sv->planes.as<int8_t>((size_t)G * gb), s);
           if (hipStreamSynchronize(s) != hipSuccess) { delete sv; return fail(PEPSI_E_DEVICE, "plane build failed"); }
           sv->plane_groups = groups;
+          sv->plane_batches = nc;
           sv->plane_group_bytes = gb;
         }
       }
@@ -1005,7 +1068,8 @@ extern "C" int pepsi_server_eval_range(pepsi_server* sv, const uint64_t* cts, co
   hipStream_t s = S(stream);
   if (!sv->ready) {
     const int tb = std::min<int>(512, std::max<int>(1, (int)sv->max_load));
-    int rc = sv->eng.setup(sv->P, tb, 1, sv->cached_batches < sv->max_load, sv->values_hat());
+    int rc = sv->eng.setup(sv->P, tb, 1, sv->need_gen_single(), sv->values_hat());
+    if (!rc && sv->planes_only) rc = sv->eng.enable_planes(true);
     if (rc) return rc;
     sv->eng.timer = &sv->timer;
     sv->ready = true;
@@ -1018,7 +1082,8 @@ extern "C" int pepsi_server_eval_range(pepsi_server* sv, const uint64_t* cts, co
   const uint64_t* c1[1] = {cts};
   const uint64_t* r1[1] = {rlk};
   int rc = E.run(sv->cw.as<uint16_t>(), sv->cached ? sv->cache.as<uint64_t>() : nullptr, sv->cached_batches, begin,
-                 std::max(begin, stop), 1, c1, r1, s);
+                 std::max(begin, stop), 1, c1, r1, s, sv->planes_only ? sv->planes_p() : nullptr,
+                 sv->plane_group_bytes, sv->plane_batches);
   if (rc) return rc;
   E.finish(0, finalize != 0, mask, out, s);
   if (ea) {
@@ -1059,19 +1124,18 @@ extern "C" int pepsi_server_eval_batch(pepsi_server* sv, uint32_t nq, const uint
         if (free_b > fixed + (size_t)cand * nq * engine_pair_bytes(H)) { tb = cand; break; }
     }
     int rc = sv->beng.setup(sv->P, std::min<int>(tb, std::max<int>(1, (int)sv->max_load)), (int)nq,
-                            sv->cached_batches < sv->max_load, sv->values_hat());
+                            sv->need_gen_multi(), sv->values_hat());
     if (rc) return rc;
     sv->beng.timer = &sv->timer;
     sv->bqmax = (int)nq;
-    if (sv->plane_groups > 0 && (rc = sv->beng.enable_planes())) return rc;
+    if (sv->plane_groups > 0 && (rc = sv->beng.enable_planes(sv->planes_only))) return rc;
   }
   Engine& E = sv->beng;
   hipEvent_t ea = nullptr, eb = nullptr;
   if (sv->timer.on) { ea = sv->timer.get(); eb = sv->timer.get(); (void)hipEventRecord(ea, s); }
   const uint32_t stop = std::min<uint32_t>(H.mu, sv->max_load);
   int rc = E.run(sv->cw.as<uint16_t>(), sv->cached ? sv->cache.as<uint64_t>() : nullptr, sv->cached_batches, 0,
-                 stop, (int)nq, cts, rlk, s, sv->plane_groups ? sv->planes.as<int8_t>() : nullptr,
-                 sv->plane_group_bytes);
+                 stop, (int)nq, cts, rlk, s, sv->planes_p(), sv->plane_group_bytes, sv->plane_batches);
   if (rc) return rc;
   for (uint32_t q = 0; q < nq; ++q) E.finish((int)q, true, masks ? masks[q] : nullptr, out[q], s);
   if (ea) {
@@ -1183,8 +1247,7 @@ struct pepsi_serve {
         const int nb = (int)std::min<uint32_t>(eng.TBq, stop_b - b0);
         eng.run_tile(sv->cw.as<uint16_t>(), (int)b0, nb, na, qslot_dev.as<int>(), live[0],
                      Engine::cached_tile(sv->cached ? sv->cache.as<uint64_t>() : nullptr, sv->cached_batches, b0,
-                                         nb, sv->plane_groups ? sv->planes.as<int8_t>() : nullptr,
-                                         sv->plane_group_bytes),
+                                         nb, sv->planes_p(), sv->plane_group_bytes, sv->plane_batches),
                      stream);
         cursor = (cursor + 1) % T;
         ++steps;
@@ -1233,8 +1296,8 @@ extern "C" int pepsi_serve_create(pepsi_server* sv, uint32_t max_active, uint64_
   sr->slots = (int)slots;
   sr->stop_b = std::min<uint32_t>(H.mu, sv->max_load);
   sr->T = (int)((sr->stop_b + tbq - 1) / tbq);
-  int rc = sr->eng.setup(sv->P, tbq, (int)slots, sv->cached_batches < sv->max_load, sv->values_hat());
-  if (!rc && sv->plane_groups) rc = sr->eng.enable_planes();
+  int rc = sr->eng.setup(sv->P, tbq, (int)slots, sv->need_gen_multi(), sv->values_hat());
+  if (!rc && sv->plane_groups) rc = sr->eng.enable_planes(sv->planes_only);
   if (!rc) rc = sr->qslot_dev.ensure(sizeof(int) * slots);
   if (!rc && hipHostMalloc((void**)&sr->qslot_host, sizeof(int) * slots, hipHostMallocDefault) != hipSuccess)
     rc = fail(PEPSI_E_NOMEM, "pinned slot buffer");

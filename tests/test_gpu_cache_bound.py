@@ -94,3 +94,39 @@ def test_results_do_not_depend_on_the_cache_bound(case, valued):
     want = c["ctx"].server_eval(q["cts"], spos, q["rlk"], H, mask=q["mask"], vals=vtab)
     assert (ref[0][0] == want).all() and (ref[1][0] == want).all()
     ref_sv.close()
+
+
+@pytest.mark.parametrize("valued,bound", [(False, 0), (True, 0), (False, 37)])
+def test_planes_only_equals_uncached(case, valued, bound):
+    """Plaintexts kept only as digit planes (all groups, or the first two under a bound of 37):
+    single, ranged (group-aligned and not), batched and served results equal the uncached
+    server's bit for bit."""
+    import torch
+    c = case
+    pk = c["pk"]
+    vals = c["values"] if valued else None
+    ref_sv = pk.Server(c["gp"], c["server"], cache_plaintexts=False, values=vals)
+    ref = _results(c, ref_sv)
+    sv = pk.Server(c["gp"], c["server"], cache_plaintexts=True, values=vals, max_cached=bound, planes_only=True)
+    ml = ref_sv.max_load
+    want_groups = -(-ml // 16) if bound == 0 else bound // 16
+    say(f"planes only valued={valued} bound={bound}: {sv.plane_groups} groups, max_load={ml}")
+    assert sv.plane_groups == want_groups and sv.cached_batches == 0 and not sv.cached
+    got = _results(c, sv)
+    for kind, a, b in zip(("eval", "eval_batch"), ref[:2], got[:2]):
+        for i, (x, y) in enumerate(zip(a, b)):
+            assert (x == y).all(), f"{kind} query {i}"
+    assert (ref[2] == got[2]).all(), "eval_range"
+    # served
+    n = c["n"]
+    srv = pk.Serve(sv, max_active=2)
+    outs = [empty((2, L, n), np.uint64) for _ in c["dev"]]
+    ids = [srv.submit(d["cts"], d["rlk"], d["mask"], o) for d, o in zip(c["dev"], outs)]
+    for r in ids:
+        srv.wait(r)
+    srv.close()
+    torch.cuda.synchronize()
+    for i, o in enumerate(outs):
+        assert (to_host(o, np.uint64) == ref[0][i]).all(), f"served query {i}"
+    sv.close()
+    ref_sv.close()

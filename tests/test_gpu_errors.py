@@ -63,6 +63,17 @@ def test_hashing_failures():
     assert _code(lambda: gp.client_table(W.server_items(n + 1, 16, 5))) == E_CUCKOO
 
 
+def test_server_flags():
+    import ctypes as C
+    import paper_2310_14565_amd as pk
+    gp = pk.Params(10, 3, 2, 10, P.server_bin_bound(100, 1024))
+    items = W.server_items(100, 10, 7)
+    h = C.c_void_p()
+    for flags in (4, 0x80, pk.PEPSI_SERVER_PLANES_ONLY):   # unknown, or planes without the cache
+        assert pk.lib().pepsi_server_create_ex(gp.handle, items.ctypes.data_as(C.c_void_p), None, items.shape[0],
+                                               flags, 0, None, C.byref(h)) == E_ARG
+
+
 def test_bad_evaluation_arguments():
     import paper_2310_14565_amd as pk
     n, L = 1024, 3

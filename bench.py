@@ -138,7 +138,7 @@ def make_query(params, server_items, cfg, m, planted, seed):
     return dict(sk=sk, cts=cts, rlk=rlk, mask=mask, planted=planted, m=m, client=client)
 
 
-def serving_leg(pk, requests, pool, slots, load, seed):
+def serving_leg(pk, requests, pool, slots, load, seed, planes_only=False):
     """Continuous batching: `requests` requests over a pool of distinct client queries, Poisson arrivals
     at `load` x the saturated capacity measured first on the same handle; latency = completion minus
     scheduled arrival."""
@@ -156,11 +156,11 @@ def serving_leg(pk, requests, pool, slots, load, seed):
           for i, m in enumerate(sizes)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    server = pk.Server(params, server_items, cache_plaintexts=True)
+    server = pk.Server(params, server_items, cache_plaintexts=True, planes_only=planes_only)
     torch.cuda.synchronize()
     prep_s = time.perf_counter() - t0
     log(f"[bench] serving server ready in {prep_s:.1f} s: max load {server.max_load}, "
-        f"{server.cached_batches} of {server.max_load} batches cached")
+        f"{server.cached_batches} of {server.max_load} batches cached, {server.plane_groups} digit-plane groups")
     srv = pk.Serve(server, max_active=slots)
     outs = [torch.zeros((2, L, n), dtype=torch.int64, device="cuda") for _ in range(requests)]
     torch.cuda.synchronize()
@@ -206,7 +206,7 @@ def serving_leg(pk, requests, pool, slots, load, seed):
     if bad:
         log(f"[bench] WRONG RESULT in {bad} served requests")
         sys.exit(1)
-    max_load, cached_batches = server.max_load, server.cached_batches
+    max_load, cached_batches, plane_groups = server.max_load, server.cached_batches, server.plane_groups
     server.close()
     comparisons = n * sc["mu"]
     return {
@@ -216,7 +216,9 @@ def serving_leg(pk, requests, pool, slots, load, seed):
         "query_pool": pool,
         "slots": info.slots,
         "tiles_per_cycle": info.tiles,
+        "store": "digit planes only" if planes_only else "NTT-form cache (+ digit planes when both fit)",
         "cached_batches": int(cached_batches),
+        "plane_groups": int(plane_groups),
         "server_max_load": int(max_load),
         "saturated_queries_per_s": round(capacity, 3),
         "arrival_rate_per_s": round(rate, 3),
@@ -403,6 +405,8 @@ def main():
     ap.add_argument("--serve", type=int, default=500, help="requests in the serving leg (0: skip it)")
     ap.add_argument("--serve-pool", type=int, default=16, help="distinct client queries behind the requests")
     ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--serve-store", choices=["cache", "planes"], default="planes",
+                    help="serving server keeps the NTT-form cache, or only int8 digit planes")
     ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate / saturated capacity")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the plain leg, run one elementwise negation of MIB MiB of int64 (a copy kernel "
@@ -557,7 +561,7 @@ def main():
         del cts, rlk, out
         torch.cuda.empty_cache()
         line["serving"] = serving_leg(pk, args.serve, args.serve_pool, args.serve_slots, args.serve_load,
-                                      args.seed + 11)
+                                      args.seed + 11, planes_only=args.serve_store == "planes")
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample)")
         line["cpu_baseline"] = cpu_baseline(cfg, params, server_items, args.seed)

@@ -81,11 +81,23 @@ def traffic_record(kernel: str):
     return rec
 
 
-def cpu_baseline(cfg, params, server_items, seed):
-    """The oracle timed on a bounded sample: the client-ciphertext transforms plus one server batch,
-    extrapolated linearly to all mu batches of one query."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfg, params, server_items, seed, computed_batches):
+    """The oracle timed on a bounded sample: the client-ciphertext transforms, then four server
+    batches spread over the batches that hold items (each timed alone), extrapolated linearly to
+    one query over all mu batches (the oracle computes every batch, dummies included)."""
     from oracle import protocol as PR
-    from oracle.core import Context
+    from oracle.core import Context, num_threads
     import workload as W
     n, L, h = 1 << cfg["log_n"], cfg["L"], cfg["h"]
     ctx = Context(n, params.q_primes)
@@ -97,19 +109,24 @@ def cpu_baseline(cfg, params, server_items, seed):
     t0 = time.perf_counter()
     ctx.server_eval(cts, spos, rlk, h, finalize=False, begin=0, end=0)
     t_prep = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    ctx.server_eval(cts, spos, rlk, h, finalize=False, begin=0, end=1)
-    t_one = time.perf_counter() - t0
-    t_batch = max(t_one - t_prep, 1e-9)
+    sample = sorted({0, computed_batches // 3, (2 * computed_batches) // 3, max(computed_batches - 1, 0)})
+    per = []
+    for b in sample:
+        t0 = time.perf_counter()
+        ctx.server_eval(cts, spos, rlk, h, finalize=False, begin=b, end=b + 1)
+        per.append(max(time.perf_counter() - t0 - t_prep, 1e-9))
+    t_batch = float(np.mean(per))
     t_query = t_prep + cfg["mu"] * t_batch
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {
         "value": n * cfg["mu"] / t_query,
         "unit": "slot-comparisons/s",
-        "cores": cores,
+        "cores": num_threads(),
         "kind": "oracle",
-        "sample": (f"client-ciphertext transforms ({t_prep:.2f} s) + 1 of {cfg['mu']} server batches "
-                   f"({t_batch:.2f} s), extrapolated linearly to one query ({t_query:.0f} s)"),
+        "cpu_model": cpu_model(),
+        "nproc": len(os.sched_getaffinity(0)),
+        "sample": (f"client-ciphertext transforms ({t_prep:.2f} s) + server batches {sample} of {cfg['mu']} timed "
+                   f"one by one ({', '.join(f'{x:.2f}' for x in per)} s), their mean extrapolated linearly to one "
+                   f"query ({t_query:.0f} s)"),
     }
 
 
@@ -220,6 +237,8 @@ def serving_leg(pk, requests, pool, slots, load, seed, planes_only=False):
         "cached_batches": int(cached_batches),
         "plane_groups": int(plane_groups),
         "server_max_load": int(max_load),
+        "batches_computed": int(max_load),
+        "value_computed_batches": round(requests * n * max_load / span, 1),
         "saturated_queries_per_s": round(capacity, 3),
         "arrival_rate_per_s": round(rate, 3),
         "queries_per_s": round(requests / span, 3),
@@ -384,6 +403,82 @@ def batched_leg(params, server, server_items, cfg, nq, steps, seed, plain_value)
         "speedup_vs_plain": round(value / plain_value, 3),
         "select_sum_ms_per_batch": round(tm.select_sum_ms / steps, 2),
         "checked_cardinalities": nq,
+        "batches_computed": int(server.max_load),
+        "value_computed_batches": round(nq * n * server.max_load / t, 1),
+    }
+
+
+def large_leg(pk, steps, nq, seed):
+    """The large configuration (N = 16384, L = 8, h = 4, ell = 569, n = 2^24 32-bit items, m = 4096
+    with 1024 planted, mu = 3487): the plaintexts (2.1 TB) are not resident, so every query
+    regenerates them per tile; plain single queries, then one batch of nq queries sharing the
+    generation (m log-uniform in [1024, 4096], 25% planted)."""
+    import torch
+    import workload as W
+    cfg = CONFIGS["large"]
+    n, L = 1 << cfg["log_n"], cfg["L"]
+    params = pk.Params(cfg["log_n"], L, cfg["h"], cfg["item_bits"], cfg["mu"])
+    items = W.server_items(cfg["n_server"], cfg["item_bits"], seed)
+    t0 = time.perf_counter()
+    server = pk.Server(params, items, cache_plaintexts=False)
+    torch.cuda.synchronize()
+    prep = time.perf_counter() - t0
+    log(f"[bench] large leg: server ready in {prep:.1f} s, max load {server.max_load}")
+    q = make_query(params, items, cfg, cfg["m_client"], cfg["planted"], seed + 1)
+    out = torch.zeros((2, L, n), dtype=torch.int64, device="cuda")
+    server.eval(q["cts"], q["rlk"], q["mask"], out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        server.eval(q["cts"], q["rlk"], q["mask"], out)
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / steps
+    slots = torch.zeros((1, n), dtype=torch.int32, device="cuda")
+    params.decrypt(q["sk"], out.reshape(1, 2, L, n), slots)
+    torch.cuda.synchronize()
+    card = int(slots.cpu().numpy().view(np.uint32).astype(np.int64).sum() % 65537)
+    budget = params.noise_budget(q["sk"], out)
+    if card != cfg["planted"] or budget <= 0:
+        log(f"[bench] WRONG RESULT in the large leg: {card}, budget {budget}")
+        sys.exit(1)
+    g = W.rng(seed, "large-batch-sizes")
+    sizes = np.rint(np.exp(g.uniform(np.log(1024), np.log(4096), size=nq))).astype(int)
+    qs = [q] + [make_query(params, items, cfg, int(m), int(round(0.25 * m)), seed + 100 * (i + 2))
+                for i, m in enumerate(sizes[1:])]
+    outs = [torch.zeros((2, L, n), dtype=torch.int64, device="cuda") for _ in qs]
+    args = ([x["cts"] for x in qs], [x["rlk"] for x in qs], [x["mask"] for x in qs], outs)
+    server.eval_batch(*args)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    server.eval_batch(*args)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    bad = int(not torch.equal(outs[0], out))
+    for x, o in zip(qs[1:], outs[1:]):
+        params.decrypt(x["sk"], o.reshape(1, 2, L, n), slots)
+        torch.cuda.synchronize()
+        bad += int(slots.cpu().numpy().view(np.uint32).astype(np.int64).sum() % 65537) != x["planted"]
+    if bad:
+        log(f"[bench] WRONG RESULT in {bad} batched queries of the large leg")
+        sys.exit(1)
+    max_load = int(server.max_load)
+    server.close()
+    v_plain = n * cfg["mu"] / t_plain
+    v_batch = nq * n * cfg["mu"] / t_batch
+    return {
+        "workload": (f"large: N={n} L={L} t=65537 h={cfg['h']} ell={params.ell} b={n} mu={cfg['mu']} "
+                     f"n={cfg['n_server']} m={cfg['m_client']} planted={cfg['planted']}, plaintexts generated "
+                     f"per tile"),
+        "offline_s": round(prep, 2),
+        "batches_computed": max_load,
+        "plain": {"ms_per_query": round(1e3 * t_plain, 1), "value": round(v_plain, 1),
+                  "unit": "slot-comparisons/s", "steps": steps,
+                  "check": {"cardinality": card, "noise_budget_bits": budget}},
+        "batched": {"queries": nq, "m_range": [int(min(cfg["m_client"], sizes[1:].min(initial=4096))),
+                                               int(max(cfg["m_client"], sizes[1:].max(initial=0)))],
+                    "ms_per_query": round(1e3 * t_batch / nq, 1), "value": round(v_batch, 1),
+                    "unit": "slot-comparisons/s", "speedup_vs_plain": round(v_batch / v_plain, 3),
+                    "checked": "first query equals its single-query result; every cardinality"},
     }
 
 
@@ -402,6 +497,9 @@ def main():
     ap.add_argument("--psi-sum-steps", type=int, default=5, help="steps of the PSI-Sum leg (0: skip it)")
     ap.add_argument("--paper32-steps", type=int, default=5,
                     help="steps of the leg with the paper's own 32-bit parameters (0: skip it)")
+    ap.add_argument("--large-steps", type=int, default=2,
+                    help="single queries timed in the large-configuration leg (0: skip the leg)")
+    ap.add_argument("--large-batch", type=int, default=4, help="queries of the large leg's batch")
     ap.add_argument("--serve", type=int, default=500, help="requests in the serving leg (0: skip it)")
     ap.add_argument("--serve-pool", type=int, default=16, help="distinct client queries behind the requests")
     ap.add_argument("--serve-slots", type=int, default=64)
@@ -535,6 +633,11 @@ def main():
                        "p99": round(1e3 * float(np.percentile(per_step, 99)), 3)},
         "offline_s": round(offline_s, 3),
         "server_max_load": server.max_load,
+        "batches_computed": int(server.max_load),
+        "value_computed_batches": round(n * server.max_load * args.steps / t_total, 1),
+        "value_note": ("value counts b * mu slot comparisons per query; batches at or above the fullest bin hold "
+                       "only dummies, their equality ciphertext is exactly zero and they are skipped, so "
+                       "value_computed_batches counts only the batches the kernels run"),
         "check": {"cardinality": card, "noise_budget_bits": budget},
     }
     line["compression"] = compression_leg(params, out, args.seed + 17)
@@ -556,6 +659,10 @@ def main():
     if args.paper32_steps > 0 and args.config == "paper":
         server.close()
         line["paper32"] = paper32_leg(pk, args.paper32_steps, args.seed + 13)
+    if args.large_steps > 0 and args.config == "paper":
+        server.close()
+        torch.cuda.empty_cache()
+        line["large"] = large_leg(pk, args.large_steps, args.large_batch, args.seed + 19)
     if args.serve > 0:
         server.close()
         del cts, rlk, out
@@ -564,7 +671,7 @@ def main():
                                       args.seed + 11, planes_only=args.serve_store == "planes")
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample)")
-        line["cpu_baseline"] = cpu_baseline(cfg, params, server_items, args.seed)
+        line["cpu_baseline"] = cpu_baseline(cfg, params, server_items, args.seed, line["batches_computed"])
     print(json.dumps(line), flush=True)
 
 

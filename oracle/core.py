@@ -61,6 +61,7 @@ def lib():
             "or_chacha20_block": (None, [u32p, C.c_uint32, u32p, u32p]),
             "or_expand_uniform": (None, [vp, C.c_char_p, i, i, u64p, C.c_size_t]),
             "or_mod_switch": (None, [vp, u64p, u64p]),
+            "or_num_threads": (i, []),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -263,3 +264,8 @@ def chacha20_block(key_words, counter: int, nonce_words):
     out = np.zeros(16, dtype=np.uint32)
     lib().or_chacha20_block(_c(key_words, np.uint32), counter, _c(nonce_words, np.uint32), out)
     return out
+
+
+def num_threads() -> int:
+    """Threads the oracle's parallel regions use (OpenMP)."""
+    return int(lib().or_num_threads())

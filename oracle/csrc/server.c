@@ -173,3 +173,7 @@ void or_server_eval(const or_ctx* c, int ell, int h, int mu_begin, int mu_end,
     }
   }
 }
+
+/* threads an OpenMP region of the oracle uses (reported beside its timings) */
+#include <omp.h>
+int or_num_threads(void) { return omp_get_max_threads(); }

@@ -599,7 +599,7 @@ struct Engine {
   // stay off, which is an error if the server holds its plaintexts only as planes (required).
   int enable_planes(bool required) {
     planes_on = false;
-    if (P->H.ell > PL_MAX_ELL) return 0;
+    if (!planes_supported(P->H.ell)) return 0;
     const size_t need = (size_t)Qmax * cpstride();
     if (need > cplanes.cap) {
       size_t free_b = 0, total_b = 0;
@@ -668,14 +668,17 @@ struct Engine {
   // Select-and-sum of one tile: batches [b0, b0 + nb) of nq active queries (slots qslot[0..nq), or
   // single_slot when nq == 1) into Sout [nb * nq][2][L][N]; plaintexts from the cache (pv) or
   // generated.
-  void produce_s(const uint16_t* cw, int b0, int nb, int nq, const int* qslot, int single_slot,
-                 const PtView& pv, uint64_t* Sout, hipStream_t s) {
+  int produce_s(const uint16_t* cw, int b0, int nb, int nq, const int* qslot, int single_slot,
+                const PtView& pv, uint64_t* Sout, hipStream_t s) {
     const HostParams& H = P->H;
     const size_t n = H.n, L = H.L;
     if (pv.p || (pv.planes && planes_on)) {
       timed_select_sum(pv, nb, nq, qslot, single_slot, Sout, s);
-      return;
+      return 0;
     }
+    // a tile the resident plaintexts do not cover needs the generation buffers of setup()
+    if (GB <= 0 || !gen_poly.p || !gen_p.p)
+      return fail(PEPSI_E_ARG, "batches [%d, %d) are neither resident nor generable by this workspace", b0, b0 + nb);
     for (int g0 = 0; g0 < nb; g0 += GB) {
       const int g = std::min(GB, nb - g0);
       encode_server_planes(P->T, H.logn, cw, H.h, H.ell, b0 + g0, g, gen_poly.as<uint32_t>(), s);
@@ -688,6 +691,7 @@ struct Engine {
       gv.gs = GB;
       timed_select_sum(gv, g, nq, qslot, single_slot, Sout + (size_t)g0 * nq * 2 * L * n, s);
     }
+    return 0;
   }
 
   // The product tree of one tile from its select-and-sum outputs Sin, and the accumulation.
@@ -755,10 +759,12 @@ struct Engine {
   }
 
   // One tile on one stream.
-  void run_tile(const uint16_t* cw, int b0, int nb, int nq, const int* qslot, int single_slot,
-                const PtView& pv, hipStream_t s) {
-    produce_s(cw, b0, nb, nq, qslot, single_slot, pv, sq.as<uint64_t>(), s);
+  int run_tile(const uint16_t* cw, int b0, int nb, int nq, const int* qslot, int single_slot,
+               const PtView& pv, hipStream_t s) {
+    int rc = produce_s(cw, b0, nb, nq, qslot, single_slot, pv, sq.as<uint64_t>(), s);
+    if (rc) return rc;
     consume_s(sq.as<uint64_t>(), b0, nb, nq, qslot, single_slot, s);
+    return 0;
   }
 
   // out = coefficient form of query q's sum, optionally times (h!)^-1 plus Delta [encode(mask)]_t
@@ -816,8 +822,9 @@ struct Engine {
     for (int q = 0; q < nq; ++q) admit(q, cts[q], rlk[q], s);
     for (uint32_t b0 = begin; b0 < stop; b0 += TBq) {
       const int nb = (int)std::min<uint32_t>(TBq, stop - b0);
-      run_tile(cw, (int)b0, nb, nq, nullptr, 0,
-               cached_tile(cache, cached, b0, nb, planes, group_bytes, plane_batches), s);
+      const int rc = run_tile(cw, (int)b0, nb, nq, nullptr, 0,
+                              cached_tile(cache, cached, b0, nb, planes, group_bytes, plane_batches), s);
+      if (rc) return rc;
     }
     return 0;
   }
@@ -937,7 +944,7 @@ extern "C" int pepsi_server_create_ex(const pepsi_params* Pc, const uint32_t* it
     if (hipStreamSynchronize(s) != hipSuccess) { delete sv; return fail(PEPSI_E_DEVICE, "value encoding failed"); }
     sv->valued = true;
   }
-  if ((flags & PEPSI_SERVER_PLANES_ONLY) && max_load > 0 && H.ell <= PL_MAX_ELL) {
+  if ((flags & PEPSI_SERVER_PLANES_ONLY) && max_load > 0 && planes_supported(H.ell)) {
     // digit planes only, as many 16-batch groups as fit beside the working reserve (and the
     // one-group staging store they are generated in)
     const size_t gb = plaintext_plane_group_bytes(H.consts, H.ell);
@@ -1011,7 +1018,7 @@ extern "C" int pepsi_server_create_ex(const pepsi_params* Pc, const uint32_t* it
       // digit planes of the cached groups for the batched path, when they fit beside the reserve
       const uint32_t groups = (nc + PT_GROUP - 1) / PT_GROUP;
       const size_t gb = plaintext_plane_group_bytes(H.consts, H.ell);
-      if (gs == PT_GROUP && H.ell <= PL_MAX_ELL) {
+      if (gs == PT_GROUP && planes_supported(H.ell)) {
         if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) { delete sv; return fail(PEPSI_E_DEVICE, "hipMemGetInfo failed"); }
         if (free_b > reserve && (free_b - reserve) / gb >= groups) {
           if ((rc = sv->planes.ensure(gb * groups))) { delete sv; return rc; }
@@ -1123,12 +1130,15 @@ extern "C" int pepsi_server_eval_batch(pepsi_server* sv, uint32_t nq, const uint
       for (int cand : {64, 32})
         if (free_b > fixed + (size_t)cand * nq * engine_pair_bytes(H)) { tb = cand; break; }
     }
+    // the workspace counts as set up only once every part of it is (a failed call leaves
+    // bqmax at 0, so the next call sets it up again instead of running on a partial one)
+    sv->bqmax = 0;
     int rc = sv->beng.setup(sv->P, std::min<int>(tb, std::max<int>(1, (int)sv->max_load)), (int)nq,
                             sv->need_gen_multi(), sv->values_hat());
     if (rc) return rc;
     sv->beng.timer = &sv->timer;
-    sv->bqmax = (int)nq;
     if (sv->plane_groups > 0 && (rc = sv->beng.enable_planes(sv->planes_only))) return rc;
+    sv->bqmax = (int)nq;
   }
   Engine& E = sv->beng;
   hipEvent_t ea = nullptr, eb = nullptr;
@@ -1245,10 +1255,13 @@ struct pepsi_serve {
         }
         const uint32_t b0 = (uint32_t)cursor * eng.TBq;
         const int nb = (int)std::min<uint32_t>(eng.TBq, stop_b - b0);
-        eng.run_tile(sv->cw.as<uint16_t>(), (int)b0, nb, na, qslot_dev.as<int>(), live[0],
-                     Engine::cached_tile(sv->cached ? sv->cache.as<uint64_t>() : nullptr, sv->cached_batches, b0,
-                                         nb, sv->planes_p(), sv->plane_group_bytes, sv->plane_batches),
-                     stream);
+        if (eng.run_tile(sv->cw.as<uint16_t>(), (int)b0, nb, na, qslot_dev.as<int>(), live[0],
+                         Engine::cached_tile(sv->cached ? sv->cache.as<uint64_t>() : nullptr, sv->cached_batches,
+                                             b0, nb, sv->planes_p(), sv->plane_group_bytes, sv->plane_batches),
+                         stream)) {
+          fail_all(g_err.c_str());
+          return;
+        }
         cursor = (cursor + 1) % T;
         ++steps;
       }

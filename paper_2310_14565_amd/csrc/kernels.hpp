@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include "params.hpp"
+#include "planes.hpp"
 
 namespace pepsi {
 
@@ -126,7 +127,6 @@ void select_sum_multi(const Tables& T, const Consts& hc, const uint64_t* Cq, lon
 // int8, query q's at Cp + qslot[q] * cps.  A tile is nb <= 64 batches: the group at Pp and the
 // ones after it.  Valid for ell <= PL_MAX_ELL (exact int32 and 64-bit sums); rows
 // b >= nb of a group are read but not written.
-constexpr int PL_DG = 7, PL_K = 64, PL_MAX_ELL = 4096;
 inline int plane_kblocks(int ell) { return (ell + PL_K - 1) / PL_K; }
 size_t plaintext_plane_group_bytes(const Consts& hc, int ell);
 size_t request_plane_bytes(const Consts& hc, int ell);

@@ -778,16 +778,6 @@ __global__ void __launch_bounds__(MTPB) k_select_sum_multi(Tables T, const uint6
 // four weights (|V_g| < 2^53 <= q_l for ell <= PL_MAX_ELL), each brought into [0, 2 q_l) and
 // multiplied by 2^(32 g) mod q_l, with one reduction of the 128-bit total.
 typedef int v4i __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ void balanced_digits(uint64_t x, int8_t (&d)[PL_DG]) {
-#pragma unroll
-  for (int i = 0; i < PL_DG - 1; ++i) {
-    int v = (int)(x & 255);
-    v -= v >= 128 ? 256 : 0;
-    d[i] = (int8_t)v;
-    x = (x - (uint64_t)(int64_t)v) >> 8;
-  }
-  d[PL_DG - 1] = (int8_t)x;     // below 65 for x < 2^54
-}
 // Plaintext planes of one group of 16 batches of a cache store (group size gs = 16), layout
 // [l][k][kb][digit][batch][64].  Wave = one (l, k, kb); lane = (batch, 16-position quarter).
 __global__ void __launch_bounds__(TPB) k_plaintext_planes(Tables T, const uint64_t* __restrict__ Pc, int gs,
@@ -908,21 +898,16 @@ __global__ void __launch_bounds__(TPB) k_select_sum_planes(Tables T, const int8_
   }
   if (!live) return;
   const Prime& pr = C.prm[l];
-  const uint64_t p = pr.p;
-  const uint64_t wgt[4] = {1, 1ull << 32, pr.r64, mulmod(pr.r64, 1ull << 32, pr)};   // 2^(32 g) mod p
+  uint64_t wgt[4];
+  plane_group_weights(pr, wgt);
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int b = 16 * half + 4 * g4 + i;   // output row of this lane
     if (b >= nb) continue;
-    u128 tot = 0;
+    int32_t Ts[PL_WEIGHTS];
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      int64_t V = 0;
-#pragma unroll
-      for (int s2 = 4 * g; s2 < 4 * g + 4 && s2 < 2 * PL_DG - 1; ++s2) V += (int64_t)acc[s2][i] << (8 * (s2 - 4 * g));
-      tot += (u128)(uint64_t)(V + (int64_t)p) * wgt[g];
-    }
-    S[(((size_t)b * nq + q) * 2 + c) * L * N + (size_t)l * N + k] = reduce128((uint64_t)tot, (uint64_t)(tot >> 64), pr);
+    for (int s2 = 0; s2 < PL_WEIGHTS; ++s2) Ts[s2] = acc[s2][i];
+    S[(((size_t)b * nq + q) * 2 + c) * L * N + (size_t)l * N + k] = plane_recombine(Ts, pr, wgt);
   }
 }
 

@@ -73,3 +73,32 @@ def test_batch_equals_alone(h, nq, cache, n_server):
     _, _, spos, _ = PR.server_prepare(cfg, server)
     want = ctx.server_eval(qs[-1]["cts"], spos, qs[-1]["rlk"], h, mask=qs[-1]["mask"])
     assert (got[-1] == want).all()
+
+
+def test_code_length_beyond_planes_limit():
+    """h = 1 over 13-bit items gives ell = 8192, beyond the 4096 positions for which the int8
+    digit-plane contraction is exact: the server keeps no digit planes even when asked for them
+    only, and the batched path runs on the 64-bit kernels with the same results."""
+    import paper_2310_14565_amd as pk
+    log_n, L, h, bits, n_server = 10, 2, 1, 13, 200
+    n = 1 << log_n
+    mu = P.server_bin_bound(n_server, n)
+    cfg = PR.Config(n=n, L=L, h=h, item_bits=bits, mu=mu)
+    gp = pk.Params(log_n, L, h, bits, mu, hash_seed=cfg.hash_seed)
+    assert gp.ell == cfg.ell == 8192
+    ctx = Context(n, gp.q_primes)
+    server = W.server_items(n_server, bits, 77)
+    sv = pk.Server(gp, server, cache_plaintexts=True, planes_only=True)
+    assert sv.plane_groups == 0 and sv.cached_batches == sv.max_load
+    qs = make_queries(ctx, cfg, server, 2, 8080)
+    d_cts = [to_dev(q["cts"]) for q in qs]
+    d_rlk = [to_dev(q["rlk"]) for q in qs]
+    d_mask = [None if q["mask"] is None else to_dev(q["mask"]) for q in qs]
+    outs = [empty((2, L, n), np.uint64) for _ in qs]
+    sv.eval_batch(d_cts, d_rlk, d_mask, outs)
+    _, _, spos, _ = PR.server_prepare(cfg, server)
+    for i, q in enumerate(qs):
+        got = to_host(outs[i], np.uint64)
+        want = ctx.server_eval(q["cts"], spos, q["rlk"], h, mask=q["mask"])
+        assert (got == want).all(), f"query {i}"
+    sv.close()

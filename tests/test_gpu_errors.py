@@ -111,3 +111,61 @@ def test_modulus_too_small_is_reported():
     assert ctx.noise_budget(sk, got) <= 0
     assert gp.noise_budget(to_dev(W.secret_key(n, 9)), out) <= 0
     assert PR.extract_cardinality(ctx.decrypt_slots(sk, got)) != 12
+
+
+def test_batched_setup_failure_is_retried():
+    """A planes-only server whose request planes cannot be allocated: the batched evaluation
+    fails with PEPSI_E_NOMEM, a retry fails the same way (it sets the workspace up again
+    instead of running on a partial one), and once memory is free again it succeeds and equals
+    the single-query result.  Device memory is filled from the host with torch tensors."""
+    import torch
+    import paper_2310_14565_amd as pk
+    from gpu_util import say
+    from test_gpu_batch import make_queries
+    log_n, L, h, bits, n_server = 10, 3, 2, 16, 12000
+    n = 1 << log_n
+    mu = P.server_bin_bound(n_server, n)
+    cfg = PR.Config(n=n, L=L, h=h, item_bits=bits, mu=mu)
+    gp = pk.Params(log_n, L, h, bits, mu, hash_seed=cfg.hash_seed)
+    ctx = Context(n, gp.q_primes)
+    server = W.server_items(n_server, bits, 41)
+    sv = pk.Server(gp, server, cache_plaintexts=True, planes_only=True)
+    assert sv.plane_groups * 16 >= sv.max_load and sv.cached_batches == 0
+    qs = make_queries(ctx, cfg, server, 3, 4242)
+    cts = [to_dev(q["cts"]) for q in qs]
+    rlk = [to_dev(q["rlk"]) for q in qs]
+    masks = [None if q["mask"] is None else to_dev(q["mask"]) for q in qs]
+    alone = []
+    for i in range(3):
+        o = empty((2, L, n), np.uint64)
+        sv.eval(cts[i], rlk[i], masks[i], o)
+        alone.append(to_host(o, np.uint64))
+    outs = [empty((2, L, n), np.uint64) for _ in qs]
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    fill = []
+    chunk = 8 << 30
+    while True:
+        free, _ = torch.cuda.mem_get_info()
+        if free < (3 << 29):
+            break
+        want = min(chunk, free - (1 << 30))
+        if want < (64 << 20):
+            break
+        try:
+            fill.append(torch.empty(want, dtype=torch.uint8, device="cuda"))
+        except torch.OutOfMemoryError:
+            chunk //= 2
+            if chunk < (64 << 20):
+                break
+    say(f"filled {sum(t.numel() for t in fill) >> 30} GiB, {torch.cuda.mem_get_info()[0] >> 20} MiB free")
+    try:
+        for attempt in range(2):
+            assert _code(lambda: sv.eval_batch(cts, rlk, masks, outs)) == E_NOMEM, f"attempt {attempt}"
+    finally:
+        del fill
+        torch.cuda.empty_cache()
+    sv.eval_batch(cts, rlk, masks, outs)
+    for i in range(3):
+        assert (to_host(outs[i], np.uint64) == alone[i]).all(), f"query {i}"
+    sv.close()

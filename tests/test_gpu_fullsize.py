@@ -18,11 +18,13 @@ pytestmark = pytest.mark.gpu
 
 CASES = {
     # Paper-shaped query (n = 2^20, m = 1024), plaintexts resident as in the benchmark.
+    # The range starts inside a 16-batch group of the plaintext store and its launch spans three
+    # batch groups of the select-and-sum, the last one partial.
     "paper": dict(log_n=13, L=4, h=4, bits=32, mu=526, n=1 << 20, m=1024, planted=256, cache=True,
-                  samples=(0, 233, -1), chunk=50),
+                  samples=(0, 233, -1), ranges=((216, 249),), chunk=50),
     # Large configuration (N = 16384, 8 primes, n = 2^24, m = 4096): plaintexts generated per tile.
     "large": dict(log_n=14, L=8, h=4, bits=32, mu=3487, n=1 << 24, m=4096, planted=1024, cache=False,
-                  samples=(-1,), chunk=800),
+                  samples=(-1,), ranges=(), chunk=800),
 }
 
 
@@ -44,7 +46,7 @@ def _add(a, b, primes):
 
 
 @pytest.mark.slow
-@pytest.mark.timeout(900)
+@pytest.mark.timeout(1000)
 @pytest.mark.parametrize("name", ["paper", "large"])
 def test_full_size(name, capsys):
     import torch
@@ -75,6 +77,12 @@ def test_full_size(name, capsys):
         _progress(capsys, f"{name}: oracle batch {b}")
         want = ctx.server_eval(cts, spos, rlk, c["h"], finalize=False, begin=b, end=b + 1)
         assert (got == want).all(), f"batch {b}"
+    for b0, b1 in c["ranges"]:
+        sv.eval_range(d_cts, d_rlk, b0, b1, False, None, out)
+        got = to_host(out, np.uint64).copy()
+        _progress(capsys, f"{name}: oracle batches [{b0}, {b1})")
+        want = ctx.server_eval(cts, spos, rlk, c["h"], finalize=False, begin=b0, end=b1)
+        assert (got == want).all(), f"batches [{b0}, {b1})"
 
     # the whole range in the normal tiles equals the sum of chunked ranges
     _progress(capsys, f"{name}: whole range vs chunks")
@@ -99,17 +107,21 @@ def test_full_size(name, capsys):
     _progress(capsys, f"{name}: cardinality {card}, noise budget {budget} bits")
     assert card == c["planted"] and budget > 0
 
+    # the batched path at full size: each query's result equals its single-query result
+    q2 = bench.make_query(gp, items, {"item_bits": c["bits"]}, c["m"] // 2, c["planted"] // 2, 35)
+    alone2 = torch.zeros_like(res)
+    sv.eval(q2["cts"], q2["rlk"], q2["mask"], alone2)
+    qs = [q, q2, q]
+    outs = [torch.zeros_like(res) for _ in qs]
     if c["cache"]:
-        # the batched path at full size: digit planes of every cached group, tiles of up to 64
-        # batches on the matrix cores; each query's result equals its single-query result
+        # digit planes of every cached group, tiles of up to 64 batches on the matrix cores
         assert sv.plane_groups == -(-sv.cached_batches // 16) > 0
-        q2 = bench.make_query(gp, items, {"item_bits": c["bits"]}, c["m"] // 2, c["planted"] // 2, 35)
-        alone2 = torch.zeros_like(res)
-        sv.eval(q2["cts"], q2["rlk"], q2["mask"], alone2)
-        qs = [q, q2, q]
-        outs = [torch.zeros_like(res) for _ in qs]
-        _progress(capsys, f"{name}: batched path, {len(qs)} queries")
-        sv.eval_batch([x["cts"] for x in qs], [x["rlk"] for x in qs], [x["mask"] for x in qs], outs)
-        torch.cuda.synchronize()
-        assert torch.equal(outs[0], res) and torch.equal(outs[2], res) and torch.equal(outs[1], alone2)
+    else:
+        # plaintexts generated per 16-batch tile, shared by the queries of the batch
+        assert sv.plane_groups == 0 and sv.cached_batches == 0
+    _progress(capsys, f"{name}: batched path, {len(qs)} queries")
+    sv.eval_batch([x["cts"] for x in qs], [x["rlk"] for x in qs], [x["mask"] for x in qs], outs)
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], res) and torch.equal(outs[2], res) and torch.equal(outs[1], alone2)
     sv.close()
+

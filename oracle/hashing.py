@@ -77,8 +77,9 @@ def pbh_place(x: int, i: int, seed: int, n_bins: int, lam: int):
 
 def cuckoo_table(items, n_bins: int, seed: int, n_hash: int = 3, max_evictions: int = 500,
                  pbh_bits: int | None = None):
-    """Client table T_c (gamma = 1): returns (table uint32[b], valid uint8[b]).  With pbh_bits
-    (the element length lambda) the table holds PBH values instead of the elements."""
+    """Client table T_c (gamma = 1): returns (table uint32[b], valid uint8[b]; uint64 once a value
+    exceeds 32 bits).  With pbh_bits (the element length lambda) the table holds PBH values
+    instead of the elements."""
     items = [int(x) for x in items]
     if len(set(items)) != len(items):
         raise ValueError("duplicate client items")
@@ -101,18 +102,24 @@ def cuckoo_table(items, n_bins: int, seed: int, n_hash: int = 3, max_evictions: 
             evictions += 1
             if evictions > max_evictions:
                 raise CuckooFailure(f"eviction limit {max_evictions} reached")
-    out = np.zeros(n_bins, dtype=np.uint32)
+    stored = [0] * n_bins
     valid = np.zeros(n_bins, dtype=np.uint8)
     for k, v in enumerate(table):
         if v is not None:
-            out[k] = pbh_place(v, which[k], seed, n_bins, pbh_bits)[1] if pbh_bits else v
+            stored[k] = pbh_place(v, which[k], seed, n_bins, pbh_bits)[1] if pbh_bits else v
             valid[k] = 1
-    return out, valid
+    return np.array(stored, dtype=_value_dtype(max(stored, default=0))), valid
+
+
+def _value_dtype(largest: int):
+    """uint32 tables for values of up to 32 bits (the 32-bit elements), uint64 beyond."""
+    return np.uint32 if largest < (1 << 32) else np.uint64
 
 
 def simple_table(items: np.ndarray, n_bins: int, mu: int, seed: int, n_hash: int = 3,
                  pbh_bits: int | None = None, with_index: bool = False):
-    """Server table T_s: returns (table uint32[mu][b], valid uint8[mu][b], max_load), and with
+    """Server table T_s: returns (table uint32[mu][b] (uint64 once a value exceeds 32 bits),
+    valid uint8[mu][b], max_load), and with
     with_index also the element's input position per entry (int64[mu][b], -1 for dummies).
 
     Entry (i', k) is the i'-th element appended to bin k, in input order.  With pbh_bits the
@@ -149,9 +156,10 @@ def simple_table(items: np.ndarray, n_bins: int, mu: int, seed: int, n_hash: int
         raise BinOverflow(f"server bin load {max_load} exceeds mu={mu}")
     starts = np.concatenate([[0], np.cumsum(counts)[:-1]])
     rank = np.arange(sel_bin.shape[0]) - starts[sel_bin]
-    table = np.zeros((mu, n_bins), dtype=np.uint32)
+    dt = _value_dtype(int(sel_val.max()) if sel_val.size else 0)
+    table = np.zeros((mu, n_bins), dtype=dt)
     valid = np.zeros((mu, n_bins), dtype=np.uint8)
-    table[rank, sel_bin] = sel_val.astype(np.uint32)
+    table[rank, sel_bin] = sel_val.astype(dt)
     valid[rank, sel_bin] = 1
     if with_index:
         index = np.full((mu, n_bins), -1, dtype=np.int64)

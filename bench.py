@@ -482,6 +482,87 @@ def large_leg(pk, steps, nq, seed):
     }
 
 
+# Large elements (Table "psisum-eval": PSI-Sum, b = 16384, n = 2^20, mu = 296, m = 1024): 32-byte
+# strings hashed to lambda = 40 + ceil(log2(b mu)) = 63 bits, permutation-based hashing (stored
+# values of 51 bits with the hash index), h = 16 (N = 2^14 from Table "mod-per-hamming-weight"),
+# 5 primes (270 bits against the table's 240), 12-bit server values.
+LARGE_ELEMENTS = dict(log_n=14, L=5, h=16, mu=296, n_server=1 << 20, m_client=1024, planted=256, length=32)
+
+
+def large_elements_leg(pk, steps, seed):
+    """PSI-Sum over large elements at the shape of Table "psisum-eval" (n = 2^20)."""
+    import torch
+    import workload as W
+    c = LARGE_ELEMENTS
+    n, L = 1 << c["log_n"], c["L"]
+    lam = pk.large_element_bits(n, 1, c["mu"])
+    params = pk.Params(c["log_n"], L, c["h"], lam, c["mu"], pbh=True)
+    server_e = W.byte_elements(c["n_server"], c["length"], seed)
+    t0 = time.perf_counter()
+    hs = pk.hash_elements(server_e, lam)
+    t_hash = time.perf_counter() - t0
+    values = W.item_values(c["n_server"], 0, 1 << 12, seed + 1)
+    t0 = time.perf_counter()
+    server = pk.Server(params, hs, cache_plaintexts=True, values=values)
+    torch.cuda.synchronize()
+    prep = time.perf_counter() - t0
+    g = W.rng(seed, "large-elements-client")
+    common = np.sort(g.choice(c["n_server"], size=c["planted"], replace=False))
+    fresh = W.byte_elements(c["m_client"] - c["planted"], c["length"], seed + 2, tag="client-elements")
+    client_e = np.concatenate([server_e[common], fresh])[g.permutation(c["m_client"])]
+    hc = pk.hash_elements(client_e, lam)
+    table, valid = params.client_table(hc)
+    planes = params.codeword_planes(table, valid)
+    ell = params.ell
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed + 3)
+    sk = dev(W.secret_key(n, seed + 4))
+    a = torch.stack([torch.randint(0, q, (ell, n), generator=gen, device="cuda", dtype=torch.int64)
+                     for q in params.q_primes], dim=1).contiguous()
+    e = torch.clamp(torch.round(torch.randn((ell, n), generator=gen, device="cuda") * 3.2), -19, 19).to(torch.int32)
+    cts = torch.empty((ell, 2, L, n), dtype=torch.int64, device="cuda")
+    params.encrypt(sk, dev(planes), a, e, cts)
+    ka = torch.stack([torch.randint(0, q, (L, n), generator=gen, device="cuda", dtype=torch.int64)
+                      for q in params.q_primes], dim=1).contiguous()
+    ke = torch.clamp(torch.round(torch.randn((L, n), generator=gen, device="cuda") * 3.2), -19, 19).to(torch.int32)
+    rlk = torch.empty((L, 2, L, n), dtype=torch.int64, device="cuda")
+    params.keygen_relin(sk, ka, ke, rlk)
+    mask = dev(W.zero_sum_mask(n, 65537, seed + 5))
+    out = torch.zeros((2, L, n), dtype=torch.int64, device="cuda")
+    server.eval(cts, rlk, mask, out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        server.eval(cts, rlk, mask, out)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    slots = torch.zeros((1, n), dtype=torch.int32, device="cuda")
+    params.decrypt(sk, out.reshape(1, 2, L, n), slots)
+    torch.cuda.synchronize()
+    got = int(slots.cpu().numpy().view(np.uint32).astype(np.int64).sum() % 65537)
+    want = int(values[common].astype(np.int64).sum() % 65537)
+    budget = params.noise_budget(sk, out)
+    max_load = int(server.max_load)
+    server.close()
+    if got != want or budget <= 0:
+        log(f"[bench] WRONG PSI-Sum over large elements: {got} (want {want}), budget {budget}")
+        sys.exit(1)
+    return {
+        "workload": (f"PSI-Sum over {c['length']}-byte elements: N=b={n} L={L} h={c['h']} lambda={lam} "
+                     f"(PBH, stored {params.effective_bits} bits) ell={ell} n=2^20 mu={c['mu']} m={c['m_client']} "
+                     f"planted={c['planted']}, 12-bit values, plaintexts cached"),
+        "ms_per_query": round(1e3 * t, 3),
+        "value": round(n * c["mu"] / t, 1),
+        "unit": "slot-comparisons/s",
+        "steps": steps,
+        "batches_computed": max_load,
+        "hash_s": round(t_hash, 3),
+        "offline_s": round(prep, 3),
+        "paper_online_s": 7.0,
+        "check": {"sum_mod_t": got, "noise_budget_bits": budget},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -500,6 +581,8 @@ def main():
     ap.add_argument("--large-steps", type=int, default=2,
                     help="single queries timed in the large-configuration leg (0: skip the leg)")
     ap.add_argument("--large-batch", type=int, default=4, help="queries of the large leg's batch")
+    ap.add_argument("--large-elements-steps", type=int, default=3,
+                    help="steps of the PSI-Sum leg over large (hashed 32-byte) elements (0: skip it)")
     ap.add_argument("--serve", type=int, default=500, help="requests in the serving leg (0: skip it)")
     ap.add_argument("--serve-pool", type=int, default=16, help="distinct client queries behind the requests")
     ap.add_argument("--serve-slots", type=int, default=64)
@@ -659,6 +742,10 @@ def main():
     if args.paper32_steps > 0 and args.config == "paper":
         server.close()
         line["paper32"] = paper32_leg(pk, args.paper32_steps, args.seed + 13)
+    if args.large_elements_steps > 0 and args.config == "paper":
+        server.close()
+        torch.cuda.empty_cache()
+        line["large_elements"] = large_elements_leg(pk, args.large_elements_steps, args.seed + 23)
     if args.large_steps > 0 and args.config == "paper":
         server.close()
         torch.cuda.empty_cache()

@@ -73,7 +73,8 @@ typedef struct {
   uint32_t log_n;          /* N = 2^log_n = number of bins b; 10..14                   */
   uint32_t n_q;            /* L, number of ciphertext primes; 1..8                     */
   uint32_t h;              /* Hamming weight of the constant-weight code; 1..16        */
-  uint32_t item_bits;      /* element bit length lambda; 1..32                         */
+  uint32_t item_bits;      /* element bit length lambda; 1..64 (values above 32 bits:
+                              large elements hashed to lambda bits, with the *64 calls) */
   uint32_t mu;             /* server maximum bin load                                  */
   uint32_t n_hash;         /* number of hash functions k (3 in the paper)             */
   uint32_t max_evictions;  /* cuckoo eviction limit per insertion                     */
@@ -139,6 +140,32 @@ int pepsi_client_table(const pepsi_params* params, const uint32_t* items, uint64
  * ell client plaintexts pt_c[j]. */
 int pepsi_codeword_planes(const pepsi_params* params, const uint32_t* table,
                           const uint8_t* valid, uint32_t* planes);
+
+/* The same for elements and stored values of up to 64 bits (item_bits > 32, or stored PBH
+ * values above 32 bits): items uint64 [m], table uint64 [N].  The 32-bit calls above reject
+ * parameters whose stored values exceed 32 bits (PEPSI_E_ARG). */
+int pepsi_client_table64(const pepsi_params* params, const uint64_t* items, uint64_t m,
+                         uint64_t* table, uint8_t* valid);
+int pepsi_codeword_planes64(const pepsi_params* params, const uint64_t* table,
+                            const uint8_t* valid, uint32_t* planes);
+
+/* ------------------------------------------------------------------ */
+/* Large elements (Sec. 5, "Optimization for Large Elements", Lemma    */
+/* "fail-collide"; Sec. 7, "Parameters for Large Elements"), host      */
+/* ------------------------------------------------------------------ */
+/* Element length for a failure rate below 2^-alpha: unequal elements hashed to lambda bits
+ * match only if they collide and share a bin, and at most n_bins * mu_client * mu_server pairs
+ * are compared, so *bits = lambda = alpha + ceil(log2(n_bins mu_client mu_server)) (alpha = 40
+ * and mu_client = 1 in the paper's runs).  Needs no device.  Errors: PEPSI_E_ARG (a zero size). */
+int pepsi_large_element_bits(uint32_t n_bins, uint32_t mu_client, uint32_t mu_server, uint32_t alpha,
+                             uint32_t* bits);
+/* Hashes count byte strings (element e is data[offsets[e] .. offsets[e + 1]), offsets has
+ * count + 1 entries) to bits-bit values, 1 <= bits <= 64: out[e] = the first `bits` bits of
+ * SHA-256 (FIPS 180-4) of the element, read big-endian (the paper names no hash function).  The
+ * values are then the elements of pepsi_client_table64 / pepsi_server_create64 with
+ * item_bits = bits.  Host memory; needs no device.  Errors: PEPSI_E_ARG. */
+int pepsi_hash_elements(uint32_t bits, const uint8_t* data, const uint64_t* offsets, uint64_t count,
+                        uint64_t* out);
 
 /* ------------------------------------------------------------------ */
 /* Keys, encryption, decryption (FV, Sec. 3.1), device memory          */
@@ -237,6 +264,11 @@ int pepsi_server_create_with_values(const pepsi_params* params, const uint32_t* 
 int pepsi_server_create_ex(const pepsi_params* params, const uint32_t* items, const uint32_t* values,
                            uint64_t n, uint32_t flags, uint32_t max_cached, void* stream,
                            pepsi_server** out);
+/* Server preparation for elements of up to 64 bits (large elements hashed with
+ * pepsi_hash_elements): as pepsi_server_create_ex with items uint64 [n]. */
+int pepsi_server_create64(const pepsi_params* params, const uint64_t* items, const uint32_t* values,
+                          uint64_t n, uint32_t flags, uint32_t max_cached, void* stream,
+                          pepsi_server** out);
 int pepsi_server_get_info(const pepsi_server* server, pepsi_server_info* out);
 /* Copy of the codeword-position table uint16 [mu][N][h] to host memory. */
 int pepsi_server_codewords(const pepsi_server* server, uint16_t* out);

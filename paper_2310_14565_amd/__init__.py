@@ -75,6 +75,13 @@ _SIGS = {
     "pepsi_exact_path_count": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint64)]),
     "pepsi_client_table": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p]),
     "pepsi_codeword_planes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pepsi_client_table64": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p]),
+    "pepsi_codeword_planes64": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pepsi_large_element_bits": (C.c_int, [C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
+                                           C.POINTER(C.c_uint32)]),
+    "pepsi_hash_elements": (C.c_int, [C.c_uint32, C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p]),
+    "pepsi_server_create64": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_uint32,
+                                        C.c_uint32, C.c_void_p, C.POINTER(C.c_void_p)]),
     "pepsi_encrypt": (C.c_int, [C.c_void_p] * 5 + [C.c_uint32, C.c_void_p, C.c_void_p]),
     "pepsi_keygen_relin": (C.c_int, [C.c_void_p] * 6),
     "pepsi_decrypt": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]),
@@ -202,18 +209,28 @@ class Params:
         _check(lib().pepsi_exact_path_count(self._h, C.byref(v)))
         return int(v.value)
 
+    @property
+    def wide(self) -> bool:
+        """Elements or stored values above 32 bits: the 64-bit client and server calls."""
+        return self.info.item_bits > 32 or self.effective_bits > 32
+
     # client preparation (host numpy)
     def client_table(self, items: np.ndarray):
-        items = np.ascontiguousarray(items, dtype=np.uint32)
-        table = np.zeros(self.n, np.uint32)
+        """Cuckoo table of the client's elements: (table, valid); uint64 values for wide parameters."""
+        dt = np.uint64 if self.wide else np.uint32
+        items = np.ascontiguousarray(items, dtype=dt)
+        table = np.zeros(self.n, dt)
         valid = np.zeros(self.n, np.uint8)
-        _check(lib().pepsi_client_table(self._h, _host(items), items.shape[0], _host(table), _host(valid)))
+        f = lib().pepsi_client_table64 if self.wide else lib().pepsi_client_table
+        _check(f(self._h, _host(items), items.shape[0], _host(table), _host(valid)))
         return table, valid
 
     def codeword_planes(self, table: np.ndarray, valid: np.ndarray):
         planes = np.zeros((self.ell, self.n), np.uint32)
-        _check(lib().pepsi_codeword_planes(self._h, _host(np.ascontiguousarray(table, np.uint32)),
-                                           _host(np.ascontiguousarray(valid, np.uint8)), _host(planes)))
+        dt = np.uint64 if self.wide else np.uint32
+        f = lib().pepsi_codeword_planes64 if self.wide else lib().pepsi_codeword_planes
+        _check(f(self._h, _host(np.ascontiguousarray(table, dt)), _host(np.ascontiguousarray(valid, np.uint8)),
+                 _host(planes)))
         return planes
 
     # device operations (torch tensors)
@@ -278,7 +295,8 @@ class Server:
         """values (one per item, < t) make every evaluation PSI-Sum (with a mask) or labelled
         PSI (without); None is PSI-cardinality / the indicator.  max_cached bounds the cached
         batches (0: as many as fit); planes_only keeps the cache only as int8 digit planes."""
-        items = np.ascontiguousarray(items, dtype=np.uint32)
+        wide = params.wide
+        items = np.ascontiguousarray(items, dtype=np.uint64 if wide else np.uint32)
         h_ = C.c_void_p()
         flags = PEPSI_SERVER_CACHE_PLAINTEXTS if cache_plaintexts else 0
         if planes_only:
@@ -291,8 +309,9 @@ class Server:
             vp = _host(values)
         if not 0 <= max_cached < 2**32:
             raise ValueError("max_cached out of range")
-        _check(lib().pepsi_server_create_ex(params.handle, _host(items), vp, items.shape[0], flags, max_cached,
-                                            _stream(stream), C.byref(h_)))
+        create = lib().pepsi_server_create64 if wide else lib().pepsi_server_create_ex
+        _check(create(params.handle, _host(items), vp, items.shape[0], flags, max_cached, _stream(stream),
+                      C.byref(h_)))
         self._h = h_
         self.params = params
         info = ServerInfo()
@@ -339,6 +358,33 @@ class Server:
     def eval_range(self, cts, rlk, begin: int, end: int, finalize: bool, mask, out, stream=None):
         _check(lib().pepsi_server_eval_range(self._h, _dev(cts), _dev(rlk), begin, end,
                                              1 if finalize else 0, _dev(mask), _dev(out), _stream(stream)))
+
+
+def large_element_bits(n_bins: int, mu_client: int, mu_server: int, alpha: int = 40) -> int:
+    """lambda = alpha + ceil(log2(b mu_c mu_s)) (pepsi_large_element_bits)."""
+    v = C.c_uint32()
+    _check(lib().pepsi_large_element_bits(n_bins, mu_client, mu_server, alpha, C.byref(v)))
+    return int(v.value)
+
+
+def hash_elements(elements, bits: int) -> np.ndarray:
+    """Byte strings -> their first `bits` bits of SHA-256 (pepsi_hash_elements), uint64.  elements:
+    a list of bytes, or a uint8 [count][length] array of equal-length elements."""
+    if isinstance(elements, np.ndarray) and elements.ndim == 2 and elements.dtype == np.uint8:
+        count, length = elements.shape
+        data = np.ascontiguousarray(elements).reshape(-1)
+        offsets = np.arange(count + 1, dtype=np.uint64) * np.uint64(length)
+    else:
+        blobs = [bytes(e) for e in elements]
+        count = len(blobs)
+        offsets = np.zeros(count + 1, np.uint64)
+        offsets[1:] = np.cumsum([len(b) for b in blobs], dtype=np.uint64)
+        data = np.frombuffer(b"".join(blobs), dtype=np.uint8)
+    if data.size == 0:
+        data = np.zeros(1, np.uint8)
+    out = np.zeros(count, np.uint64)
+    _check(lib().pepsi_hash_elements(bits, _host(data), _host(offsets), count, _host(out)))
+    return out
 
 
 def clock() -> float:

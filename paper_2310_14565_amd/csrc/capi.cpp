@@ -238,13 +238,13 @@ extern "C" int pepsi_exact_path_count(const pepsi_params* P, uint64_t* out) {
 }
 
 // ------------------------------------------------------------------ client preparation
-extern "C" int pepsi_client_table(const pepsi_params* P, const uint32_t* items, uint64_t m,
-                                  uint32_t* table, uint8_t* valid) {
-  if (!P || (!items && m) || !table || !valid) return fail(PEPSI_E_ARG, "null argument");
+namespace {
+int client_table_impl(const pepsi_params* P, const uint64_t* items, uint64_t m, uint64_t* table, uint8_t* valid) {
   const HostParams& H = P->H;
-  std::unordered_set<uint32_t> seen;
+  std::unordered_set<uint64_t> seen;
+  seen.reserve(m * 2);
   for (uint64_t i = 0; i < m; ++i) {
-    if (H.item_bits < 32 && (items[i] >> H.item_bits)) return fail(PEPSI_E_RANGE, "item %llu out of range", (unsigned long long)i);
+    if (H.item_bits < 64 && (items[i] >> H.item_bits)) return fail(PEPSI_E_RANGE, "item %llu out of range", (unsigned long long)i);
     if (!seen.insert(items[i]).second) return fail(PEPSI_E_RANGE, "duplicate client item");
   }
   if (m > (uint64_t)H.n) return fail(PEPSI_E_CUCKOO, "more items than bins");
@@ -254,18 +254,71 @@ extern "C" int pepsi_client_table(const pepsi_params* P, const uint32_t* items, 
   return PEPSI_OK;
 }
 
-extern "C" int pepsi_codeword_planes(const pepsi_params* P, const uint32_t* table, const uint8_t* valid,
-                                     uint32_t* planes) {
-  if (!P || !table || !valid || !planes) return fail(PEPSI_E_ARG, "null argument");
+template <class V>
+int codeword_planes_impl(const pepsi_params* P, const V* table, const uint8_t* valid, uint32_t* planes) {
   const HostParams& H = P->H;
   CwEncoder enc(H.ell, H.h);
   memset(planes, 0, sizeof(uint32_t) * (size_t)H.ell * H.n);
   std::vector<uint16_t> pos(H.h);
   for (int k = 0; k < H.n; ++k) {
     if (!valid[k]) continue;
-    if (H.eff_bits < 32 && (table[k] >> H.eff_bits)) return fail(PEPSI_E_RANGE, "value out of range");
-    enc.encode(table[k], pos.data());
+    const uint64_t v = table[k];
+    if (H.eff_bits < 64 && (v >> H.eff_bits)) return fail(PEPSI_E_RANGE, "value out of range");
+    enc.encode(v, pos.data());
     for (int r = 0; r < H.h; ++r) planes[(size_t)pos[r] * H.n + k] = 1;
+  }
+  return PEPSI_OK;
+}
+}  // namespace
+
+extern "C" int pepsi_client_table(const pepsi_params* P, const uint32_t* items, uint64_t m,
+                                  uint32_t* table, uint8_t* valid) {
+  if (!P || (!items && m) || !table || !valid) return fail(PEPSI_E_ARG, "null argument");
+  if (P->H.eff_bits > 32) return fail(PEPSI_E_ARG, "stored values exceed 32 bits: use pepsi_client_table64");
+  std::vector<uint64_t> wide(items, items + m), t64(P->H.n);
+  const int rc = client_table_impl(P, wide.data(), m, t64.data(), valid);
+  if (rc) return rc;
+  for (int k = 0; k < P->H.n; ++k) table[k] = (uint32_t)t64[k];
+  return PEPSI_OK;
+}
+
+extern "C" int pepsi_client_table64(const pepsi_params* P, const uint64_t* items, uint64_t m, uint64_t* table,
+                                    uint8_t* valid) {
+  if (!P || (!items && m) || !table || !valid) return fail(PEPSI_E_ARG, "null argument");
+  return client_table_impl(P, items, m, table, valid);
+}
+
+extern "C" int pepsi_codeword_planes(const pepsi_params* P, const uint32_t* table, const uint8_t* valid,
+                                     uint32_t* planes) {
+  if (!P || !table || !valid || !planes) return fail(PEPSI_E_ARG, "null argument");
+  return codeword_planes_impl(P, table, valid, planes);
+}
+
+extern "C" int pepsi_codeword_planes64(const pepsi_params* P, const uint64_t* table, const uint8_t* valid,
+                                       uint32_t* planes) {
+  if (!P || !table || !valid || !planes) return fail(PEPSI_E_ARG, "null argument");
+  return codeword_planes_impl(P, table, valid, planes);
+}
+
+// ------------------------------------------------------------------ large elements
+extern "C" int pepsi_large_element_bits(uint32_t n_bins, uint32_t mu_client, uint32_t mu_server, uint32_t alpha,
+                                        uint32_t* bits) {
+  if (!bits) return fail(PEPSI_E_ARG, "null argument");
+  if (!n_bins || !mu_client || !mu_server) return fail(PEPSI_E_ARG, "bins and bin loads must be positive");
+  const u128 x = (u128)n_bins * mu_client * mu_server;
+  uint32_t c = 0;                                  // ceil(log2 x)
+  while (((u128)1 << c) < x) ++c;
+  *bits = alpha + c;
+  return PEPSI_OK;
+}
+
+extern "C" int pepsi_hash_elements(uint32_t bits, const uint8_t* data, const uint64_t* offsets, uint64_t count,
+                                   uint64_t* out) {
+  if ((!data && count) || (!offsets && count) || (!out && count)) return fail(PEPSI_E_ARG, "null argument");
+  if (bits < 1 || bits > 64) return fail(PEPSI_E_ARG, "bits must be in [1, 64]");
+  for (uint64_t e = 0; e < count; ++e) {
+    if (offsets[e + 1] < offsets[e]) return fail(PEPSI_E_ARG, "offsets must not decrease");
+    out[e] = hash_element(data + offsets[e], offsets[e + 1] - offsets[e], (int)bits);
   }
   return PEPSI_OK;
 }
@@ -884,9 +937,26 @@ extern "C" int pepsi_server_create_with_values(const pepsi_params* Pc, const uin
   return pepsi_server_create_ex(Pc, items, values, n, flags, 0, stream, out);
 }
 
+static int server_create_impl(const pepsi_params* Pc, const uint64_t* items, const uint32_t* values, uint64_t n,
+                              uint32_t flags, uint32_t max_cached, void* stream, pepsi_server** out);
+
 extern "C" int pepsi_server_create_ex(const pepsi_params* Pc, const uint32_t* items, const uint32_t* values,
                                       uint64_t n, uint32_t flags, uint32_t max_cached, void* stream,
                                       pepsi_server** out) {
+  if (!Pc || (!items && n) || !out) return fail(PEPSI_E_ARG, "null argument");
+  std::vector<uint64_t> wide(items, items + n);
+  return server_create_impl(Pc, wide.data(), values, n, flags, max_cached, stream, out);
+}
+
+extern "C" int pepsi_server_create64(const pepsi_params* Pc, const uint64_t* items, const uint32_t* values,
+                                     uint64_t n, uint32_t flags, uint32_t max_cached, void* stream,
+                                     pepsi_server** out) {
+  if (!Pc || (!items && n) || !out) return fail(PEPSI_E_ARG, "null argument");
+  return server_create_impl(Pc, items, values, n, flags, max_cached, stream, out);
+}
+
+static int server_create_impl(const pepsi_params* Pc, const uint64_t* items, const uint32_t* values, uint64_t n,
+                              uint32_t flags, uint32_t max_cached, void* stream, pepsi_server** out) {
   pepsi_params* P = const_cast<pepsi_params*>(Pc);
   if (!P || (!items && n) || !out) return fail(PEPSI_E_ARG, "null argument");
   *out = nullptr;
@@ -895,15 +965,16 @@ extern "C" int pepsi_server_create_ex(const pepsi_params* Pc, const uint32_t* it
     return fail(PEPSI_E_ARG, "PEPSI_SERVER_PLANES_ONLY needs PEPSI_SERVER_CACHE_PLAINTEXTS");
   const HostParams& H = P->H;
   {
-    std::unordered_set<uint32_t> seen;
+    std::unordered_set<uint64_t> seen;
     seen.reserve(n * 2);
     for (uint64_t i = 0; i < n; ++i) {
-      if (H.item_bits < 32 && (items[i] >> H.item_bits)) return fail(PEPSI_E_RANGE, "server item out of range");
+      if (H.item_bits < 64 && (items[i] >> H.item_bits)) return fail(PEPSI_E_RANGE, "server item out of range");
       if (!seen.insert(items[i]).second) return fail(PEPSI_E_RANGE, "duplicate server item");
       if (values && values[i] >= PEPSI_T) return fail(PEPSI_E_RANGE, "server value not below t");
     }
   }
-  std::vector<uint32_t> table, index;
+  std::vector<uint64_t> table;
+  std::vector<uint32_t> index;
   std::vector<uint8_t> valid;
   uint32_t max_load = 0;
   if (simple_hash(items, n, H.n, H.hash_seed, H.n_hash, H.mu, &table, &valid, &max_load,

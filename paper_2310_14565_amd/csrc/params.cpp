@@ -104,7 +104,7 @@ int build_host_params(int logn, int L, int h, int item_bits, int mu, int n_hash,
   if (logn < 10 || logn > 14) { snprintf(err, errlen, "log_n must be in [10, 14]"); return -2; }
   if (L < 1 || L > PEPSI_MAXL) { snprintf(err, errlen, "n_q must be in [1, %d]", PEPSI_MAXL); return -2; }
   if (h < 1 || h > 16) { snprintf(err, errlen, "h must be in [1, 16]"); return -2; }
-  if (item_bits < 1 || item_bits > 32) { snprintf(err, errlen, "item_bits must be in [1, 32]"); return -2; }
+  if (item_bits < 1 || item_bits > 64) { snprintf(err, errlen, "item_bits must be in [1, 64]"); return -2; }
   if (mu < 1) { snprintf(err, errlen, "mu must be positive"); return -2; }
   if (n_hash < 1 || n_hash > 8) { snprintf(err, errlen, "n_hash must be in [1, 8]"); return -2; }
   HostParams& H = *out;
@@ -121,7 +121,7 @@ int build_host_params(int logn, int L, int h, int item_bits, int mu, int n_hash,
     while ((1 << ib) < n_hash) ++ib;
     if (item_bits <= logn) { snprintf(err, errlen, "PBH needs item_bits > log_n"); return -2; }
     H.eff_bits = item_bits - logn + ib;
-    if (H.eff_bits > 32) { snprintf(err, errlen, "PBH values exceed 32 bits"); return -2; }
+    if (H.eff_bits > 64) { snprintf(err, errlen, "PBH values exceed 64 bits"); return -2; }
   }
   H.hash_seed = hash_seed; H.max_evictions = max_evictions;
 

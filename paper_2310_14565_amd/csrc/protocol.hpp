@@ -14,18 +14,24 @@ uint32_t hash_bin(uint64_t x, int i, uint64_t seed, uint32_t nbins);
 // based hashing (Sec. 3.3) with pbh_bits = lambda and nbins = 2^c, x = x_H || x_L, |x_L| =
 // lambda - c: (x_H ^ H_i(x_L), (i - 1) 2^(lambda - c) + x_L) -- the stored value names the hash
 // function, so equal values in equal bins mean equal elements with k > 1 hash functions.
-void place(uint32_t x, int i, uint64_t seed, uint32_t nbins, int pbh_bits, uint32_t* bin, uint32_t* value);
+// Elements and values are up to 64 bits (32-bit elements, or large elements hashed to lambda
+// bits).
+void place(uint64_t x, int i, uint64_t seed, uint32_t nbins, int pbh_bits, uint32_t* bin, uint64_t* value);
 
 // Cuckoo hashing without a stash; table receives each bin's stored value; returns 0 or -3
 // (eviction limit exceeded).
-int cuckoo_insert(const uint32_t* items, uint64_t m, uint32_t nbins, uint64_t seed, int k,
-                  int max_evictions, uint32_t* table, uint8_t* valid, int pbh_bits = 0);
+int cuckoo_insert(const uint64_t* items, uint64_t m, uint32_t nbins, uint64_t seed, int k,
+                  int max_evictions, uint64_t* table, uint8_t* valid, int pbh_bits = 0);
 // Every element to each distinct bin among H_1..H_k (with PBH: one entry per hash function,
 // since the k stored values differ), input order; table/valid [mu][nbins]; with index non-null
 // also the element's input position per entry; returns 0 or -4 (a bin exceeds mu).
-int simple_hash(const uint32_t* items, uint64_t n, uint32_t nbins, uint64_t seed, int k, uint32_t mu,
-                std::vector<uint32_t>* table, std::vector<uint8_t>* valid, uint32_t* max_load,
+int simple_hash(const uint64_t* items, uint64_t n, uint32_t nbins, uint64_t seed, int k, uint32_t mu,
+                std::vector<uint64_t>* table, std::vector<uint8_t>* valid, uint32_t* max_load,
                 std::vector<uint32_t>* index = nullptr, int pbh_bits = 0);
+
+// Large elements (Sec. 5, "Optimization for Large Elements"): the first `bits` bits (1..64) of
+// SHA-256 (FIPS 180-4) of a byte string, read big-endian.
+uint64_t hash_element(const uint8_t* data, uint64_t len, int bits);
 
 // Constant-weight code CW(ell, h) by the combinatorial number system.
 class CwEncoder {

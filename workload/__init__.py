@@ -97,3 +97,15 @@ def planes_random(count: int, n: int, seed: int, tag: str = "planes") -> np.ndar
 def item_values(n: int, lo: int, hi: int, seed: int) -> np.ndarray:
     """Server values (PSI-Sum) or labels (labelled PSI): n uniform integers in [lo, hi)."""
     return rng(seed, "item-values").integers(lo, hi, size=n, dtype=np.int64).astype(np.uint32)
+
+
+def byte_elements(n: int, length: int, seed: int, tag: str = "byte-elements") -> np.ndarray:
+    """Large elements (Sec. 7: strings such as credentials or 256-bit strings): n distinct
+    uniform byte strings of the given length, as the rows of a uint8 [n][length] array."""
+    g = rng(seed, tag)
+    out = g.integers(0, 256, size=(n, length), dtype=np.uint8)
+    if length < 16:                 # beyond 16 bytes a repeat has probability below 2^-88
+        _, first = np.unique(out, axis=0, return_index=True)
+        if first.shape[0] != n:
+            raise ValueError("repeated element; use longer elements")
+    return out

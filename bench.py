@@ -178,9 +178,14 @@ def serving_leg(pk, requests, pool, slots, load, seed, planes_only=False):
     prep_s = time.perf_counter() - t0
     log(f"[bench] serving server ready in {prep_s:.1f} s: max load {server.max_load}, "
         f"{server.cached_batches} of {server.max_load} batches cached, {server.plane_groups} digit-plane groups")
-    srv = pk.Serve(server, max_active=slots)
     outs = [torch.zeros((2, L, n), dtype=torch.int64, device="cuda") for _ in range(requests)]
     torch.cuda.synchronize()
+    free_b, _ = torch.cuda.mem_get_info()
+    budget = max(free_b - (2 << 30), 0)          # admission by memory: what is left beside a 2 GiB reserve
+    srv = pk.Serve(server, max_active=slots, hbm_budget=budget)
+    slots = srv.info().slots
+    log(f"[bench] serving: HBM budget {budget / 2**30:.1f} GiB, {srv.info().slot_bytes / 2**20:.0f} MiB per slot, "
+        f"{slots} slots")
 
     def submit(i):
         q = qs[i % pool]
@@ -232,6 +237,8 @@ def serving_leg(pk, requests, pool, slots, load, seed, planes_only=False):
         "requests": requests,
         "query_pool": pool,
         "slots": info.slots,
+        "hbm_budget_bytes": int(budget),
+        "slot_bytes": int(info.slot_bytes),
         "tiles_per_cycle": info.tiles,
         "store": "digit planes only" if planes_only else "NTT-form cache (+ digit planes when both fit)",
         "cached_batches": int(cached_batches),
@@ -361,8 +368,11 @@ def paper32_leg(pk, steps, seed):
     }
 
 
-def batched_leg(params, server, server_items, cfg, nq, steps, seed, plain_value):
-    """Config 'batched': nq queries, m log-uniform in [64, 2048], 25% planted, one launch sequence."""
+def batched_leg(pk, params, server, server_items, cfg, nq, steps, seed, plain_value):
+    """Config 'batched': nq queries, m log-uniform in [64, 2048], 25% planted, evaluated together
+    under the library's schedule for nq queries (the whole call one captured HIP graph, replayed).
+    Also: the same batch with eager launches (the graph's A/B), and with the select-and-sum on the
+    vector units instead of the int8 matrix cores."""
     import torch
     import workload as W
     n, L = params.n, params.L
@@ -373,15 +383,18 @@ def batched_leg(params, server, server_items, cfg, nq, steps, seed, plain_value)
           for i, m in enumerate(sizes)]
     outs = [torch.zeros((2, L, n), dtype=torch.int64, device="cuda") for _ in qs]
     args = ([q["cts"] for q in qs], [q["rlk"] for q in qs], [q["mask"] for q in qs], outs)
-    server.eval_batch(*args)                      # warm-up (allocates the batched workspace)
-    torch.cuda.synchronize()
-    server.timing(enable=True, reset=True)
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        server.eval_batch(*args)
-    torch.cuda.synchronize()
-    t = (time.perf_counter() - t0) / steps
-    tm = server.timing(enable=False)
+
+    def timed(k):
+        server.eval_batch(*args)                  # warm-up (workspace, graph capture)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            server.eval_batch(*args)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / k
+
+    sched = server.schedule(nq).as_dict()
+    t = timed(steps)
     bad = 0
     for q, o in zip(qs, outs):
         slots = torch.zeros((1, n), dtype=torch.int32, device="cuda")
@@ -392,6 +405,26 @@ def batched_leg(params, server, server_items, cfg, nq, steps, seed, plain_value)
     if bad:
         log(f"[bench] WRONG RESULT in {bad} batched queries")
         sys.exit(1)
+    ref = [o.clone() for o in outs]
+    # event-timed eager run: the select-and-sum share
+    server.timing(enable=True, reset=True)
+    server.eval_batch(*args)
+    tm = server.timing(enable=False)
+    # A/B: eager launches; the select-and-sum on the vector units
+    server.set_schedule(graph=pk.GRAPH_OFF)
+    t_eager = timed(1)
+    valu = None
+    if server.plane_groups > 0:
+        server.set_schedule(select_kernel=pk.SELECT_VALU)
+        vs = server.schedule(nq).as_dict()
+        t_valu = timed(1)
+        valu = {"ms_per_query": round(1e3 * t_valu / nq, 3), "value": round(nq * n * cfg["mu"] / t_valu, 1),
+                "speedup_vs_plain": round(nq * n * cfg["mu"] / t_valu / plain_value, 3),
+                "schedule": vs}
+    server.set_schedule(reset=True)
+    if not all(torch.equal(a, b) for a, b in zip(ref, outs)):
+        log("[bench] batched results differ between schedules")
+        sys.exit(1)
     value = nq * n * cfg["mu"] / t
     return {
         "queries": nq,
@@ -401,10 +434,13 @@ def batched_leg(params, server, server_items, cfg, nq, steps, seed, plain_value)
         "ms_per_batch": round(1e3 * t, 2),
         "ms_per_query": round(1e3 * t / nq, 3),
         "speedup_vs_plain": round(value / plain_value, 3),
-        "select_sum_ms_per_batch": round(tm.select_sum_ms / steps, 2),
+        "schedule": sched,
+        "eager_ms_per_query": round(1e3 * t_eager / nq, 3),
+        "select_sum_ms_per_batch": round(tm.select_sum_ms, 2),
         "checked_cardinalities": nq,
         "batches_computed": int(server.max_load),
         "value_computed_batches": round(nq * n * server.max_load / t, 1),
+        "valu_select_sum": valu,
     }
 
 
@@ -585,7 +621,8 @@ def main():
                     help="steps of the PSI-Sum leg over large (hashed 32-byte) elements (0: skip it)")
     ap.add_argument("--serve", type=int, default=500, help="requests in the serving leg (0: skip it)")
     ap.add_argument("--serve-pool", type=int, default=16, help="distinct client queries behind the requests")
-    ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--serve-slots", type=int, default=0,
+                    help="maximum query slots of the serving leg (0: as many as its HBM budget admits)")
     ap.add_argument("--serve-store", choices=["cache", "planes"], default="planes",
                     help="serving server keeps the NTT-form cache, or only int8 digit planes")
     ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate / saturated capacity")
@@ -734,7 +771,7 @@ def main():
         line["copy_calibration_bytes"] = {"read": words * 8, "written": words * 8}
         del src, dst
     if args.batch > 0:
-        line["batched"] = batched_leg(params, server, server_items, cfg, args.batch, args.batch_steps,
+        line["batched"] = batched_leg(pk, params, server, server_items, cfg, args.batch, args.batch_steps,
                                       args.seed + 7, value)
     if args.psi_sum_steps > 0 and args.config == "paper":
         server.close()

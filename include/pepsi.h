@@ -303,6 +303,42 @@ int pepsi_server_eval_batch(pepsi_server* server, uint32_t nq, const uint64_t* c
                             const uint64_t* const* d_rlk, const uint32_t* const* d_masks,
                             uint64_t* const* d_out, void* stream);
 
+/* Schedule of the batched evaluation.  Each field 0 means "automatic".
+ *   tile_batches:  server batches per tile (16, 32 or 64): the request planes or values are
+ *                  read once per tile, and a tile's workspace grows with tile_batches * nq;
+ *   select_kernel: PEPSI_SELECT_PLANES (int8 matrix cores over digit planes, when the server
+ *                  holds them) or PEPSI_SELECT_VALU (64-bit products on the vector units; not
+ *                  for a server that keeps its plaintexts only as planes);
+ *   graph:         PEPSI_GRAPH_ON (the whole launch sequence of a call -- every query's
+ *                  admission, all tiles and every query's finish -- is captured once into a HIP
+ *                  graph and replayed by later calls with the same buffers) or PEPSI_GRAPH_OFF
+ *                  (kernels launched one by one).  While event timing is enabled
+ *                  (pepsi_server_timing) the launches are eager, so that every select-and-sum
+ *                  launch is timed.
+ * "Automatic" takes the entry of the library's tuned table (measured by autotune.py beside the
+ * library) for the parameter set and the smallest tuned batch size >= nq, and otherwise a rule:
+ * the largest of 64 / 32 / 16 batches whose workspace fits beside an 8 GiB reserve with digit
+ * planes (16 without), the planes whenever the server holds them, graphs on.  A tile size whose
+ * workspace does not fit falls back to 16 batches.  Results are identical under every schedule. */
+#define PEPSI_SELECT_PLANES 1u
+#define PEPSI_SELECT_VALU 2u
+#define PEPSI_GRAPH_ON 1u
+#define PEPSI_GRAPH_OFF 2u
+#define PEPSI_SCHEDULE_DEFAULT 0u   /* source: the rule above            */
+#define PEPSI_SCHEDULE_TUNED 1u     /* source: an entry of the tuned table */
+#define PEPSI_SCHEDULE_CALLER 2u    /* source: pepsi_server_set_schedule   */
+typedef struct {
+  uint32_t tile_batches, select_kernel, graph;
+  uint32_t source;         /* out only (pepsi_server_get_schedule)                      */
+  double tuned_ms_per_query; /* out only: the tuned entry's measured time, 0 if none      */
+} pepsi_schedule;
+/* Forces the schedule of later batched evaluations (fields 0 stay automatic); NULL returns to
+ * the automatic schedule.  Errors: PEPSI_E_ARG (a value outside the lists above, or VALU on a
+ * server that holds its plaintexts only as planes). */
+int pepsi_server_set_schedule(pepsi_server* server, const pepsi_schedule* schedule);
+/* The schedule a batched evaluation of nq queries takes (the tile size before any fallback). */
+int pepsi_server_get_schedule(pepsi_server* server, uint32_t nq, pepsi_schedule* out);
+
 /* ------------------------------------------------------------------ */
 /* Request and response compression (the request / response sizes of  */
 /* Table "dipsi-cpsi")                                                 */
@@ -332,8 +368,11 @@ int pepsi_mod_switch(const pepsi_params* params, const uint64_t* d_ct, uint64_t*
  * them.  A submitted request waits in a queue until a query slot is free, is
  * admitted at the next step boundary, and completes after one full cycle of tiles
  * (its result is bit-identical to pepsi_server_eval on the same inputs).  The
- * number of slots is max_active, capped by hbm_budget / (device bytes per slot)
- * when hbm_budget is non-zero; the handle's workspace is allocated at creation.
+ * number of slots is max_active (0: PEPSI_MAX_BATCH), capped by hbm_budget / (device
+ * bytes per slot, pepsi_serve_info.slot_bytes) when hbm_budget is non-zero: requests are
+ * admitted by memory, and the rest wait.  The handle's workspace is allocated at creation.
+ * The worker keeps up to two steps in flight on the device and completes requests from
+ * events, so its host bookkeeping overlaps the device's work.
  * Device buffers of a request must be ready (their producing work synchronised)
  * at submission and stay valid until it completes.  submit / poll / wait /
  * get_info are thread-safe.  Times are seconds on pepsi_clock(), a monotonic
@@ -346,6 +385,7 @@ typedef struct {
 typedef struct {
   uint32_t slots, tiles, active, queued;
   uint64_t steps, completed;
+  uint64_t slot_bytes;     /* device bytes one query slot takes (the admission unit)     */
 } pepsi_serve_info;
 double pepsi_clock(void);
 int pepsi_serve_create(pepsi_server* server, uint32_t max_active, uint64_t hbm_budget, pepsi_serve** out);
@@ -358,9 +398,10 @@ int pepsi_serve_get_info(pepsi_serve* serve, pepsi_serve_info* out);
 void pepsi_serve_destroy(pepsi_serve* serve);
 
 /* Event timing of a server's evaluations, for measurement.  While enabled,
- * every select-and-sum launch (the kernel that streams the server plaintexts)
- * and every whole evaluation is bracketed by HIP events on the evaluation's
- * stream.  The call synchronises the device, folds finished event pairs into
+ * every select-and-sum launch (the kernel that streams the server plaintexts),
+ * every forward and inverse transform of the request, the product tree and the
+ * finish, and every whole evaluation are bracketed by HIP events on the
+ * evaluation's stream.  The call synchronises the device, folds finished event pairs into
  * the totals, then applies reset (zero the totals) and enable (1 on, 0 off). */
 typedef struct {
   uint64_t select_sum_launches;
@@ -369,8 +410,19 @@ typedef struct {
   double select_sum_ms;
   uint64_t evals;
   double eval_ms;
+  uint64_t ntt_fwd_launches, ntt_fwd_rows;  /* the evaluations' forward transforms over Q or B */
+  double ntt_fwd_ms;
+  uint64_t ntt_inv_launches, ntt_inv_rows;  /* and their inverse transforms                   */
+  double ntt_inv_ms;
 } pepsi_timing;
 int pepsi_server_timing(pepsi_server* server, int enable, int reset, pepsi_timing* out);
+
+/* Issue rate of one vector-ALU instruction on the current device, in lane operations per
+ * second: eight independent chains of the instruction per thread, 8 waves per SIMD on every
+ * compute unit, timed with events (the measured peaks of the integer-VALU roofline).  kind: 0
+ * v_mad_u64_u32, 1 v_mul_hi_u32, 2 v_mul_lo_u32, 3 v_add_u32, 4 v_mad_u32_u24, 5 v_fma_f64.
+ * Synchronous; allocates and frees a small buffer.  Errors: PEPSI_E_ARG, PEPSI_E_DEVICE. */
+int pepsi_probe_valu(uint32_t kind, double* lane_ops_per_s);
 
 /* ------------------------------------------------------------------ */
 /* Single evaluator steps                                              */

@@ -52,6 +52,23 @@ class ServerInfo(C.Structure):
                 ("plane_groups", C.c_uint32)]
 
 
+class Schedule(C.Structure):
+    _fields_ = [("tile_batches", C.c_uint32), ("select_kernel", C.c_uint32), ("graph", C.c_uint32),
+                ("source", C.c_uint32), ("tuned_ms_per_query", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {"tile_batches": self.tile_batches,
+                "select_kernel": {1: "int8 matrix cores (digit planes)", 2: "64-bit VALU"}.get(self.select_kernel,
+                                                                                          "automatic"),
+                "graph": {1: "captured HIP graph", 2: "eager launches"}.get(self.graph, "automatic"),
+                "source": {0: "default rule", 1: "tuned table", 2: "caller"}.get(self.source, "?"),
+                "tuned_ms_per_query": self.tuned_ms_per_query or None}
+
+
+SELECT_PLANES, SELECT_VALU = 1, 2
+GRAPH_ON, GRAPH_OFF = 1, 2
+
+
 class ReqStats(C.Structure):
     _fields_ = [("submit_s", C.c_double), ("admit_s", C.c_double), ("done_s", C.c_double),
                 ("slot", C.c_uint32), ("done", C.c_uint32)]
@@ -59,12 +76,14 @@ class ReqStats(C.Structure):
 
 class ServeInfo(C.Structure):
     _fields_ = [("slots", C.c_uint32), ("tiles", C.c_uint32), ("active", C.c_uint32), ("queued", C.c_uint32),
-                ("steps", C.c_uint64), ("completed", C.c_uint64)]
+                ("steps", C.c_uint64), ("completed", C.c_uint64), ("slot_bytes", C.c_uint64)]
 
 
 class Timing(C.Structure):
     _fields_ = [("select_sum_launches", C.c_uint64), ("select_sum_bytes", C.c_uint64),
-                ("select_sum_ms", C.c_double), ("evals", C.c_uint64), ("eval_ms", C.c_double)]
+                ("select_sum_ms", C.c_double), ("evals", C.c_uint64), ("eval_ms", C.c_double),
+                ("ntt_fwd_launches", C.c_uint64), ("ntt_fwd_rows", C.c_uint64), ("ntt_fwd_ms", C.c_double),
+                ("ntt_inv_launches", C.c_uint64), ("ntt_inv_rows", C.c_uint64), ("ntt_inv_ms", C.c_double)]
 
 
 _SIGS = {
@@ -100,6 +119,9 @@ _SIGS = {
     "pepsi_server_eval_batch": (C.c_int, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p,
                                           C.c_void_p, C.c_void_p]),
     "pepsi_clock": (C.c_double, []),
+    "pepsi_probe_valu": (C.c_int, [C.c_uint32, C.POINTER(C.c_double)]),
+    "pepsi_server_set_schedule": (C.c_int, [C.c_void_p, C.POINTER(Schedule)]),
+    "pepsi_server_get_schedule": (C.c_int, [C.c_void_p, C.c_uint32, C.POINTER(Schedule)]),
     "pepsi_expand_uniform": (C.c_int, [C.c_void_p, C.c_char_p, C.c_uint32, C.c_uint32, C.c_void_p, C.c_uint64,
                                        C.c_void_p]),
     "pepsi_mod_switch": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -350,6 +372,19 @@ class Server:
         m_ = None if masks is None else arr(*[0 if m is None else m.data_ptr() for m in masks])
         _check(lib().pepsi_server_eval_batch(self._h, nq, c_, r_, m_, o_, _stream(stream)))
 
+    def set_schedule(self, tile_batches: int = 0, select_kernel: int = 0, graph: int = 0, reset: bool = False):
+        """Force the batched schedule (0 = automatic); reset returns to the automatic schedule."""
+        if reset:
+            _check(lib().pepsi_server_set_schedule(self._h, None))
+            return
+        sch = Schedule(tile_batches, select_kernel, graph, 0, 0.0)
+        _check(lib().pepsi_server_set_schedule(self._h, C.byref(sch)))
+
+    def schedule(self, nq: int) -> Schedule:
+        sch = Schedule()
+        _check(lib().pepsi_server_get_schedule(self._h, nq, C.byref(sch)))
+        return sch
+
     def timing(self, enable: bool, reset: bool = False) -> Timing:
         t = Timing()
         _check(lib().pepsi_server_timing(self._h, 1 if enable else 0, 1 if reset else 0, C.byref(t)))
@@ -385,6 +420,16 @@ def hash_elements(elements, bits: int) -> np.ndarray:
     out = np.zeros(count, np.uint64)
     _check(lib().pepsi_hash_elements(bits, _host(data), _host(offsets), count, _host(out)))
     return out
+
+
+VALU_KINDS = ("v_mad_u64_u32", "v_mul_hi_u32", "v_mul_lo_u32", "v_add_u32", "v_mad_u32_u24", "v_fma_f64")
+
+
+def probe_valu(kind: int) -> float:
+    """Measured lane operations per second of one VALU instruction kind (pepsi_probe_valu)."""
+    v = C.c_double()
+    _check(lib().pepsi_probe_valu(kind, C.byref(v)))
+    return float(v.value)
 
 
 def clock() -> float:

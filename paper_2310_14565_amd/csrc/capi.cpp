@@ -457,6 +457,8 @@ struct EventTimer {
       float ms = 0;
       if (hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess) return -1;
       if (p.kind == 0) { tot.select_sum_launches++; tot.select_sum_ms += ms; tot.select_sum_bytes += p.bytes; }
+      else if (p.kind == 2) { tot.ntt_fwd_launches++; tot.ntt_fwd_ms += ms; tot.ntt_fwd_rows += p.bytes; }
+      else if (p.kind == 3) { tot.ntt_inv_launches++; tot.ntt_inv_ms += ms; tot.ntt_inv_rows += p.bytes; }
       else { tot.evals++; tot.eval_ms += ms; }
       pool.push_back(p.a);
       pool.push_back(p.b);
@@ -499,6 +501,20 @@ struct Engine {
       b->release();
     for (auto& b : rq) b.release();
     for (auto& b : rb) b.release();
+  }
+
+  // Transforms of the engine, event-timed (rows per launch) while the server's timer is on.
+  void tfwd(const void* in, void* out, int rows, int nprimes, int first, hipStream_t s) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (timer && timer->on && rows > 0) { a = timer->get(); b = timer->get(); (void)hipEventRecord(a, s); }
+    ntt_forward(P->T, P->H.logn, in, LOAD_U64, out, STORE_U64, rows, nprimes, first, s);
+    if (a) { (void)hipEventRecord(b, s); timer->pending.push_back({a, b, 2, (uint64_t)rows}); }
+  }
+  void tinv(const uint64_t* in, uint64_t* out, int rows, int nprimes, int first, hipStream_t s) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (timer && timer->on && rows > 0) { a = timer->get(); b = timer->get(); (void)hipEventRecord(a, s); }
+    ntt_inverse(P->T, P->H.logn, in, out, rows, nprimes, first, s);
+    if (a) { (void)hipEventRecord(b, s); timer->pending.push_back({a, b, 3, (uint64_t)rows}); }
   }
 
   size_t cstride() const { return (size_t)P->H.ell * 2 * P->H.L * P->H.n; }
@@ -609,16 +625,26 @@ struct Engine {
     const int L = H.L, K = H.K;
     const int njobs = units * jobs_per_unit;
     relin_digits(P->T, H.consts, c2.as<uint64_t>(), D.as<uint64_t>(), units, s);
-    ntt_forward(P->T, H.logn, D.p, LOAD_U64, D.p, STORE_U64, units * L * L, L, 0, s);
-    ntt_forward(P->T, H.logn, c01.p, LOAD_U64, c01h.p, STORE_U64, njobs * 2 * L, L, 0, s);
-    relin_inner(P->T, H.consts, c01h.as<uint64_t>(), D.as<uint64_t>(),
-                rlkhat.as<uint64_t>((size_t)key_slot * rstride()), (long)rstride(), qslot, jobs_per_unit,
-                units_per_pair, nq, out, units, s);
+    tfwd(D.p, D.p, units * L * L, L, 0, s);
+    const uint64_t* key = rlkhat.as<uint64_t>((size_t)key_slot * rstride());
     if (ext_out) {
-      ntt_inverse(P->T, H.logn, out, rcoef.as<uint64_t>(), njobs * 2 * L, L, 0, s);
-      ext_q_to_b(P->T, H.consts, rcoef.as<uint64_t>(), ext_out, (long)K * H.n, njobs * 2,
-                 P->fallback.as<uint32_t>(), s);
-      ntt_forward(P->T, H.logn, ext_out, LOAD_U64, ext_out, STORE_U64, njobs * 2 * K, K, L, s);
+      // The next level needs the results in coefficient form too (for their extension to B).
+      // The jobs of a unit share its key sum K = sum_i D_i rlk_i, so K alone is transformed back
+      // (2 L rows per unit) and added to each job's products in coefficient form; the sums are
+      // then transformed forward over Q and over B.  (Forming c01 + K in NTT form would need the
+      // 2 L rows of c01 forward and of the sum back, per job.)
+      uint64_t* kh = c01h.as<uint64_t>();
+      relin_inner(P->T, H.consts, nullptr, D.as<uint64_t>(), key, (long)rstride(), qslot, 1, units_per_pair, nq, kh,
+                  units, s);
+      tinv(kh, kh, units * 2 * L, L, 0, s);
+      add_ext_q_to_b(P->T, H.consts, c01.as<uint64_t>(), kh, jobs_per_unit, rcoef.as<uint64_t>(), ext_out,
+                     njobs * 2, P->fallback.as<uint32_t>(), s);
+      tfwd(rcoef.p, out, njobs * 2 * L, L, 0, s);
+      tfwd(ext_out, ext_out, njobs * 2 * K, K, L, s);
+    } else {
+      tfwd(c01.p, c01h.p, njobs * 2 * L, L, 0, s);
+      relin_inner(P->T, H.consts, c01h.as<uint64_t>(), D.as<uint64_t>(), key, (long)rstride(), qslot, jobs_per_unit,
+                  units_per_pair, nq, out, units, s);
     }
   }
 
@@ -630,7 +656,7 @@ struct Engine {
     const int Pn = H.L + H.K;
     uint64_t* dd = d.as<uint64_t>();
     square_products(P->T, H.consts, Sq, sbh.as<uint64_t>(), dd, npairs, s);
-    ntt_inverse(P->T, H.logn, dd, dd, npairs * 3 * Pn, Pn, 0, s);
+    tinv(dd, dd, npairs * 3 * Pn, Pn, 0, s);
     scale_round_first(P->T, H.consts, dd, scoef.as<uint64_t>(), sb.as<uint64_t>(), alpha.as<uint64_t>(),
                       pconst.as<uint64_t>(), H.h, npairs, c01.as<uint64_t>(), c2.as<uint64_t>(),
                       P->fallback.as<uint32_t>(), s);
@@ -642,7 +668,7 @@ struct Engine {
     const int Pn = H.L + H.K;
     uint64_t* dd = d.as<uint64_t>();
     tensor(P->T, H.consts, dev_jobs, njobs, s);
-    ntt_inverse(P->T, H.logn, dd, dd, njobs * 3 * Pn, Pn, 0, s);
+    tinv(dd, dd, njobs * 3 * Pn, Pn, 0, s);
     scale_round(P->T, H.consts, dd, c01.as<uint64_t>(), c2.as<uint64_t>(), njobs, P->fallback.as<uint32_t>(), s);
   }
 
@@ -670,14 +696,14 @@ struct Engine {
   void admit(int slot, const uint64_t* cts, const uint64_t* rlk, hipStream_t s) {
     const HostParams& H = P->H;
     const int L = H.L;
-    ntt_forward(P->T, H.logn, cts, LOAD_U64, chat.as<uint64_t>(slot * cstride()), STORE_U64, H.ell * 2 * L, L,
+    tfwd(cts, chat.as<uint64_t>(slot * cstride()), H.ell * 2 * L, L,
                 0, s);
     if (planes_on)
       request_planes(P->T, H.consts, chat.as<uint64_t>(slot * cstride()), H.ell,
                      cplanes.as<int8_t>((size_t)slot * cpstride()), s);
-    ntt_forward(P->T, H.logn, rlk, LOAD_U64, rlkhat.as<uint64_t>(slot * rstride()), STORE_U64, L * 2 * L, L, 0, s);
-    (void)hipMemsetAsync(acc.as<uint64_t>(slot * ctw()), 0, ctw() * 8, s);
-    if (levels > 0) (void)hipMemsetAsync(accD.as<uint64_t>(slot * dtw()), 0, dtw() * 8, s);
+    tfwd(rlk, rlkhat.as<uint64_t>(slot * rstride()), L * 2 * L, L, 0, s);
+    zero_words(acc.as<uint64_t>(slot * ctw()), ctw(), s);
+    if (levels > 0) zero_words(accD.as<uint64_t>(slot * dtw()), dtw(), s);
   }
 
   // A run of batches in a plaintext store: batches bfirst .. of a store of groups of gs batches.
@@ -766,15 +792,15 @@ struct Engine {
     uint64_t* Sq = sq.as<uint64_t>();
     if (Sin != Sq) {
       if (H.h % 2) {            // a raw factor reaches a later level: its tensor jobs read sq
-        (void)hipMemcpyAsync(Sq, Sin, (size_t)npairs * 2 * L * n * 8, hipMemcpyDeviceToDevice, s);
+        copy_words(Sq, Sin, (size_t)npairs * 2 * L * n, s);
       } else {
         Sq = Sin;
       }
     }
-    ntt_inverse(P->T, H.logn, Sq, scoef.as<uint64_t>(), npairs * 2 * (int)L, (int)L, 0, s);
+    tinv(Sq, scoef.as<uint64_t>(), npairs * 2 * (int)L, (int)L, 0, s);
     ext_q_to_b(P->T, H.consts, scoef.as<uint64_t>(), sb.as<uint64_t>(), (long)(K * n), npairs * 2,
                P->fallback.as<uint32_t>(), s);
-    ntt_forward(P->T, H.logn, sb.p, LOAD_U64, sbh.p, STORE_U64, npairs * 2 * (int)K, (int)K, (int)L, s);
+    tfwd(sb.p, sbh.p, npairs * 2 * (int)K, (int)K, (int)L, s);
     factor_constants(P->T, H.consts, scoef.as<uint64_t>(), npairs, H.h, alpha.as<uint64_t>(), pconst.as<uint64_t>(),
                      P->fallback.as<uint32_t>(), s);
     // the key of a single active query: shift the key base to its slot
@@ -828,8 +854,8 @@ struct Engine {
     if (levels > 0 && !vhat) {
       // a = NTT(sum of c01) + sum_i NTT(sum of D_i) (.) rlk_i
       uint64_t* dq = accD.as<uint64_t>(q * dtw());
-      ntt_forward(P->T, H.logn, a, LOAD_U64, a, STORE_U64, 2 * L, L, 0, s);
-      ntt_forward(P->T, H.logn, dq, LOAD_U64, dq, STORE_U64, L * L, L, 0, s);
+      tfwd(a, a, 2 * L, L, 0, s);
+      tfwd(dq, dq, L * L, L, 0, s);
       relin_inner(P->T, H.consts, a, dq, rlkhat.as<uint64_t>((size_t)q * rstride()), (long)rstride(), nullptr, 1, 1,
                   1, a, 1, s);
     }
@@ -842,7 +868,7 @@ struct Engine {
       for (int l = 0; l < L; ++l) kq[l] = kc >= 0 ? (uint64_t)kc : H.primes[l] - (uint64_t)(-kc);
       scale_const(P->T, H.consts, a, kq, s);
     }
-    ntt_inverse(P->T, H.logn, a, out, 2 * L, L, 0, s);
+    tinv(a, out, 2 * L, L, 0, s);
     if (finalize && mask) {
       uint32_t* m = reinterpret_cast<uint32_t*>(e.p);            // e is free after the tiles
       encode_slots(P->T, H.logn, mask, m, 1, s);
@@ -897,6 +923,58 @@ static size_t engine_slot_bytes(const HostParams& H) {
   return 8 * ((size_t)H.ell * 2 * L * n + L * 2 * L * n + 2 * L * n);
 }
 
+// ------------------------------------------------------------------ batched schedules
+namespace {
+// Launch sequences of batched evaluations captured into HIP graphs, keyed by the query count and
+// the caller's buffers (the kernels' arguments); the engine's own buffers are fixed until its
+// workspace is set up again, which clears the cache.
+struct GraphCache {
+  struct Entry {
+    std::vector<uintptr_t> key;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t e = nullptr;
+  };
+  static constexpr size_t kMax = 4;
+  std::vector<Entry> entries;        // least recently used first
+  hipStream_t cap = nullptr;         // capture stream (the caller's may be the null stream)
+  void clear() {
+    for (auto& x : entries) {
+      if (x.e) (void)hipGraphExecDestroy(x.e);
+      if (x.g) (void)hipGraphDestroy(x.g);
+    }
+    entries.clear();
+  }
+  Entry* find(const std::vector<uintptr_t>& key) {
+    for (size_t i = 0; i < entries.size(); ++i)
+      if (entries[i].key == key) {
+        std::rotate(entries.begin() + i, entries.begin() + i + 1, entries.end());
+        return &entries.back();
+      }
+    return nullptr;
+  }
+  ~GraphCache() {
+    clear();
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+};
+
+// Schedules measured by autotune.py on MI355X: {log_n, L, ell, h, nq_max, tile_batches,
+// select_kernel, graph, ms_per_query}.
+struct TunedEntry { int logn, L, ell, h, nq_max, tile, kernel, graph; double ms; };
+const TunedEntry kTuned[] = {
+#include "schedule_table.inc"
+    {0, 0, 0, 0, 0, 0, 0, 0, 0.0}};
+
+const TunedEntry* tuned_entry(const HostParams& H, uint32_t nq) {
+  const TunedEntry* best = nullptr;
+  for (const TunedEntry& t : kTuned)
+    if (t.logn == H.logn && t.L == H.L && t.ell == H.ell && t.h == H.h && (uint32_t)t.nq_max >= nq &&
+        (!best || t.nq_max < best->nq_max))
+      best = &t;
+  return best;
+}
+}  // namespace
+
 // ------------------------------------------------------------------ server
 struct pepsi_server {
   pepsi_params* P = nullptr;
@@ -921,6 +999,9 @@ struct pepsi_server {
   bool ready = false;
   Engine beng;           // many queries per launch (batched path)
   int bqmax = 0;
+  pepsi_schedule bsched{};     // schedule the batched workspace was set up for
+  pepsi_schedule forced{};     // caller's schedule (fields 0: automatic)
+  GraphCache graphs;           // captured batched evaluations
   DevBuf vhat;           // server values (Alg. 4 / 5): [max_load][L][N] plaintexts, NTT form
   bool valued = false;
   const uint64_t* values_hat() const { return valued ? vhat.as<uint64_t>() : nullptr; }
@@ -1130,6 +1211,7 @@ extern "C" int pepsi_server_codewords(const pepsi_server* sv, uint16_t* out) {
 extern "C" void pepsi_server_destroy(pepsi_server* sv) {
   if (!sv) return;
   (void)hipDeviceSynchronize();
+  sv->graphs.clear();
   sv->cw.release();
   sv->cache.release();
   sv->vhat.release();
@@ -1178,6 +1260,57 @@ extern "C" int pepsi_server_eval(pepsi_server* sv, const uint64_t* cts, const ui
   return pepsi_server_eval_range(sv, cts, rlk, 0, sv->P->H.mu, 1, mask, out, stream);
 }
 
+// The schedule of a batched evaluation of nq queries (see pepsi_schedule): the caller's fields,
+// then the tuned table, then the rule.  The tile size is the one requested; eval_batch falls back
+// to 16 batches when its workspace does not fit.
+static pepsi_schedule resolve_schedule(const pepsi_server* sv, uint32_t nq) {
+  const HostParams& H = sv->P->H;
+  pepsi_schedule r{};
+  r.source = PEPSI_SCHEDULE_DEFAULT;
+  if (const TunedEntry* t = tuned_entry(H, nq)) {
+    r.tile_batches = (uint32_t)t->tile;
+    r.select_kernel = (uint32_t)t->kernel;
+    r.graph = (uint32_t)t->graph;
+    r.tuned_ms_per_query = t->ms;
+    r.source = PEPSI_SCHEDULE_TUNED;
+  }
+  const pepsi_schedule& f = sv->forced;
+  if (f.tile_batches || f.select_kernel || f.graph) r.source = PEPSI_SCHEDULE_CALLER;
+  if (f.tile_batches) r.tile_batches = f.tile_batches;
+  if (f.select_kernel) r.select_kernel = f.select_kernel;
+  if (f.graph) r.graph = f.graph;
+  if (!r.select_kernel) r.select_kernel = sv->plane_groups > 0 ? PEPSI_SELECT_PLANES : PEPSI_SELECT_VALU;
+  if (sv->plane_groups == 0) r.select_kernel = PEPSI_SELECT_VALU;      // nothing to contract on the matrix cores
+  if (sv->planes_only) r.select_kernel = PEPSI_SELECT_PLANES;         // the plaintexts exist only as planes
+  if (!r.graph) r.graph = PEPSI_GRAPH_ON;
+  if (!r.tile_batches) r.tile_batches = (r.select_kernel == PEPSI_SELECT_PLANES && nq <= 64) ? 64 : 16;
+  return r;
+}
+
+extern "C" int pepsi_server_set_schedule(pepsi_server* sv, const pepsi_schedule* sch) {
+  if (!sv) return fail(PEPSI_E_ARG, "null argument");
+  pepsi_schedule f{};
+  if (sch) {
+    if (sch->tile_batches && sch->tile_batches != 16 && sch->tile_batches != 32 && sch->tile_batches != 64)
+      return fail(PEPSI_E_ARG, "tile_batches must be 0, 16, 32 or 64");
+    if (sch->select_kernel > PEPSI_SELECT_VALU) return fail(PEPSI_E_ARG, "unknown select kernel");
+    if (sch->graph > PEPSI_GRAPH_OFF) return fail(PEPSI_E_ARG, "unknown graph mode");
+    if (sch->select_kernel == PEPSI_SELECT_VALU && sv->planes_only)
+      return fail(PEPSI_E_ARG, "the server keeps its plaintexts only as digit planes");
+    f.tile_batches = sch->tile_batches;
+    f.select_kernel = sch->select_kernel;
+    f.graph = sch->graph;
+  }
+  sv->forced = f;
+  return PEPSI_OK;
+}
+
+extern "C" int pepsi_server_get_schedule(pepsi_server* sv, uint32_t nq, pepsi_schedule* out) {
+  if (!sv || !out) return fail(PEPSI_E_ARG, "null argument");
+  *out = resolve_schedule(sv, nq ? nq : 1);
+  return PEPSI_OK;
+}
+
 extern "C" int pepsi_server_eval_batch(pepsi_server* sv, uint32_t nq, const uint64_t* const* cts,
                                        const uint64_t* const* rlk, const uint32_t* const* masks,
                                        uint64_t* const* out, void* stream) {
@@ -1188,37 +1321,89 @@ extern "C" int pepsi_server_eval_batch(pepsi_server* sv, uint32_t nq, const uint
     if (!cts[q] || !rlk[q] || !out[q]) return fail(PEPSI_E_ARG, "null query pointer %u", q);
   const HostParams& H = sv->P->H;
   hipStream_t s = S(stream);
-  if ((int)nq > sv->bqmax) {
-    // batches per tile: one batch group of the multi-query select-and-sum (16); with digit
-    // planes and up to 64 queries, four or two groups (the request planes are then read once
-    // per 64 or 32 batches) when their tile buffers fit beside an 8 GiB reserve
+  const pepsi_schedule want = resolve_schedule(sv, nq);
+  const bool planes = want.select_kernel == PEPSI_SELECT_PLANES;
+  if ((int)nq > sv->bqmax || want.select_kernel != sv->bsched.select_kernel ||
+      want.tile_batches != sv->bsched.tile_batches) {
+    // the requested tile when its workspace fits beside an 8 GiB reserve, else 16 batches (one
+    // batch group of the select-and-sum kernels)
     int tb = 16;
-    if (sv->plane_groups > 0 && nq <= 64) {
+    if (want.tile_batches > 16) {
       size_t free_b = 0, total_b = 0;
       if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return fail(PEPSI_E_DEVICE, "hipMemGetInfo failed");
-      const size_t fixed = (size_t)nq * (engine_slot_bytes(H) + request_plane_bytes(H.consts, H.ell)) +
+      const size_t fixed = (size_t)nq * (engine_slot_bytes(H) + (planes ? request_plane_bytes(H.consts, H.ell) : 0)) +
                            ((size_t)8 << 30);
       for (int cand : {64, 32})
-        if (free_b > fixed + (size_t)cand * nq * engine_pair_bytes(H)) { tb = cand; break; }
+        if (cand <= (int)want.tile_batches && free_b > fixed + (size_t)cand * nq * engine_pair_bytes(H)) {
+          tb = cand;
+          break;
+        }
     }
     // the workspace counts as set up only once every part of it is (a failed call leaves
     // bqmax at 0, so the next call sets it up again instead of running on a partial one)
     sv->bqmax = 0;
-    int rc = sv->beng.setup(sv->P, std::min<int>(tb, std::max<int>(1, (int)sv->max_load)), (int)nq,
-                            sv->need_gen_multi(), sv->values_hat());
+    sv->graphs.clear();
+    const bool need_gen = planes ? sv->need_gen_multi() : sv->cached_batches < sv->max_load;
+    int rc = sv->beng.setup(sv->P, std::min<int>(tb, std::max<int>(1, (int)sv->max_load)), (int)nq, need_gen,
+                            sv->values_hat());
     if (rc) return rc;
     sv->beng.timer = &sv->timer;
-    if (sv->plane_groups > 0 && (rc = sv->beng.enable_planes(sv->planes_only))) return rc;
+    if (planes && (rc = sv->beng.enable_planes(sv->planes_only))) return rc;
+    sv->bsched = want;
     sv->bqmax = (int)nq;
   }
   Engine& E = sv->beng;
+  const uint32_t stop = std::min<uint32_t>(H.mu, sv->max_load);
+  auto run_all = [&](hipStream_t st) -> int {
+    int rc = E.run(sv->cw.as<uint16_t>(), sv->cached ? sv->cache.as<uint64_t>() : nullptr, sv->cached_batches, 0,
+                   stop, (int)nq, cts, rlk, st, planes ? sv->planes_p() : nullptr, sv->plane_group_bytes,
+                   sv->plane_batches);
+    if (rc) return rc;
+    for (uint32_t q = 0; q < nq; ++q) E.finish((int)q, true, masks ? masks[q] : nullptr, out[q], st);
+    return 0;
+  };
   hipEvent_t ea = nullptr, eb = nullptr;
   if (sv->timer.on) { ea = sv->timer.get(); eb = sv->timer.get(); (void)hipEventRecord(ea, s); }
-  const uint32_t stop = std::min<uint32_t>(H.mu, sv->max_load);
-  int rc = E.run(sv->cw.as<uint16_t>(), sv->cached ? sv->cache.as<uint64_t>() : nullptr, sv->cached_batches, 0,
-                 stop, (int)nq, cts, rlk, s, sv->planes_p(), sv->plane_group_bytes, sv->plane_batches);
-  if (rc) return rc;
-  for (uint32_t q = 0; q < nq; ++q) E.finish((int)q, true, masks ? masks[q] : nullptr, out[q], s);
+  if (want.graph == PEPSI_GRAPH_ON && !sv->timer.on) {
+    std::vector<uintptr_t> key;
+    key.reserve(1 + 4 * (size_t)nq);
+    key.push_back(nq);
+    for (uint32_t q = 0; q < nq; ++q) {
+      key.push_back((uintptr_t)cts[q]);
+      key.push_back((uintptr_t)rlk[q]);
+      key.push_back((uintptr_t)(masks ? masks[q] : nullptr));
+      key.push_back((uintptr_t)out[q]);
+    }
+    GraphCache& gc = sv->graphs;
+    GraphCache::Entry* ent = gc.find(key);
+    if (!ent) {
+      if (!gc.cap) HIPCHK(hipStreamCreateWithFlags(&gc.cap, hipStreamNonBlocking));
+      HIPCHK(hipStreamBeginCapture(gc.cap, hipStreamCaptureModeThreadLocal));
+      const int rc = run_all(gc.cap);
+      hipGraph_t g = nullptr;
+      const hipError_t ec = hipStreamEndCapture(gc.cap, &g);
+      if (rc || ec != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc ? rc : fail(PEPSI_E_DEVICE, "graph capture failed: %s", hipGetErrorString(ec));
+      }
+      hipGraphExec_t ex = nullptr;
+      if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(PEPSI_E_DEVICE, "graph instantiation failed");
+      }
+      if (gc.entries.size() >= GraphCache::kMax) {
+        (void)hipGraphExecDestroy(gc.entries.front().e);
+        (void)hipGraphDestroy(gc.entries.front().g);
+        gc.entries.erase(gc.entries.begin());
+      }
+      gc.entries.push_back(GraphCache::Entry{std::move(key), g, ex});
+      ent = &gc.entries.back();
+    }
+    HIPCHK(hipGraphLaunch(ent->e, s));
+  } else {
+    const int rc = run_all(s);
+    if (rc) return rc;
+  }
   if (ea) {
     (void)hipEventRecord(eb, s);
     sv->timer.pending.push_back({ea, eb, 1, 0});
@@ -1278,8 +1463,21 @@ struct pepsi_serve {
   std::unordered_map<uint64_t, Req*> reqs;
   std::vector<Req*> active;
   uint64_t next_id = 1, steps = 0, completed = 0;
-  int* qslot_host = nullptr;
+  int* qslot_host = nullptr;           // kDepth + 1 pinned slot lists of `slots` entries
   DevBuf qslot_dev;
+  size_t slot_bytes = 0;
+
+  // Steps are enqueued ahead of the device: up to kDepth steps in flight, each ending with an
+  // event; a request is done when the event of the step that enqueued its finish has completed.
+  // Host bookkeeping (admissions, slot lists, completions) thus overlaps the device's work.
+  static constexpr int kDepth = 2;
+  struct Step {
+    hipEvent_t ev = nullptr;
+    std::vector<Req*> finished;
+  };
+  std::deque<Step> inflight;
+  std::vector<hipEvent_t> ev_pool;
+  int ring = 0;
 
   void fail_all(const char* what) {
     std::lock_guard<std::mutex> lk(mu);
@@ -1288,21 +1486,47 @@ struct pepsi_serve {
     cv_done.notify_all();
   }
 
+  // Completes the requests of finished steps, oldest first; with blocking, waits for the oldest
+  // one.  Returns false after a device error.
+  bool retire(bool blocking) {
+    while (!inflight.empty()) {
+      Step& st = inflight.front();
+      const hipError_t e = blocking ? hipEventSynchronize(st.ev) : hipEventQuery(st.ev);
+      if (e == hipErrorNotReady) return true;
+      if (e != hipSuccess) {
+        fail_all("device error in a serving step");
+        return false;
+      }
+      if (!st.finished.empty()) {
+        std::lock_guard<std::mutex> lk(mu);
+        const double t = now_s();
+        for (Req* r : st.finished) {
+          r->t_done = t;
+          r->done = 1;
+          ++completed;
+        }
+        cv_done.notify_all();
+      }
+      ev_pool.push_back(st.ev);
+      inflight.pop_front();
+      blocking = false;
+    }
+    return true;
+  }
+
   void loop() {
     (void)hipSetDevice(sv->P->device);
     for (;;) {
+      if (!retire(false)) return;
       std::vector<Req*> admitted;
+      bool any_active = false;
       {
         std::unique_lock<std::mutex> lk(mu);
-        cv.wait(lk, [&] {
-          if (stop) return true;
-          if (!queue.empty()) return true;
-          for (Req* r : active) if (r) return true;
-          return false;
-        });
-        bool any = false;
-        for (Req* r : active) any |= r != nullptr;
-        if (stop && queue.empty() && !any) break;
+        for (Req* r : active) any_active |= r != nullptr;
+        if (!any_active && queue.empty() && inflight.empty()) {
+          cv.wait(lk, [&] { return stop || !queue.empty(); });
+          if (stop && queue.empty()) break;
+        }
         for (int s = 0; s < slots && !queue.empty(); ++s) {
           if (active[s]) continue;
           Req* r = queue.front();
@@ -1311,16 +1535,24 @@ struct pepsi_serve {
           r->t_admit = now_s();
           active[s] = r;
           admitted.push_back(r);
+          any_active = true;
         }
       }
+      if (!any_active) {                   // only completions are pending
+        if (!retire(true)) return;
+        continue;
+      }
+      if ((int)inflight.size() >= kDepth && !retire(true)) return;
       for (Req* r : admitted) eng.admit(r->slot, r->cts, r->rlk, stream);
       std::vector<int> live;
       for (int s = 0; s < slots; ++s) if (active[s]) live.push_back(s);
-      std::vector<Req*> finished;
       const int na = (int)live.size();
-      if (T > 0 && na > 0) {
-        for (int i = 0; i < na; ++i) qslot_host[i] = live[i];
-        if (hipMemcpyAsync(qslot_dev.p, qslot_host, sizeof(int) * na, hipMemcpyHostToDevice, stream) != hipSuccess) {
+      Step st;
+      if (T > 0) {
+        int* hb = qslot_host + (size_t)ring * slots;      // its last reader has retired
+        ring = (ring + 1) % (kDepth + 1);
+        for (int i = 0; i < na; ++i) hb[i] = live[i];
+        if (hipMemcpyAsync(qslot_dev.p, hb, sizeof(int) * na, hipMemcpyHostToDevice, stream) != hipSuccess) {
           fail_all("slot upload failed");
           return;
         }
@@ -1340,25 +1572,30 @@ struct pepsi_serve {
         Req* r = active[s];
         if (++r->tiles >= T) {
           eng.finish(s, true, r->mask, r->out, stream);
-          finished.push_back(r);
+          st.finished.push_back(r);
+          std::lock_guard<std::mutex> lk(mu);
+          active[s] = nullptr;                           // the slot takes a new request at once
         }
       }
-      if (hipStreamSynchronize(stream) != hipSuccess) {
-        fail_all("device error in a serving step");
+      if (ev_pool.empty()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+          fail_all("event creation failed");
+          return;
+        }
+        ev_pool.push_back(e);
+      }
+      st.ev = ev_pool.back();
+      ev_pool.pop_back();
+      if (hipEventRecord(st.ev, stream) != hipSuccess) {
+        fail_all("event record failed");
         return;
       }
-      if (!finished.empty()) {
-        std::lock_guard<std::mutex> lk(mu);
-        const double t = now_s();
-        for (Req* r : finished) {
-          r->t_done = t;
-          r->done = 1;
-          active[r->slot] = nullptr;
-          ++completed;
-        }
-        cv_done.notify_all();
-      }
+      inflight.push_back(std::move(st));
     }
+    (void)retire(true);
+    while (!inflight.empty())
+      if (!retire(true)) return;
   }
 };
 
@@ -1383,7 +1620,9 @@ extern "C" int pepsi_serve_create(pepsi_server* sv, uint32_t max_active, uint64_
   int rc = sr->eng.setup(sv->P, tbq, (int)slots, sv->need_gen_multi(), sv->values_hat());
   if (!rc && sv->plane_groups) rc = sr->eng.enable_planes(sv->planes_only);
   if (!rc) rc = sr->qslot_dev.ensure(sizeof(int) * slots);
-  if (!rc && hipHostMalloc((void**)&sr->qslot_host, sizeof(int) * slots, hipHostMallocDefault) != hipSuccess)
+  sr->slot_bytes = per_slot;
+  if (!rc && hipHostMalloc((void**)&sr->qslot_host, sizeof(int) * slots * (pepsi_serve::kDepth + 1),
+                           hipHostMallocDefault) != hipSuccess)
     rc = fail(PEPSI_E_NOMEM, "pinned slot buffer");
   if (!rc && hipStreamCreateWithFlags(&sr->stream, hipStreamNonBlocking) != hipSuccess)
     rc = fail(PEPSI_E_DEVICE, "stream creation failed");
@@ -1457,6 +1696,7 @@ extern "C" int pepsi_serve_get_info(pepsi_serve* sr, pepsi_serve_info* o) {
   for (auto* r : sr->active) o->active += r != nullptr;
   o->steps = sr->steps;
   o->completed = sr->completed;
+  o->slot_bytes = sr->slot_bytes;
   return PEPSI_OK;
 }
 
@@ -1470,6 +1710,8 @@ extern "C" void pepsi_serve_destroy(pepsi_serve* sr) {
   if (sr->worker.joinable()) sr->worker.join();
   if (sr->stream) (void)hipStreamDestroy(sr->stream);
   if (sr->qslot_host) (void)hipHostFree(sr->qslot_host);
+  for (hipEvent_t e : sr->ev_pool) (void)hipEventDestroy(e);
+  for (auto& st : sr->inflight) (void)hipEventDestroy(st.ev);
   for (auto& kv : sr->reqs) delete kv.second;
   delete sr;
 }
@@ -1494,6 +1736,15 @@ extern "C" int pepsi_mod_switch(const pepsi_params* P, const uint64_t* ct, uint6
   if (!P || !ct || !out) return fail(PEPSI_E_ARG, "null argument");
   mod_switch(P->T, P->H.consts, ct, out, S(stream));
   HIPCHK(hipGetLastError());
+  return PEPSI_OK;
+}
+
+// ------------------------------------------------------------------ measurement
+extern "C" int pepsi_probe_valu(uint32_t kind, double* lane_ops_per_s) {
+  if (!lane_ops_per_s || kind > 5) return fail(PEPSI_E_ARG, "kind must be 0..5 and the output non-null");
+  const int rc = probe_valu((int)kind, lane_ops_per_s);
+  if (rc == PEPSI_E_NOMEM) return fail(rc, "probe buffer allocation failed");
+  if (rc) return fail(rc, "VALU probe failed");
   return PEPSI_OK;
 }
 
@@ -1610,3 +1861,4 @@ extern "C" int pepsi_relin(const pepsi_params* Pc, const uint64_t* ct3, const ui
   HIPCHK(hipGetLastError());
   return PEPSI_OK;
 }
+

@@ -53,6 +53,11 @@ void encode_server_planes(const Tables& T, int logn, const uint16_t* cw, int h, 
 // (out row stride ostride words between consecutive input rows, starting at limb 0 of B).
 void ext_q_to_b(const Tables& T, const Consts& hc, const uint64_t* in, uint64_t* out,
                 long ostride, int rows, uint32_t* fallback_count, hipStream_t s);
+// x = c01 + key (mod Q) for rows r = job * 2 + c (c01 [jobs][2][L][N], key [units][2][L][N] with
+// jobs_per_unit jobs per unit, both coefficient form) into xq [rows][L][N], and its centred Q -> B
+// extension into xb [rows][K][N].
+void add_ext_q_to_b(const Tables& T, const Consts& hc, const uint64_t* c01, const uint64_t* key, int jobs_per_unit,
+                    uint64_t* xq, uint64_t* xb, int rows, uint32_t* fallback_count, hipStream_t s);
 // The h factor constants of one select-and-sum ciphertext per batch: alpha[b][r][p] is
 // added to every NTT position of c0's limb p for f_r = S + Delta * [-r]_t.
 // scoef: coefficient form [nb][2][L][N] (only coefficient 0 of c0 is read).
@@ -87,7 +92,8 @@ void scale_round_first(const Tables& T, const Consts& hc, const uint64_t* d, con
 void relin_digits(const Tables& T, const Consts& hc, const uint64_t* c2, uint64_t* D, int units,
                   hipStream_t s);
 // out[job][c] = c01h[job][c] + sum_i Dhat[unit]_i * rlk_i,c (all NTT form) for the jobs_per_unit
-// jobs of each unit (job = unit * jobs_per_unit + u); c01h, out [jobs][2][L][N], Dhat
+// jobs of each unit (job = unit * jobs_per_unit + u), or the key sum alone when c01h is null;
+// c01h, out [jobs][2][L][N], Dhat
 // [units][L][L][N].  Unit u belongs to pair u / units_per_pair, pair = b * nq + q, and uses the
 // key rlk + slot(q) * rlk_stride ([L][2][L][N] each), where slot(q) = qslot[q] (device array) or
 // q when qslot is null; likewise for the other per-query arrays below.
@@ -139,6 +145,9 @@ void select_sum_planes(const Tables& T, const Consts& hc, const int8_t* Pp, cons
                        const int* qslot, int nq, int nb, int ell, uint64_t* S, hipStream_t s);
 
 // ---------------- elementwise helpers ----------------
+// p[0 .. words) = 0, and dst = src over words words, as kernels.
+void zero_words(uint64_t* p, size_t words, hipStream_t s);
+void copy_words(uint64_t* dst, const uint64_t* src, size_t words, hipStream_t s);
 // out = a * b pointwise (both [rows][L][N] NTT form, b broadcast over rows if bcast)
 void pointwise_mul(const Tables& T, const Consts& hc, const uint64_t* a, const uint64_t* b,
                    uint64_t* out, int rows, int nprimes, bool bcast, hipStream_t s);
@@ -164,5 +173,11 @@ void keygen_finish(const Tables& T, const Consts& hc, const uint64_t* s2, const 
 // elementwise (a + b) mod q_l, rows [rows][nprimes][N]
 void add_rows(const Tables& T, const Consts& hc, const uint64_t* a, const uint64_t* b, uint64_t* out,
               int rows, int nprimes, hipStream_t s);
+
+// ---------------- measurement ----------------
+// Lane operations per second of one VALU instruction kind on the current device (0
+// v_mad_u64_u32, 1 v_mul_hi_u32, 2 v_mul_lo_u32, 3 v_add_u32, 4 v_mad_u32_u24, 5 v_fma_f64);
+// synchronous; 0 or a negative status.
+int probe_valu(int kind, double* lane_ops_per_s);
 
 }  // namespace pepsi

@@ -73,3 +73,48 @@ def test_serving_budget_too_small():
     sv = pk.Server(gp, W.server_items(300, 10, 5))
     with pytest.raises(pk.PepsiError):
         pk.Serve(sv, max_active=4, hbm_budget=1 << 20)
+
+
+def test_serving_admission_by_memory():
+    """A budget of k slots' device bytes gives exactly k slots: k requests run at once, the rest
+    wait in the queue (no failure), and every result equals its single-query result."""
+    import torch
+    import paper_2310_14565_amd as pk
+    import workload as W
+    log_n, L, h, bits, n_server = 10, 3, 2, 14, 6000
+    n = 1 << log_n
+    mu = P.server_bin_bound(n_server, n)
+    cfg = PR.Config(n=n, L=L, h=h, item_bits=bits, mu=mu)
+    gp = pk.Params(log_n, L, h, bits, mu, hash_seed=cfg.hash_seed)
+    ctx = Context(n, gp.q_primes)
+    server = W.server_items(n_server, bits, 191)
+    sv = pk.Server(gp, server, cache_plaintexts=True)
+    qs = make_queries(ctx, cfg, server, 7, 707)
+    dev = [dict(cts=to_dev(q["cts"]), rlk=to_dev(q["rlk"]), mask=None if q["mask"] is None else to_dev(q["mask"]),
+                out=empty((2, L, n), np.uint64)) for q in qs]
+    alone = []
+    for d in dev:
+        o = empty((2, L, n), np.uint64)
+        sv.eval(d["cts"], d["rlk"], d["mask"], o)
+        alone.append(to_host(o, np.uint64))
+    probe = pk.Serve(sv, max_active=1)
+    per_slot = probe.info().slot_bytes
+    probe.close()
+    assert per_slot > 0
+    k = 3
+    srv = pk.Serve(sv, max_active=0, hbm_budget=k * per_slot + per_slot // 2)
+    assert srv.info().slots == k
+    ids = [srv.submit(d["cts"], d["rlk"], d["mask"], d["out"]) for d in dev]
+    queued_seen = srv.info().queued
+    stats = [srv.wait(i) for i in ids]
+    info = srv.info()
+    srv.close()
+    say(f"admission by memory: {per_slot} bytes per slot, {info.slots} slots, {queued_seen} queued at first")
+    assert info.completed == len(dev) and info.queued == 0
+    assert queued_seen >= 1                             # requests beyond the slots waited in the queue
+    assert {s.slot for s in stats} == set(range(k))     # every slot used, none beyond the budget
+    admits = sorted(s.admit_s for s in stats)
+    assert admits[k] > admits[k - 1]                    # the (k+1)-th request waited for a slot
+    for i, d in enumerate(dev):
+        assert (to_host(d["out"], np.uint64) == alone[i]).all(), f"request {i}"
+

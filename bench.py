@@ -81,6 +81,38 @@ def traffic_record(kernel: str):
     return rec
 
 
+# The lazy Shoup butterfly on 32-bit lanes (the NTT's per-butterfly minimum): the truncated quotient
+# takes two high 32 x 32 products and one 32 x 32 -> 64 multiply-add, the low 64 bits of x w - q p two
+# multiply-adds and four low products, and the sums (two three-input adds, one add, U + V, U - V + 4p)
+# eight single-issue operations.
+BUTTERFLY_MIX = {"v_mad_u64_u32": 3, "v_mul_hi_u32": 2, "v_mul_lo_u32": 4, "v_add_u32": 8}
+CHIP_LANE_ISSUE = 256 * 64 * 2.4e9          # 256 CUs x 64 lanes x 2.4 GHz, one VALU op per lane per clock
+
+
+def valu_roofline(pk, tm, n):
+    """Integer-VALU roofline of the transforms: measured issue rates of the butterfly's instructions
+    (pepsi_probe_valu) give the peak butterfly rate; the engine's event-timed transforms of the timed
+    steps give the achieved one."""
+    rates = {k: pk.probe_valu(i) for i, k in enumerate(pk.VALU_KINDS)}
+    sec_per_bfly = sum(cnt / rates[k] for k, cnt in BUTTERFLY_MIX.items())   # per lane, whole chip
+    peak = 1.0 / sec_per_bfly
+    logn = n.bit_length() - 1
+    out = {"valu_probe_T_lane_ops_per_s": {k: round(v / 1e12, 3) for k, v in rates.items()},
+           "chip_lane_issue_T_per_s": round(CHIP_LANE_ISSUE / 1e12, 2),
+           "butterfly_mix": BUTTERFLY_MIX}
+    for name, rows, ms, launches in (("k_ntt_fwd", tm.ntt_fwd_rows, tm.ntt_fwd_ms, tm.ntt_fwd_launches),
+                                     ("k_ntt_inv", tm.ntt_inv_rows, tm.ntt_inv_ms, tm.ntt_inv_launches)):
+        if not launches or ms <= 0:
+            continue
+        bfly = rows * (n // 2) * logn
+        achieved = bfly / (ms / 1e3)
+        out[name] = {"bound": "alu", "achieved": round(achieved / 1e9, 1), "peak": round(peak / 1e9, 1),
+                     "unit": "Gbutterfly/s", "frac": round(achieved / peak, 4),
+                     "avg_launch_ms": round(ms / launches, 4), "rows_per_launch": round(rows / launches, 1),
+                     "ns_per_row": round(1e6 * ms / rows, 2)}
+    return out
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -760,6 +792,7 @@ def main():
                        "value_computed_batches counts only the batches the kernels run"),
         "check": {"cardinality": card, "noise_budget_bits": budget},
     }
+    line["roofline_valu"] = valu_roofline(pk, tm, n)
     line["compression"] = compression_leg(params, out, args.seed + 17)
     if args.copy_calibration > 0:
         words = (args.copy_calibration << 20) // 8

@@ -450,6 +450,18 @@ int pepsi_select_sum(const pepsi_params* params, const uint64_t* d_cts, const ui
  * d_x, d_y [2][L][N]; d_out [3][L][N]. */
 int pepsi_multiply(const pepsi_params* params, const uint64_t* d_x, const uint64_t* d_y,
                    uint64_t* d_out, void* stream);
+/* The product of pepsi_multiply, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): its scratch (the operands
+ * extended to the auxiliary base and the tensor, 8 (4 L N + 4 K N + 3 (L + K) N) bytes) lives in a
+ * fixed 8 MiB device array of the library, of which each GPU holds its own copy until the process
+ * ends; the call allocates and frees nothing and does not synchronise.  Parameter sets whose
+ * scratch exceeds 8 MiB (e.g. N = 16384 with 8 primes) are refused with PEPSI_E_ARG before any
+ * device work; N = 8192 with 4 primes takes 4.1 MB.  Every call on one GPU shares that GPU's array:
+ * calls that overlap on one GPU (several streams or threads) race and must be serialised by the
+ * caller.  Must run on the device the parameters were created on.  Same arguments and result as
+ * pepsi_multiply. */
+int pepsi_multiply_noalloc(const pepsi_params* params, const uint64_t* d_x, const uint64_t* d_y,
+                           uint64_t* d_out, void* stream);
 /* Relinearisation with the RNS gadget: digits D_i = [d2 (Q/q_i)^-1]_{q_i} in
  * [0, q_i); out = (d0 + sum_i D_i rlk_i0, d1 + sum_i D_i rlk_i1).
  * d_ct3 [3][L][N], d_rlk [L][2][L][N], d_out [2][L][N]. */

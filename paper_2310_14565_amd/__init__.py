@@ -139,6 +139,7 @@ _SIGS = {
     "pepsi_decode": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]),
     "pepsi_select_sum": (C.c_int, [C.c_void_p] * 5),
     "pepsi_multiply": (C.c_int, [C.c_void_p] * 5),
+    "pepsi_multiply_noalloc": (C.c_int, [C.c_void_p] * 5),
     "pepsi_relin": (C.c_int, [C.c_void_p] * 5),
 }
 
@@ -304,6 +305,10 @@ class Params:
 
     def multiply(self, x, y, out, stream=None):
         _check(lib().pepsi_multiply(self._h, _dev(x), _dev(y), _dev(out), _stream(stream)))
+
+    def multiply_noalloc(self, x, y, out, stream=None):
+        """pepsi_multiply without device allocation (scratch in the library's fixed array)."""
+        _check(lib().pepsi_multiply_noalloc(self._h, _dev(x), _dev(y), _dev(out), _stream(stream)))
 
     def relin(self, ct3, rlk, out, stream=None):
         _check(lib().pepsi_relin(self._h, _dev(ct3), _dev(rlk), _dev(out), _stream(stream)))

@@ -1862,3 +1862,66 @@ extern "C" int pepsi_relin(const pepsi_params* Pc, const uint64_t* ct3, const ui
   return PEPSI_OK;
 }
 
+// ------------------------------------------------------------------ allocation-free product
+// Scratch memory of pepsi_multiply_noalloc: a file-scope device array, of which every GPU the
+// library runs on holds its own copy until the process ends.  Its name is a host-side stand-in
+// in host code, so host code never passes it to a kernel: it takes each device's address of the
+// array from hipGetSymbolAddress on the first call on that device, and uses that address only.
+static constexpr size_t kNoAllocScratchBytes = (size_t)8 << 20;
+static __device__ __align__(256) uint64_t scratch[kNoAllocScratchBytes / 8];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint64_t* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's address of the scratch array (looked up once per device).
+int scratch_of_current_device(uint64_t** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(PEPSI_E_DEVICE, "device %d beyond the scratch table", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = static_cast<uint64_t*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return 0;
+}
+}  // namespace
+
+extern "C" int pepsi_multiply_noalloc(const pepsi_params* P, const uint64_t* x, const uint64_t* y, uint64_t* out,
+                                      void* stream) {
+  if (!P || !x || !y || !out) return fail(PEPSI_E_ARG, "null argument");
+  const HostParams& H = P->H;
+  const size_t n = H.n, L = H.L, K = H.K, Pn = L + K;
+  const size_t w_q = 2 * L * n, w_b = 2 * K * n, w_d = 3 * Pn * n;
+  const size_t need = (2 * w_q + 2 * w_b + w_d) * 8;
+  if (need > kNoAllocScratchBytes)
+    return fail(PEPSI_E_ARG, "this product needs %zu bytes of scratch; the allocation-free buffer holds %zu "
+                "(N = %zu, %zu + %zu primes)", need, kNoAllocScratchBytes, n, L, K);
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev != P->device) return fail(PEPSI_E_ARG, "call on the device the parameters were created on");
+  uint64_t* base = nullptr;
+  int rc = scratch_of_current_device(&base);
+  if (rc) return rc;
+  uint64_t* xq = base;
+  uint64_t* yq = xq + w_q;
+  uint64_t* xb = yq + w_q;
+  uint64_t* yb = xb + w_b;
+  uint64_t* dd = yb + w_b;
+  hipStream_t s = S(stream);
+  ext_q_to_b(P->T, H.consts, x, xb, (long)(K * n), 2, P->fallback.as<uint32_t>(), s);
+  ext_q_to_b(P->T, H.consts, y, yb, (long)(K * n), 2, P->fallback.as<uint32_t>(), s);
+  ntt_forward(P->T, H.logn, x, LOAD_U64, xq, STORE_U64, (int)(2 * L), (int)L, 0, s);
+  ntt_forward(P->T, H.logn, y, LOAD_U64, yq, STORE_U64, (int)(2 * L), (int)L, 0, s);
+  ntt_forward(P->T, H.logn, xb, LOAD_U64, xb, STORE_U64, (int)(2 * K), (int)K, (int)L, s);
+  ntt_forward(P->T, H.logn, yb, LOAD_U64, yb, STORE_U64, (int)(2 * K), (int)K, (int)L, s);
+  tensor_one(P->T, H.consts, TensorJob{xq, xb, yq, yb, nullptr, nullptr, dd}, s);
+  ntt_inverse(P->T, H.logn, dd, dd, (int)(3 * Pn), (int)Pn, 0, s);
+  scale_round(P->T, H.consts, dd, out, out + 2 * L * n, 1, P->fallback.as<uint32_t>(), s);
+  HIPCHK(hipGetLastError());
+  return PEPSI_OK;
+}

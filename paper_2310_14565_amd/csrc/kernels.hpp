@@ -73,6 +73,8 @@ struct TensorJob {
   const uint64_t* ax; const uint64_t* ay; uint64_t* d;
 };
 void tensor(const Tables& T, const Consts& hc, const TensorJob* jobs_dev, int njobs, hipStream_t s);
+// the same for one job given by value
+void tensor_one(const Tables& T, const Consts& hc, const TensorJob& job, hipStream_t s);
 // First tree level: d[p] = (X0^2, 2 X0 X1, X1^2) over Q u B for each pair's select-and-sum X,
 // given in NTT form as xq [pairs][2][L][N] and xb [pairs][2][K][N]; d [pairs][3][L+K][N].
 void square_products(const Tables& T, const Consts& hc, const uint64_t* xq, const uint64_t* xb, uint64_t* d,

@@ -318,6 +318,14 @@ __global__ void __launch_bounds__(TPB) k_tensor(Tables T, const TensorJob* __res
   tensor_at(C, jobs[blockIdx.z], k, (int)blockIdx.y);
 }
 
+// One tensor job passed by value (no job array in device memory).
+__global__ void __launch_bounds__(TPB) k_tensor_one(Tables T, TensorJob J) {
+  const Consts& C = *T.c;
+  const int k = blockIdx.x * TPB + threadIdx.x;
+  if (k >= C.n) return;
+  tensor_at(C, J, k, (int)blockIdx.y);
+}
+
 // First tree level.  Every factor is f_r = X + delta_r (X the select-and-sum ciphertext, delta_r
 // an integer added to coefficient 0 of c0, the exact difference of the centred lifts), so over
 // the integers
@@ -1243,6 +1251,9 @@ void factor_constants(const Tables& T, const Consts& hc, const uint64_t* scoef, 
 void tensor(const Tables& T, const Consts& hc, const TensorJob* jobs, int njobs, hipStream_t s) {
   if (njobs <= 0) return;
   hipLaunchKernelGGL(k_tensor, grid_for(hc.n, hc.L + hc.K, njobs), dim3(TPB), 0, s, T, jobs);
+}
+void tensor_one(const Tables& T, const Consts& hc, const TensorJob& job, hipStream_t s) {
+  hipLaunchKernelGGL(k_tensor_one, grid_for(hc.n, hc.L + hc.K), dim3(TPB), 0, s, T, job);
 }
 void square_products(const Tables& T, const Consts& hc, const uint64_t* xq, const uint64_t* xb, uint64_t* d,
                      int pairs, hipStream_t s) {

@@ -504,11 +504,21 @@ struct Engine {
   }
 
   // Transforms of the engine, event-timed (rows per launch) while the server's timer is on.
-  void tfwd(const void* in, void* out, int rows, int nprimes, int first, hipStream_t s) {
+  void tfwd(const void* in, void* out, int rows, int nprimes, int first, hipStream_t s, NttLoad ld = LOAD_U64) {
     hipEvent_t a = nullptr, b = nullptr;
     if (timer && timer->on && rows > 0) { a = timer->get(); b = timer->get(); (void)hipEventRecord(a, s); }
-    ntt_forward(P->T, P->H.logn, in, LOAD_U64, out, STORE_U64, rows, nprimes, first, s);
+    ntt_forward(P->T, P->H.logn, in, ld, out, STORE_U64, rows, nprimes, first, s);
     if (a) { (void)hipEventRecord(b, s); timer->pending.push_back({a, b, 2, (uint64_t)rows}); }
+  }
+  // inverse transforms of products formed while loading (INV_SQUARES of the pairs' X, or
+  // INV_TENSOR of the jobs) into d [units][3][L + K][N]
+  void tinv_products(InvProducts mode, const uint64_t* xq, const uint64_t* xb, const TensorJob* jobs, uint64_t* out,
+                     int units, hipStream_t s) {
+    const int Pn = P->H.L + P->H.K, rows = units * 3 * Pn;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (timer && timer->on && rows > 0) { a = timer->get(); b = timer->get(); (void)hipEventRecord(a, s); }
+    ntt_inverse_products(P->T, P->H.logn, mode, xq, xb, jobs, out, units, Pn, s);
+    if (a) { (void)hipEventRecord(b, s); timer->pending.push_back({a, b, 3, (uint64_t)rows}); }
   }
   void tinv(const uint64_t* in, uint64_t* out, int rows, int nprimes, int first, hipStream_t s) {
     hipEvent_t a = nullptr, b = nullptr;
@@ -624,8 +634,8 @@ struct Engine {
     const HostParams& H = P->H;
     const int L = H.L, K = H.K;
     const int njobs = units * jobs_per_unit;
-    relin_digits(P->T, H.consts, c2.as<uint64_t>(), D.as<uint64_t>(), units, s);
-    tfwd(D.p, D.p, units * L * L, L, 0, s);
+    // the digits of component 2 are formed while their transform loads c2
+    tfwd(c2.p, D.p, units * L * L, L, 0, s, LOAD_DIGITS);
     const uint64_t* key = rlkhat.as<uint64_t>((size_t)key_slot * rstride());
     if (ext_out) {
       // The next level needs the results in coefficient form too (for their extension to B).
@@ -649,26 +659,23 @@ struct Engine {
   }
 
   // First tree level of npairs pairs: the h / 2 products (f_2u, f_2u+1) of each pair share the
-  // products of S (k_square), one inverse NTT of them and one component 2 (so one
-  // relinearisation sum).  Leaves the rescaled products in c01 / c2.
+  // products of S (formed while their inverse transform loads S), one inverse transform of them
+  // and one component 2 (so one relinearisation sum).  Leaves the rescaled products in c01 / c2.
   void first_level(const uint64_t* Sq, int npairs, hipStream_t s) {
     const HostParams& H = P->H;
-    const int Pn = H.L + H.K;
     uint64_t* dd = d.as<uint64_t>();
-    square_products(P->T, H.consts, Sq, sbh.as<uint64_t>(), dd, npairs, s);
-    tinv(dd, dd, npairs * 3 * Pn, Pn, 0, s);
+    tinv_products(INV_SQUARES, Sq, sbh.as<uint64_t>(), nullptr, dd, npairs, s);
     scale_round_first(P->T, H.consts, dd, scoef.as<uint64_t>(), sb.as<uint64_t>(), alpha.as<uint64_t>(),
                       pconst.as<uint64_t>(), H.h, npairs, c01.as<uint64_t>(), c2.as<uint64_t>(),
                       P->fallback.as<uint32_t>(), s);
   }
 
-  // A later tree level: njobs independent products (TensorJob operands) into c01 / c2.
+  // A later tree level: njobs independent products (TensorJob operands, tensored while their
+  // inverse transform loads them) into c01 / c2.
   void later_level(const TensorJob* dev_jobs, int njobs, hipStream_t s) {
     const HostParams& H = P->H;
-    const int Pn = H.L + H.K;
     uint64_t* dd = d.as<uint64_t>();
-    tensor(P->T, H.consts, dev_jobs, njobs, s);
-    tinv(dd, dd, njobs * 3 * Pn, Pn, 0, s);
+    tinv_products(INV_TENSOR, nullptr, nullptr, dev_jobs, dd, njobs, s);
     scale_round(P->T, H.consts, dd, c01.as<uint64_t>(), c2.as<uint64_t>(), njobs, P->fallback.as<uint32_t>(), s);
   }
 
@@ -828,11 +835,10 @@ struct Engine {
       } else {
         // The last level's relinearisation is linear in (c01, D), so both are summed over the
         // batches (coefficient form, one entry per pair) and the key is applied once per query.
-        relin_digits(P->T, H.consts, c2.as<uint64_t>(), D.as<uint64_t>(), npairs, s);
         accumulate(P->T, H.consts, c01.as<uint64_t>(), (long)(2 * L * n), nb, nq, 2 * (int)L, acc_slot, acc_base,
                    (long)ctw(), s);
-        accumulate(P->T, H.consts, D.as<uint64_t>(), (long)(L * L * n), nb, nq, (int)(L * L), acc_slot,
-                   accD.as<uint64_t>(acc_q * dtw()), (long)dtw(), s);
+        accumulate_digits(P->T, H.consts, c2.as<uint64_t>(), (long)(L * n), nb, nq, acc_slot,
+                          accD.as<uint64_t>(acc_q * dtw()), (long)dtw(), s);
       }
     }
   }

@@ -11,7 +11,7 @@ namespace pepsi {
 // Row r of a [rows][N] array is transformed modulo prime (first + r % nprimes).
 // Forward: coefficient order in, bit-reversed evaluation order out:
 //   out[k] = a(psi^(2 brv(k) + 1)).   Inverse: the exact inverse.
-enum NttLoad { LOAD_U64 = 0, LOAD_LIFT_T = 1, LOAD_I8 = 2, LOAD_I32 = 3 };
+enum NttLoad { LOAD_U64 = 0, LOAD_LIFT_T = 1, LOAD_I8 = 2, LOAD_I32 = 3, LOAD_DIGITS = 4 };
 enum NttStore { STORE_U64 = 0, STORE_PLAINTEXT = 1 };
 
 // Server plaintexts in NTT form (STORE_PLAINTEXT).  Each residue is split into 27-bit halves (low
@@ -27,7 +27,9 @@ struct PtLayout { int ell = 0, gs = 0, bbase = 0; };
 
 // in: LOAD_U64 -> const uint64_t[rows][N]; LOAD_LIFT_T -> const uint32_t[rows / nprimes][N]
 // (a plaintext mod t, lifted to its centred representative); LOAD_I8 / LOAD_I32 -> small
-// signed integers [rows / nprimes][N].
+// signed integers [rows / nprimes][N]; LOAD_DIGITS -> the relinearisation digits of component-2
+// rows c2 [units][L][N] (coefficient form), formed while loading: row r of [units][L][L] (with
+// nprimes = L) is D_i = [c2_i (Q/q_i)^-1]_{q_i} taken mod q_j, i = (r / L) % L, j = r % L.
 void ntt_forward(const Tables& T, int logn, const void* in, NttLoad load, void* out,
                  NttStore store, int rows, int nprimes, int first, hipStream_t s);
 // Plaintext rows mod t ([nb][ell][N] u32) lifted, transformed over q_0..q_{L-1} and stored into a
@@ -36,6 +38,16 @@ void ntt_forward_plaintexts(const Tables& T, int logn, const uint32_t* in, uint6
                             const PtLayout& pl, hipStream_t s);
 void ntt_inverse(const Tables& T, int logn, const uint64_t* in, uint64_t* out, int rows,
                  int nprimes, int first, hipStream_t s);
+// Inverse transforms of ciphertext products over Q u B formed while loading (P = L + K primes,
+// rows [units][3][P] into out [units][3][P][N]):
+//   INV_SQUARES: unit = pair, the products (X0^2, 2 X0 X1, X1^2) of X given in NTT form as
+//                xq [pairs][2][L][N] and xb [pairs][2][K][N];
+//   INV_TENSOR:  unit = job, the tensor (x0 y0, x0 y1 + x1 y0, x1 y1) of TensorJob jobs[job]
+//                (with its constants added to c0).
+struct TensorJob;
+enum InvProducts { INV_SQUARES = 1, INV_TENSOR = 2 };
+void ntt_inverse_products(const Tables& T, int logn, InvProducts mode, const uint64_t* xq, const uint64_t* xb,
+                          const TensorJob* jobs, uint64_t* out, int units, int nprimes, hipStream_t s);
 
 // ---------------- batching over Z_t ----------------
 // slots (natural order, slot k <-> psi_t^(2k+1)) -> plaintext polynomial, coefficients in [0, t)
@@ -145,6 +157,12 @@ void plaintext_planes(const Tables& T, const Consts& hc, const uint64_t* P, int 
 void request_planes(const Tables& T, const Consts& hc, const uint64_t* ch, int ell, int8_t* out, hipStream_t s);
 void select_sum_planes(const Tables& T, const Consts& hc, const int8_t* Pp, const int8_t* Cp, long cps,
                        const int* qslot, int nq, int nb, int ell, uint64_t* S, hipStream_t s);
+
+// acc[slot(q)] [L][L][N] += sum over b < nb of the relinearisation digits of the component-2
+// rows c2[b * nq + q] ([L][N], cstride words apart): entry (i, j) adds [c2_i (Q/q_i)^-1]_{q_i}
+// taken mod q_j (coefficient form).
+void accumulate_digits(const Tables& T, const Consts& hc, const uint64_t* c2, long cstride, int nb, int nq,
+                       const int* qslot, uint64_t* acc, long astride, hipStream_t s);
 
 // ---------------- elementwise helpers ----------------
 // p[0 .. words) = 0, and dst = src over words words, as kernels.

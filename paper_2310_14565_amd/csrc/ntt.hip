@@ -171,10 +171,18 @@ __device__ __forceinline__ void inv_passes(uint64_t* x, uint64_t* lds, int tid,
 }
 
 template <NttLoad LD>
-__device__ __forceinline__ uint64_t load_elem(const void* in, size_t row, int nprimes, int N,
+__device__ __forceinline__ uint64_t load_elem(const Consts& C, const void* in, size_t row, int nprimes, int N,
                                               int j, uint64_t p) {
   if constexpr (LD == LOAD_U64) {
     return static_cast<const uint64_t*>(in)[row * N + j];
+  } else if constexpr (LD == LOAD_DIGITS) {
+    // D_i = [c2_i (Q/q_i)^-1]_{q_i} < q_i < 2 q_j, reduced mod q_j = p by one subtraction
+    const int L = nprimes;
+    const int i = (int)((row / L) % L);
+    const size_t unit = row / ((size_t)L * L);
+    const uint64_t v = static_cast<const uint64_t*>(in)[(unit * L + i) * N + j];
+    const uint64_t d = shoup(v, C.qhat_inv[i], C.qhat_inv_shoup[i], C.prm[i].p);
+    return d >= p ? d - p : d;
   } else if constexpr (LD == LOAD_LIFT_T) {
     const uint32_t v = static_cast<const uint32_t*>(in)[(row / nprimes) * N + j];
     return v <= (PEPSI_T - 1) / 2 ? (uint64_t)v : p - (uint64_t)(PEPSI_T - v);
@@ -220,7 +228,7 @@ k_ntt_fwd(Tables T, const void* __restrict__ in, void* __restrict__ out, int npr
   const int tid = threadIdx.x;
   uint64_t x[E];
 #pragma unroll
-  for (int m = 0; m < E; ++m) x[m] = load_elem<LD>(in, row, nprimes, N, m * TT + tid, p);
+  for (int m = 0; m < E; ++m) x[m] = load_elem<LD>(*T.c, in, row, nprimes, N, m * TT + tid, p);
   fwd_pass<LOGN, EL, 0, EL>(x, tid, W, Wq, p);
   to_lds<LOGN, EL, 0, EL>(lds, x, tid);
   fwd_passes<LOGN, EL, EL, KEEP>(x, lds, tid, W, Wq, p);
@@ -243,9 +251,68 @@ k_ntt_fwd(Tables T, const void* __restrict__ in, void* __restrict__ out, int npr
   }
 }
 
-template <int LOGN, int EL = ntt_el<LOGN>()>
+// Where an inverse transform's input words come from: a plain row, or a component of a
+// ciphertext product over Q u B formed on the fly (InvProducts).  The row's unit, component and
+// prime are uniform over the workgroup.
+struct InvSrc { const uint64_t* xq; const uint64_t* xb; const TensorJob* jobs; };
+template <int IL>
+struct InvRow {
+  const uint64_t* in;
+  size_t row;
+  // product rows: the operands' limb rows and the constants added to c0
+  const uint64_t *x0, *x1, *y0, *y1;
+  uint64_t ax, ay;
+  int comp;
+  Prime pr;
+  __device__ __forceinline__ InvRow(const Consts& C, const uint64_t* in_, size_t row_, const InvSrc& src, int N)
+      : in(in_), row(row_) {
+    if constexpr (IL != 0) {
+      const int L = C.L, K = C.K, P = L + K;
+      const int p = (int)(row % P);
+      comp = (int)((row / P) % 3);
+      const size_t unit = row / ((size_t)3 * P);
+      pr = C.prm[p];
+      ax = ay = 0;
+      if constexpr (IL == INV_SQUARES) {
+        const uint64_t* base = p < L ? src.xq + (unit * 2 * L + p) * N : src.xb + (unit * 2 * K + (p - L)) * N;
+        const size_t cstep = (size_t)(p < L ? L : K) * N;
+        x0 = y0 = base;
+        x1 = y1 = base + cstep;
+      } else {
+        const TensorJob J = src.jobs[unit];
+        const size_t a0 = p < L ? (size_t)p * N : (size_t)(p - L) * N;
+        const size_t cstep = (size_t)(p < L ? L : K) * N;
+        const uint64_t* xs = p < L ? J.xq : J.xb;
+        const uint64_t* ys = p < L ? J.yq : J.yb;
+        x0 = xs + a0; x1 = xs + a0 + cstep;
+        y0 = ys + a0; y1 = ys + a0 + cstep;
+        if (J.ax) ax = J.ax[p];
+        if (J.ay) ay = J.ay[p];
+      }
+    }
+  }
+  __device__ __forceinline__ uint64_t at(int N, int j) const {
+    if constexpr (IL == 0) {
+      return in[row * N + j];
+    } else if constexpr (IL == INV_SQUARES) {
+      const uint64_t a = x0[j], b = x1[j];
+      if (comp == 0) return mulmod(a, a, pr);
+      if (comp == 1) return mulmod(addmod(a, a, pr.p), b, pr);
+      return mulmod(b, b, pr);
+    } else {
+      if (comp == 2) return mulmod(x1[j], y1[j], pr);
+      const uint64_t a = ax ? addmod(x0[j], ax, pr.p) : x0[j];
+      const uint64_t c = ay ? addmod(y0[j], ay, pr.p) : y0[j];
+      if (comp == 0) return mulmod(a, c, pr);
+      const u128 m = (u128)a * y1[j] + (u128)x1[j] * c;
+      return reduce116((uint64_t)m, (uint64_t)(m >> 64), pr);
+    }
+  }
+};
+
+template <int LOGN, int IL = 0, int EL = ntt_el<LOGN>()>
 __global__ void __launch_bounds__((1 << LOGN) >> EL)
-k_ntt_inv(Tables T, const uint64_t* __restrict__ in, uint64_t* __restrict__ out, int nprimes, int first) {
+k_ntt_inv(Tables T, const uint64_t* __restrict__ in, uint64_t* __restrict__ out, int nprimes, int first, InvSrc src) {
   constexpr int N = 1 << LOGN, E = 1 << EL, TT = N >> EL, NP = (LOGN + EL - 1) / EL;
   constexpr int SL = (NP - 1) * EL, DL = LOGN - SL;   // first inverse pass: stages [SL, LOGN)
   __shared__ uint64_t lds[N + N / 32];
@@ -255,6 +322,7 @@ k_ntt_inv(Tables T, const uint64_t* __restrict__ in, uint64_t* __restrict__ out,
   const uint64_t* W = T.ipsi_rev + (size_t)pidx * N;
   const uint64_t* Wq = T.ipsi_rev_shoup + (size_t)pidx * N;
   const int tid = threadIdx.x;
+  const InvRow<IL> src_row(*T.c, in, row, src, N);
   uint64_t x[E];
   if constexpr (ntt_direct(DL) && NP > 2) {
     // Runs of 2^DL consecutive inputs go straight to registers for the first pass.
@@ -262,7 +330,7 @@ k_ntt_inv(Tables T, const uint64_t* __restrict__ in, uint64_t* __restrict__ out,
     for (int u = 0; u < (1 << (EL - DL)); ++u)
 #pragma unroll
       for (int m = 0; m < (1 << DL); ++m)
-        x[u * (1 << DL) + m] = in[row * N + elem_index<LOGN, EL, SL, DL>(tid, u, m)];
+        x[u * (1 << DL) + m] = src_row.at(N, elem_index<LOGN, EL, SL, DL>(tid, u, m));
     inv_pass<LOGN, EL, SL, DL, true>(x, tid, W, Wq, p);
     to_lds<LOGN, EL, SL, DL>(lds, x, tid);
     inv_passes<LOGN, EL, NP - 2>(x, lds, tid, W, Wq, p);
@@ -270,7 +338,7 @@ k_ntt_inv(Tables T, const uint64_t* __restrict__ in, uint64_t* __restrict__ out,
 #pragma unroll
     for (int m = 0; m < E; ++m) {
       const int j = m * TT + tid;
-      lds[lds_idx(j)] = in[row * N + j];
+      lds[lds_idx(j)] = src_row.at(N, j);
     }
     inv_passes<LOGN, EL, NP - 1>(x, lds, tid, W, Wq, p);
   }
@@ -434,6 +502,7 @@ void launch_fwd(const Tables& T, const void* in, NttLoad ld, void* out, NttStore
       case LOAD_LIFT_T: PEPSI_FWD(LOAD_LIFT_T, STORE_U64); break;
       case LOAD_I8: PEPSI_FWD(LOAD_I8, STORE_U64); break;
       case LOAD_I32: PEPSI_FWD(LOAD_I32, STORE_U64); break;
+      case LOAD_DIGITS: PEPSI_FWD(LOAD_DIGITS, STORE_U64); break;
     }
   } else {
     if (ld == LOAD_LIFT_T) PEPSI_FWD(LOAD_LIFT_T, STORE_PLAINTEXT);
@@ -468,16 +537,35 @@ void ntt_forward_plaintexts(const Tables& T, int logn, const uint32_t* in, uint6
   }
 }
 
+template <int IL>
+void launch_inv(const Tables& T, int logn, const uint64_t* in, uint64_t* out, int rows, int nprimes, int first,
+                const InvSrc& src, hipStream_t s) {
+#define PEPSI_INV(LL) hipLaunchKernelGGL((k_ntt_inv<LL, IL>), dim3(rows), dim3((1 << LL) >> ntt_el<LL>()), 0, s, T, in, \
+                                         out, nprimes, first, src)
+  switch (logn) {
+    case 10: PEPSI_INV(10); break;
+    case 11: PEPSI_INV(11); break;
+    case 12: PEPSI_INV(12); break;
+    case 13: PEPSI_INV(13); break;
+    case 14: PEPSI_INV(14); break;
+  }
+#undef PEPSI_INV
+}
+
 void ntt_inverse(const Tables& T, int logn, const uint64_t* in, uint64_t* out, int rows, int nprimes,
                  int first, hipStream_t s) {
   if (rows <= 0) return;
-    switch (logn) {
-    case 10: hipLaunchKernelGGL(k_ntt_inv<10>, dim3(rows), dim3((1 << 10) >> ntt_el<10>()), 0, s, T, in, out, nprimes, first); break;
-    case 11: hipLaunchKernelGGL(k_ntt_inv<11>, dim3(rows), dim3((1 << 11) >> ntt_el<11>()), 0, s, T, in, out, nprimes, first); break;
-    case 12: hipLaunchKernelGGL(k_ntt_inv<12>, dim3(rows), dim3((1 << 12) >> ntt_el<12>()), 0, s, T, in, out, nprimes, first); break;
-    case 13: hipLaunchKernelGGL(k_ntt_inv<13>, dim3(rows), dim3((1 << 13) >> ntt_el<13>()), 0, s, T, in, out, nprimes, first); break;
-    case 14: hipLaunchKernelGGL(k_ntt_inv<14>, dim3(rows), dim3((1 << 14) >> ntt_el<14>()), 0, s, T, in, out, nprimes, first); break;
-  }
+  launch_inv<0>(T, logn, in, out, rows, nprimes, first, InvSrc{nullptr, nullptr, nullptr}, s);
+}
+
+void ntt_inverse_products(const Tables& T, int logn, InvProducts mode, const uint64_t* xq, const uint64_t* xb,
+                          const TensorJob* jobs, uint64_t* out, int units, int nprimes, hipStream_t s) {
+  const int rows = units * 3 * nprimes;
+  if (rows <= 0) return;
+  if (mode == INV_SQUARES)
+    launch_inv<INV_SQUARES>(T, logn, nullptr, out, rows, nprimes, 0, InvSrc{xq, xb, nullptr}, s);
+  else
+    launch_inv<INV_TENSOR>(T, logn, nullptr, out, rows, nprimes, 0, InvSrc{nullptr, nullptr, jobs}, s);
 }
 
 #define PEPSI_T_DISPATCH(KERNEL, ...)                                                          \

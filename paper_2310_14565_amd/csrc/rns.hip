@@ -558,6 +558,46 @@ __global__ void __launch_bounds__(ATPB) k_accumulate(Tables T, const uint64_t* _
   a[(size_t)cl * N + k] = s;
 }
 
+// acc[slot(q)] [i][j] += sum over batches b of the relinearisation digit D_i of c2[b * nq + q],
+// taken mod q_j (the digits are formed here, not stored): D_i = [c2_i (Q/q_i)^-1]_{q_i}.
+template <int L>
+__global__ void __launch_bounds__(ATPB) k_accumulate_digits(Tables T, const uint64_t* __restrict__ c2, long cstride,
+                                                           int nb, int nq, const int* __restrict__ qslot,
+                                                           uint64_t* __restrict__ acc, long astride) {
+  const Consts& C = *T.c;
+  const int N = C.n;
+  const int k = blockIdx.x * ATPB + threadIdx.x;
+  const int ij = blockIdx.y, i = ij / L, j = ij % L;
+  const int q = blockIdx.z;
+  if (k >= N) return;
+  const Prime& pr = C.prm[j];
+  const uint64_t qi = C.prm[i].p, w = C.qhat_inv[i], wq = C.qhat_inv_shoup[i], qj = pr.p;
+  uint64_t* a = acc + (size_t)(qslot ? qslot[q] : q) * astride;
+  uint64_t s = a[(size_t)ij * N + k];
+  const uint64_t* src = c2 + (size_t)i * N + k;
+  int b = 0;
+  while (b < nb) {
+    u128 t = s;
+    const int end = min(nb, b + 1000);             // 1000 * 2^54 stays below 2^116
+    for (; b + AU <= end; b += AU) {
+      uint64_t v[AU];
+#pragma unroll
+      for (int u = 0; u < AU; ++u) v[u] = src[((size_t)(b + u) * nq + q) * cstride];
+#pragma unroll
+      for (int u = 0; u < AU; ++u) {
+        const uint64_t d = shoup(v[u], w, wq, qi);
+        t += d >= qj ? d - qj : d;
+      }
+    }
+    for (; b < end; ++b) {
+      const uint64_t d = shoup(src[((size_t)b * nq + q) * cstride], w, wq, qi);
+      t += d >= qj ? d - qj : d;
+    }
+    s = reduce116((uint64_t)t, (uint64_t)(t >> 64), pr);
+  }
+  a[(size_t)ij * N + k] = s;
+}
+
 // acc[slot(q)] += sum over batches b of x[b * nq + q] (.) vhat[b]: the server values of each
 // batch (NTT form [L][N], one plaintext per batch) times that batch's equality ciphertexts
 // (NTT form [2][L][N], xstride words apart), accumulated per query (NTT form).
@@ -1301,6 +1341,12 @@ void accumulate(const Tables& T, const Consts& hc, const uint64_t* x, long xstri
   if (nb <= 0 || nq <= 0 || rows <= 0) return;
   hipLaunchKernelGGL(k_accumulate, dim3((hc.n + ATPB - 1) / ATPB, rows, nq), dim3(ATPB), 0, s, T, x, xstride, nb,
                      nq, qslot, acc, astride);
+}
+void accumulate_digits(const Tables& T, const Consts& hc, const uint64_t* c2, long cstride, int nb, int nq,
+                       const int* qslot, uint64_t* acc, long astride, hipStream_t s) {
+  if (nb <= 0 || nq <= 0) return;
+  PEPSI_L_LAUNCH(k_accumulate_digits, hc.L, dim3((hc.n + ATPB - 1) / ATPB, hc.L * hc.L, nq), dim3(ATPB), s, T, c2,
+                 cstride, nb, nq, qslot, acc, astride);
 }
 void value_accumulate(const Tables& T, const Consts& hc, const uint64_t* x, long xstride, const uint64_t* vhat,
                       int nb, int nq, const int* qslot, uint64_t* acc, long astride, hipStream_t s) {

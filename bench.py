@@ -442,9 +442,14 @@ def batched_leg(pk, params, server, server_items, cfg, nq, steps, seed, plain_va
     server.timing(enable=True, reset=True)
     server.eval_batch(*args)
     tm = server.timing(enable=False)
-    # A/B: eager launches; the select-and-sum on the vector units
+    # A/B: eager launches; one select-and-sum launch per tile instead of per run; the select-and-sum
+    # on the vector units
     server.set_schedule(graph=pk.GRAPH_OFF)
     t_eager = timed(1)
+    t_tiles = None
+    if sched.get("run") == "one select-and-sum launch per run of tiles":
+        server.set_schedule(run=pk.RUN_OFF)
+        t_tiles = timed(1)
     valu = None
     if server.plane_groups > 0:
         server.set_schedule(select_kernel=pk.SELECT_VALU)
@@ -468,6 +473,7 @@ def batched_leg(pk, params, server, server_items, cfg, nq, steps, seed, plain_va
         "speedup_vs_plain": round(value / plain_value, 3),
         "schedule": sched,
         "eager_ms_per_query": round(1e3 * t_eager / nq, 3),
+        "per_tile_select_sum_ms_per_query": None if t_tiles is None else round(1e3 * t_tiles / nq, 3),
         "select_sum_ms_per_batch": round(tm.select_sum_ms, 2),
         "checked_cardinalities": nq,
         "batches_computed": int(server.max_load),

@@ -324,11 +324,17 @@ int pepsi_server_eval_batch(pepsi_server* server, uint32_t nq, const uint64_t* c
 #define PEPSI_SELECT_VALU 2u
 #define PEPSI_GRAPH_ON 1u
 #define PEPSI_GRAPH_OFF 2u
+#define PEPSI_RUN_ON 1u
+#define PEPSI_RUN_OFF 2u
 #define PEPSI_SCHEDULE_DEFAULT 0u   /* source: the rule above            */
 #define PEPSI_SCHEDULE_TUNED 1u     /* source: an entry of the tuned table */
 #define PEPSI_SCHEDULE_CALLER 2u    /* source: pepsi_server_set_schedule   */
 typedef struct {
   uint32_t tile_batches, select_kernel, graph;
+  uint32_t run;            /* with the matrix cores: PEPSI_RUN_ON (the select-and-sum of a run of
+                              tiles -- all batches when their outputs fit -- is one launch that
+                              reads each query's request planes once; the tiles' product trees
+                              then follow) or PEPSI_RUN_OFF (one select-and-sum launch per tile)  */
   uint32_t source;         /* out only (pepsi_server_get_schedule)                      */
   double tuned_ms_per_query; /* out only: the tuned entry's measured time, 0 if none      */
 } pepsi_schedule;

@@ -54,19 +54,21 @@ class ServerInfo(C.Structure):
 
 class Schedule(C.Structure):
     _fields_ = [("tile_batches", C.c_uint32), ("select_kernel", C.c_uint32), ("graph", C.c_uint32),
-                ("source", C.c_uint32), ("tuned_ms_per_query", C.c_double)]
+                ("run", C.c_uint32), ("source", C.c_uint32), ("tuned_ms_per_query", C.c_double)]
 
     def as_dict(self) -> dict:
         return {"tile_batches": self.tile_batches,
                 "select_kernel": {1: "int8 matrix cores (digit planes)", 2: "64-bit VALU"}.get(self.select_kernel,
                                                                                           "automatic"),
                 "graph": {1: "captured HIP graph", 2: "eager launches"}.get(self.graph, "automatic"),
+                "run": {1: "one select-and-sum launch per run of tiles", 2: "one per tile"}.get(self.run, "automatic"),
                 "source": {0: "default rule", 1: "tuned table", 2: "caller"}.get(self.source, "?"),
                 "tuned_ms_per_query": self.tuned_ms_per_query or None}
 
 
 SELECT_PLANES, SELECT_VALU = 1, 2
 GRAPH_ON, GRAPH_OFF = 1, 2
+RUN_ON, RUN_OFF = 1, 2
 
 
 class ReqStats(C.Structure):
@@ -377,12 +379,13 @@ class Server:
         m_ = None if masks is None else arr(*[0 if m is None else m.data_ptr() for m in masks])
         _check(lib().pepsi_server_eval_batch(self._h, nq, c_, r_, m_, o_, _stream(stream)))
 
-    def set_schedule(self, tile_batches: int = 0, select_kernel: int = 0, graph: int = 0, reset: bool = False):
+    def set_schedule(self, tile_batches: int = 0, select_kernel: int = 0, graph: int = 0, run: int = 0,
+                     reset: bool = False):
         """Force the batched schedule (0 = automatic); reset returns to the automatic schedule."""
         if reset:
             _check(lib().pepsi_server_set_schedule(self._h, None))
             return
-        sch = Schedule(tile_batches, select_kernel, graph, 0, 0.0)
+        sch = Schedule(tile_batches, select_kernel, graph, run, 0, 0.0)
         _check(lib().pepsi_server_set_schedule(self._h, C.byref(sch)))
 
     def schedule(self, nq: int) -> Schedule:

@@ -58,22 +58,25 @@ def tune(pk, name, log_n, L, h, bits, mu, n_server, counts, reps):
     entries = []
     for nq in sorted(counts):
         times = {}
-        for tile, kern, graph in itertools.product((16, 32, 64), kernels, (pk.GRAPH_ON, pk.GRAPH_OFF)):
-            server.set_schedule(tile_batches=tile, select_kernel=kern, graph=graph)
+        cands = [(t, k, g, r) for t, k, g, r in itertools.product((16, 32, 64), kernels, (pk.GRAPH_ON, pk.GRAPH_OFF),
+                                                                  (pk.RUN_ON, pk.RUN_OFF))
+                 if k == pk.SELECT_PLANES or r == pk.RUN_OFF]
+        for tile, kern, graph, run in cands:
+            server.set_schedule(tile_batches=tile, select_kernel=kern, graph=graph, run=run)
             args = (cts[:nq], rlk[:nq], None, outs[:nq])
             try:
                 server.eval_batch(*args)                     # sets the workspace up (and captures)
                 torch.cuda.synchronize()
             except pk.PepsiError as e:
-                log(f"[autotune]   nq={nq} tile={tile} kernel={kern} graph={graph}: {e}")
+                log(f"[autotune]   nq={nq} tile={tile} kernel={kern} graph={graph} run={run}: {e}")
                 continue
             t0 = time.perf_counter()
             for _ in range(reps):
                 server.eval_batch(*args)
             torch.cuda.synchronize()
             ms = 1e3 * (time.perf_counter() - t0) / reps / nq
-            times[(tile, kern, graph)] = ms
-            log(f"[autotune]   nq={nq} tile={tile} kernel={kern} graph={graph}: {ms:.3f} ms/query")
+            times[(tile, kern, graph, run)] = ms
+            log(f"[autotune]   nq={nq} tile={tile} kernel={kern} graph={graph} run={run}: {ms:.3f} ms/query")
         server.set_schedule(reset=True)
         best = choose(times)
         entries.append((log_n, L, params.ell, h, nq, best, times[best], times))
@@ -91,6 +94,11 @@ def choose(times: dict):
     return min(near, key=lambda c: (c[2] != 1, -c[0], times[c]))
 
 
+def _key(c) -> str:
+    t, k, g, r = c
+    return f"{t}/{NAMES[k]}/{'g' if g == 1 else 'e'}/{'run' if r == 1 else 'tile'}"
+
+
 TIE = 0.005
 NAMES = {1: "planes", 2: "valu"}
 
@@ -105,8 +113,10 @@ def parse_table(path):
             times = {}
             for item in m.group(2).split(", "):
                 key, v = item.split(": ")
-                t, k, g = key.split("/")
-                times[(int(t), {"planes": 1, "valu": 2}[k], 1 if g == "g" else 2)] = float(v)
+                parts = key.split("/")
+                t, k, g = parts[:3]
+                r = 1 if len(parts) > 3 and parts[3] == "run" else 2      # tables before run mode: per tile
+                times[(int(t), {"planes": 1, "valu": 2}[k], 1 if g == "g" else 2, r)] = float(v)
             pending = (int(m.group(1)), times)
             continue
         m = re.match(r"\{(\d+), (\d+), (\d+), (\d+), (\d+),", line)
@@ -123,12 +133,12 @@ def write_table(entries, path, device):
     names = NAMES
     lines = ["// Written by paper_2310_14565_amd/autotune.py on " + device + ".",
              "// {log_n, L, ell, h, nq_max, tile_batches, select_kernel (1 planes, 2 VALU), graph (1 on, 2 off),",
-             "//  ms per query}; the comment lists every candidate as tile/kernel/graph: ms per query."]
-    for (log_n, L, ell, h, nq, (tile, kern, graph), ms, times) in entries:
-        cands = ", ".join(f"{t}/{names[k]}/{'g' if gr == 1 else 'e'}: {v:.3f}"
-                          for (t, k, gr), v in sorted(times.items()))
+             "//  run (1 one select-and-sum launch per run of tiles, 2 one per tile), ms per query}; the comment",
+             "//  lists every candidate as tile/kernel/graph/run: ms per query."]
+    for (log_n, L, ell, h, nq, (tile, kern, graph, run), ms, times) in entries:
+        cands = ", ".join(f"{_key(c)}: {v:.3f}" for c, v in sorted(times.items()))
         lines.append(f"// nq <= {nq}: {cands}")
-        lines.append(f"{{{log_n}, {L}, {ell}, {h}, {nq}, {tile}, {kern}, {graph}, {ms:.3f}}},")
+        lines.append(f"{{{log_n}, {L}, {ell}, {h}, {nq}, {tile}, {kern}, {graph}, {run}, {ms:.3f}}},")
     with open(path, "w") as f:
         f.write("\n".join(lines) + "\n")
 

@@ -490,6 +490,8 @@ struct Engine {
   DevBuf jobs;                         // device TensorJob arrays, all levels
   DevBuf gen_poly, gen_p;              // on-the-fly plaintext generation
   DevBuf cplanes;                      // per query: request digit planes (matrix-core select-and-sum)
+  DevBuf sall;                         // select-and-sum outputs of a run of tiles (run mode)
+  uint32_t run_cap = 0;                // batches per run (a multiple of TBq and of 16), 0: off
   bool planes_on = false;
   int GB = 0;
   EventTimer* timer = nullptr;
@@ -497,7 +499,7 @@ struct Engine {
 
   ~Engine() {
     for (DevBuf* b : {&chat, &rlkhat, &acc, &accD, &sq, &scoef, &sb, &sbh, &alpha, &pconst, &e, &d, &c01, &c01h, &c2, &D,
-                      &rcoef, &jobs, &gen_poly, &gen_p, &cplanes})
+                      &rcoef, &jobs, &gen_poly, &gen_p, &cplanes, &sall})
       b->release();
     for (auto& b : rq) b.release();
     for (auto& b : rb) b.release();
@@ -514,11 +516,8 @@ struct Engine {
   // INV_TENSOR of the jobs) into d [units][3][L + K][N]
   void tinv_products(InvProducts mode, const uint64_t* xq, const uint64_t* xb, const TensorJob* jobs, uint64_t* out,
                      int units, hipStream_t s) {
-    const int Pn = P->H.L + P->H.K, rows = units * 3 * Pn;
-    hipEvent_t a = nullptr, b = nullptr;
-    if (timer && timer->on && rows > 0) { a = timer->get(); b = timer->get(); (void)hipEventRecord(a, s); }
-    ntt_inverse_products(P->T, P->H.logn, mode, xq, xb, jobs, out, units, Pn, s);
-    if (a) { (void)hipEventRecord(b, s); timer->pending.push_back({a, b, 3, (uint64_t)rows}); }
+    // not among the timed transforms: their loads form the products, so their rows cost more
+    ntt_inverse_products(P->T, P->H.logn, mode, xq, xb, jobs, out, units, P->H.L + P->H.K, s);
   }
   void tinv(const uint64_t* in, uint64_t* out, int rows, int nprimes, int first, hipStream_t s) {
     hipEvent_t a = nullptr, b = nullptr;
@@ -535,6 +534,7 @@ struct Engine {
   int setup(pepsi_params* params, int tbq, int qmax, bool need_gen, const uint64_t* values_hat = nullptr) {
     vhat = values_hat;
     planes_on = false;
+    run_cap = 0;
     P = params;
     const HostParams& H = P->H;
     const size_t n = H.n, L = H.L, K = H.K, Pn = L + K;
@@ -901,15 +901,64 @@ struct Engine {
   // The whole computation for nq queries in slots 0..nq-1 over batches [begin, stop).  (Running
   // the HBM-bound select-and-sum of the next tile on a second stream beside the product tree
   // was measured slower: the select-and-sum needs nearly full occupancy to cover HBM latency.)
+  // Run mode: the select-and-sum of many tiles in one matrix-core launch over whole 16-batch
+  // groups of digit planes (each query's request planes read once per run), into a buffer of
+  // run_cap x Qmax pairs; the tiles' product trees then read their slices of it.  Enabled when
+  // the planes are on, the code length fits the kernel's LDS staging, and at least one tile's
+  // outputs fit beside a 4 GiB reserve; off otherwise (the tiles then run one by one).
+  int enable_run(uint32_t max_batches) {
+    run_cap = 0;
+    if (!planes_on || plane_kblocks(P->H.ell) > PL_RUN_KBS) return 0;
+    const size_t per_batch = (size_t)Qmax * ctw() * 8;
+    uint32_t want = (max_batches + PT_GROUP - 1) / PT_GROUP * PT_GROUP;
+    const uint32_t unit = TBq % PT_GROUP == 0 ? (uint32_t)TBq : (uint32_t)PT_GROUP * TBq;
+    want = (want + unit - 1) / unit * unit;
+    if (sall.cap < (size_t)want * per_batch) {
+      size_t free_b = 0, total_b = 0;
+      if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return fail(PEPSI_E_DEVICE, "hipMemGetInfo failed");
+      const size_t reserve = (size_t)4 << 30, have = free_b > reserve ? free_b - reserve : 0;
+      const uint32_t fit = (uint32_t)std::min<size_t>(have / per_batch + sall.cap / per_batch, want);
+      want = fit / unit * unit;
+      if (want < (uint32_t)TBq) return 0;
+      sall.release();
+      int rc = sall.ensure((size_t)want * per_batch);
+      if (rc) return rc;
+    }
+    run_cap = want;
+    return 0;
+  }
+
   int run(const uint16_t* cw, const uint64_t* cache, uint32_t cached, uint32_t begin, uint32_t stop, int nq,
           const uint64_t* const* cts, const uint64_t* const* rlk, hipStream_t s, const int8_t* planes = nullptr,
           size_t group_bytes = 0, uint32_t plane_batches = 0) {
+    const HostParams& H = P->H;
     for (int q = 0; q < nq; ++q) admit(q, cts[q], rlk[q], s);
-    for (uint32_t b0 = begin; b0 < stop; b0 += TBq) {
+    uint32_t b0 = begin;
+    while (b0 < stop) {
+      if (run_cap > 0 && planes && planes_on && b0 % PT_GROUP == 0 && b0 < plane_batches) {
+        const uint32_t r1 = std::min<uint32_t>(std::min<uint32_t>(stop, plane_batches), b0 + run_cap);
+        const int nb = (int)(r1 - b0), ng = (nb + PT_GROUP - 1) / PT_GROUP;
+        hipEvent_t a = nullptr, b = nullptr;
+        if (timer && timer->on) { a = timer->get(); b = timer->get(); (void)hipEventRecord(a, s); }
+        select_sum_planes_run(P->T, H.consts, planes + (size_t)(b0 / PT_GROUP) * group_bytes, ng, cplanes.as<int8_t>(),
+                              (long)cpstride(), nullptr, nq, nb, H.ell, sall.as<uint64_t>(), s);
+        if (a) {
+          (void)hipEventRecord(b, s);
+          const uint64_t bytes = 8ull * H.n * H.L * ((uint64_t)nb * H.ell + 2ull * H.ell * nq + 2ull * nb * nq);
+          timer->pending.push_back({a, b, 0, bytes});
+        }
+        for (uint32_t t0 = b0; t0 < r1; t0 += TBq) {
+          const int nbt = (int)std::min<uint32_t>(TBq, r1 - t0);
+          consume_s(sall.as<uint64_t>((size_t)(t0 - b0) * nq * ctw()), (int)t0, nbt, nq, nullptr, 0, s);
+        }
+        b0 = r1;
+        continue;
+      }
       const int nb = (int)std::min<uint32_t>(TBq, stop - b0);
       const int rc = run_tile(cw, (int)b0, nb, nq, nullptr, 0,
                               cached_tile(cache, cached, b0, nb, planes, group_bytes, plane_batches), s);
       if (rc) return rc;
+      b0 += TBq;
     }
     return 0;
   }
@@ -965,11 +1014,11 @@ struct GraphCache {
 };
 
 // Schedules measured by autotune.py on MI355X: {log_n, L, ell, h, nq_max, tile_batches,
-// select_kernel, graph, ms_per_query}.
-struct TunedEntry { int logn, L, ell, h, nq_max, tile, kernel, graph; double ms; };
+// select_kernel, graph, run, ms_per_query}.
+struct TunedEntry { int logn, L, ell, h, nq_max, tile, kernel, graph, run; double ms; };
 const TunedEntry kTuned[] = {
 #include "schedule_table.inc"
-    {0, 0, 0, 0, 0, 0, 0, 0, 0.0}};
+    {0, 0, 0, 0, 0, 0, 0, 0, 0, 0.0}};
 
 const TunedEntry* tuned_entry(const HostParams& H, uint32_t nq) {
   const TunedEntry* best = nullptr;
@@ -1277,11 +1326,12 @@ static pepsi_schedule resolve_schedule(const pepsi_server* sv, uint32_t nq) {
     r.tile_batches = (uint32_t)t->tile;
     r.select_kernel = (uint32_t)t->kernel;
     r.graph = (uint32_t)t->graph;
+    r.run = (uint32_t)t->run;
     r.tuned_ms_per_query = t->ms;
     r.source = PEPSI_SCHEDULE_TUNED;
   }
   const pepsi_schedule& f = sv->forced;
-  if (f.tile_batches || f.select_kernel || f.graph) r.source = PEPSI_SCHEDULE_CALLER;
+  if (f.tile_batches || f.select_kernel || f.graph || f.run) r.source = PEPSI_SCHEDULE_CALLER;
   if (f.tile_batches) r.tile_batches = f.tile_batches;
   if (f.select_kernel) r.select_kernel = f.select_kernel;
   if (f.graph) r.graph = f.graph;
@@ -1289,6 +1339,9 @@ static pepsi_schedule resolve_schedule(const pepsi_server* sv, uint32_t nq) {
   if (sv->plane_groups == 0) r.select_kernel = PEPSI_SELECT_VALU;      // nothing to contract on the matrix cores
   if (sv->planes_only) r.select_kernel = PEPSI_SELECT_PLANES;         // the plaintexts exist only as planes
   if (!r.graph) r.graph = PEPSI_GRAPH_ON;
+  if (f.run) r.run = f.run;
+  if (!r.run) r.run = PEPSI_RUN_ON;
+  if (r.select_kernel != PEPSI_SELECT_PLANES) r.run = PEPSI_RUN_OFF;        // runs are a matrix-core form
   if (!r.tile_batches) r.tile_batches = (r.select_kernel == PEPSI_SELECT_PLANES && nq <= 64) ? 64 : 16;
   return r;
 }
@@ -1301,11 +1354,13 @@ extern "C" int pepsi_server_set_schedule(pepsi_server* sv, const pepsi_schedule*
       return fail(PEPSI_E_ARG, "tile_batches must be 0, 16, 32 or 64");
     if (sch->select_kernel > PEPSI_SELECT_VALU) return fail(PEPSI_E_ARG, "unknown select kernel");
     if (sch->graph > PEPSI_GRAPH_OFF) return fail(PEPSI_E_ARG, "unknown graph mode");
+    if (sch->run > PEPSI_RUN_OFF) return fail(PEPSI_E_ARG, "unknown run mode");
     if (sch->select_kernel == PEPSI_SELECT_VALU && sv->planes_only)
       return fail(PEPSI_E_ARG, "the server keeps its plaintexts only as digit planes");
     f.tile_batches = sch->tile_batches;
     f.select_kernel = sch->select_kernel;
     f.graph = sch->graph;
+    f.run = sch->run;
   }
   sv->forced = f;
   return PEPSI_OK;
@@ -1330,7 +1385,7 @@ extern "C" int pepsi_server_eval_batch(pepsi_server* sv, uint32_t nq, const uint
   const pepsi_schedule want = resolve_schedule(sv, nq);
   const bool planes = want.select_kernel == PEPSI_SELECT_PLANES;
   if ((int)nq > sv->bqmax || want.select_kernel != sv->bsched.select_kernel ||
-      want.tile_batches != sv->bsched.tile_batches) {
+      want.tile_batches != sv->bsched.tile_batches || want.run != sv->bsched.run) {
     // the requested tile when its workspace fits beside an 8 GiB reserve, else 16 batches (one
     // batch group of the select-and-sum kernels)
     int tb = 16;
@@ -1355,6 +1410,8 @@ extern "C" int pepsi_server_eval_batch(pepsi_server* sv, uint32_t nq, const uint
     if (rc) return rc;
     sv->beng.timer = &sv->timer;
     if (planes && (rc = sv->beng.enable_planes(sv->planes_only))) return rc;
+    if (planes && want.run == PEPSI_RUN_ON && (rc = sv->beng.enable_run(std::min<uint32_t>(H.mu, sv->max_load))))
+      return rc;
     sv->bsched = want;
     sv->bqmax = (int)nq;
   }

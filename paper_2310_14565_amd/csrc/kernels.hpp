@@ -157,6 +157,12 @@ void plaintext_planes(const Tables& T, const Consts& hc, const uint64_t* P, int 
 void request_planes(const Tables& T, const Consts& hc, const uint64_t* ch, int ell, int8_t* out, hipStream_t s);
 void select_sum_planes(const Tables& T, const Consts& hc, const int8_t* Pp, const int8_t* Cp, long cps,
                        const int* qslot, int nq, int nb, int ell, uint64_t* S, hipStream_t s);
+// The same over a run of ngroups consecutive 16-batch groups (nb <= 16 ngroups batches) in one
+// launch, the request planes staged once per (l, k) and query octet in LDS: needs
+// plane_kblocks(ell) <= PL_RUN_KBS (64.5 KB of LDS at 9 blocks).
+constexpr int PL_RUN_KBS = 9;
+void select_sum_planes_run(const Tables& T, const Consts& hc, const int8_t* Pp, int ngroups, const int8_t* Cp,
+                           long cps, const int* qslot, int nq, int nb, int ell, uint64_t* S, hipStream_t s);
 
 // acc[slot(q)] [L][L][N] += sum over b < nb of the relinearisation digits of the component-2
 // rows c2[b * nq + q] ([L][N], cstride words apart): entry (i, j) adds [c2_i (Q/q_i)^-1]_{q_i}

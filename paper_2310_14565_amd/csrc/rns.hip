@@ -989,6 +989,80 @@ __global__ void __launch_bounds__(TPB) k_select_sum_planes(Tables T, const int8_
   }
 }
 
+// The contraction over a run of ngroups consecutive 16-batch groups of planes in one launch, with
+// the request planes of the workgroup's query octet for its (l, k) staged once in LDS (kbs x 896
+// bytes per query) and reused by every group, so that a query's request planes are read once per
+// run instead of once per tile.  Workgroup = 4 waves on one (l, k) and one octet; wave w takes
+// groups w, w + 4, ...; the next code-position block's plaintext digits are loaded while the
+// current block's 49 products run.  The oblocks workgroups of one (l, k) are numbered
+// consecutively on one XCD and share its plaintext planes through L2.  Needs kbs <= PL_RUN_KBS.
+__global__ void __launch_bounds__(TPB) k_select_sum_planes_run(Tables T, const int8_t* __restrict__ Pp, long gbytes,
+                                                              int ngroups, const int8_t* __restrict__ Cp, long cps,
+                                                              const int* __restrict__ qslot, int nq, int nb, int kbs,
+                                                              uint64_t* __restrict__ S, int oblocks) {
+  extern __shared__ __align__(16) int8_t sB[];
+  const Consts& C = *T.c;
+  const int N = C.n, L = C.L;
+  const int bid = blockIdx.x, local = bid >> 3;
+  const int oct = local % oblocks, lk = (local / oblocks) * 8 + (bid & 7);
+  const int l = lk / N, k = lk % N;
+  const int lane = threadIdx.x & 63, m = lane & 15, g4 = lane >> 4, wv = threadIdx.x >> 6;
+  const int qbytes = kbs * PL_DG * 2 * PL_K;              // one query's planes for this (l, k)
+  // stage the octet's request planes: 8 contiguous runs of qbytes, zeros past the last query
+  for (int x = threadIdx.x; x < 8 * qbytes / 16; x += TPB) {
+    const int qi = x / (qbytes / 16), r = x % (qbytes / 16);
+    const int q = oct * 8 + qi;
+    uint4 v = {0, 0, 0, 0};
+    if (q < nq)
+      __builtin_memcpy(&v, Cp + (size_t)(qslot ? qslot[q] : q) * cps + (size_t)lk * qbytes + (size_t)r * 16, 16);
+    __builtin_memcpy(sB + (size_t)qi * qbytes + (size_t)r * 16, &v, 16);
+  }
+  __syncthreads();
+  const int q = oct * 8 + (m >> 1), c = m & 1;
+  const bool live = q < nq;
+  const int8_t* bq = sB + (size_t)(m >> 1) * qbytes + (size_t)c * PL_K + 16 * g4;
+  const Prime& pr = C.prm[l];
+  uint64_t wgt[4];
+  plane_group_weights(pr, wgt);
+  for (int g = wv; g < ngroups; g += 4) {
+    const int8_t* pa = Pp + (size_t)g * gbytes + ((size_t)lk * kbs * PL_DG * 16 + m) * PL_K + 16 * g4;
+    v4i acc[PL_WEIGHTS];
+#pragma unroll
+    for (int s2 = 0; s2 < PL_WEIGHTS; ++s2) acc[s2] = v4i{0, 0, 0, 0};
+    v4i a[PL_DG], an[PL_DG];
+#pragma unroll
+    for (int v = 0; v < PL_DG; ++v) an[v] = *reinterpret_cast<const v4i*>(pa + (size_t)v * 16 * PL_K);
+    for (int kb = 0; kb < kbs; ++kb) {
+#pragma unroll
+      for (int v = 0; v < PL_DG; ++v) a[v] = an[v];
+      if (kb + 1 < kbs) {
+#pragma unroll
+        for (int v = 0; v < PL_DG; ++v)
+          an[v] = *reinterpret_cast<const v4i*>(pa + ((size_t)(kb + 1) * PL_DG + v) * 16 * PL_K);
+      }
+      v4i bb[PL_DG];
+#pragma unroll
+      for (int u = 0; u < PL_DG; ++u)
+        bb[u] = *reinterpret_cast<const v4i*>(bq + ((size_t)kb * PL_DG + u) * 2 * PL_K);
+#pragma unroll
+      for (int v = 0; v < PL_DG; ++v)
+#pragma unroll
+        for (int u = 0; u < PL_DG; ++u)
+          acc[u + v] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[v], bb[u], acc[u + v], 0, 0, 0);
+    }
+    if (!live) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int b = 16 * g + 4 * g4 + i;     // output row of this lane
+      if (b >= nb) continue;
+      int32_t Ts[PL_WEIGHTS];
+#pragma unroll
+      for (int s2 = 0; s2 < PL_WEIGHTS; ++s2) Ts[s2] = acc[s2][i];
+      S[(((size_t)b * nq + q) * 2 + c) * L * N + (size_t)l * N + k] = plane_recombine(Ts, pr, wgt);
+    }
+  }
+}
+
 // Seeded uniform polynomials (request compression): a_{j,l}[k] = W mod q_l, W the 16 bytes
 // of the ChaCha20 keystream (RFC 8439; key = the seed, nonce = (j, l, 0)) at 16 k, little-
 // endian.  Thread = one 64-byte block = 4 coefficients.
@@ -1425,6 +1499,17 @@ void copy_words(uint64_t* dst, const uint64_t* src, size_t words, hipStream_t s)
   if (!words) return;
   const size_t blocks = std::min<size_t>((words + TPB - 1) / TPB, 4096);
   hipLaunchKernelGGL(k_copy_words, dim3((unsigned)blocks), dim3(TPB), 0, s, dst, src, words);
+}
+void select_sum_planes_run(const Tables& T, const Consts& hc, const int8_t* Pp, int ngroups, const int8_t* Cp,
+                           long cps, const int* qslot, int nq, int nb, int ell, uint64_t* S, hipStream_t s) {
+  const int kbs = plane_kblocks(ell);
+  if (nb <= 0 || nq <= 0 || ngroups <= 0 || kbs > PL_RUN_KBS) return;
+  const int oblocks = (nq + 7) / 8;
+  const int lks = hc.L * hc.n;   // a multiple of 8
+  const long gb = (long)plaintext_plane_group_bytes(hc, ell);
+  const size_t lds = (size_t)8 * kbs * PL_DG * 2 * PL_K;
+  hipLaunchKernelGGL(k_select_sum_planes_run, dim3(lks * oblocks), dim3(TPB), lds, s, T, Pp, gb, ngroups, Cp, cps,
+                     qslot, nq, nb, kbs, S, oblocks);
 }
 void pointwise_mul(const Tables& T, const Consts& hc, const uint64_t* a, const uint64_t* b,
                    uint64_t* out, int rows, int nprimes, bool bcast, hipStream_t s) {

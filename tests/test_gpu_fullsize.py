@@ -123,5 +123,16 @@ def test_full_size(name, capsys):
     sv.eval_batch([x["cts"] for x in qs], [x["rlk"] for x in qs], [x["mask"] for x in qs], outs)
     torch.cuda.synchronize()
     assert torch.equal(outs[0], res) and torch.equal(outs[2], res) and torch.equal(outs[1], alone2)
+    if c["cache"]:
+        # the select-and-sum of all batches in one matrix-core launch (request planes staged once)
+        sv.set_schedule(run=pk.RUN_ON)
+        assert sv.schedule(3).run == pk.RUN_ON
+        for o in outs:
+            o.zero_()
+        _progress(capsys, f"{name}: batched path in one select-and-sum run")
+        sv.eval_batch([x["cts"] for x in qs], [x["rlk"] for x in qs], [x["mask"] for x in qs], outs)
+        torch.cuda.synchronize()
+        assert torch.equal(outs[0], res) and torch.equal(outs[2], res) and torch.equal(outs[1], alone2)
+        sv.set_schedule(reset=True)
     sv.close()
 

@@ -90,25 +90,28 @@ def test_graph_replays(setup):
     sv.set_schedule(reset=True)
 
 
-@pytest.mark.parametrize("tile,kernel,graph", [(16, 1, 2), (32, 1, 1), (64, 1, 2), (16, 2, 1), (64, 2, 2)])
-def test_schedules_equal_alone(setup, tile, kernel, graph):
+@pytest.mark.parametrize("tile,kernel,graph,run", [(16, 1, 2, 2), (32, 1, 1, 2), (64, 1, 2, 2), (16, 2, 1, 2),
+                                                   (64, 2, 2, 2), (16, 1, 1, 1), (32, 1, 2, 1), (64, 1, 1, 1)])
+def test_schedules_equal_alone(setup, tile, kernel, graph, run):
+    """run = 1: the select-and-sum of a run of tiles in one launch (request planes staged once per
+    run), the tiles' product trees after it."""
     st = setup
     sv = st["sv"]
-    sv.set_schedule(tile_batches=tile, select_kernel=kernel, graph=graph)
+    sv.set_schedule(tile_batches=tile, select_kernel=kernel, graph=graph, run=run)
     sch = sv.schedule(6)
-    assert (sch.tile_batches, sch.select_kernel, sch.graph, sch.source) == (tile, kernel, graph, 2)
+    assert (sch.tile_batches, sch.select_kernel, sch.graph, sch.run, sch.source) == (tile, kernel, graph, run, 2)
     idx = [0, 1, 2, 3, 4, 5]
     outs = [empty((2, st["L"], st["n"]), np.uint64) for _ in idx]
     for rep in range(2):
         _batch(st, outs, idx)
-        _check(st, outs, idx, f"tile {tile} kernel {kernel} graph {graph} rep {rep}")
+        _check(st, outs, idx, f"tile {tile} kernel {kernel} graph {graph} run {run} rep {rep}")
     sv.set_schedule(reset=True)
 
 
 def test_schedule_arguments(setup):
     pk = setup["pk"]
     sv = setup["sv"]
-    for bad in (dict(tile_batches=8), dict(select_kernel=3), dict(graph=5)):
+    for bad in (dict(tile_batches=8), dict(select_kernel=3), dict(graph=5), dict(run=3)):
         with pytest.raises(pk.PepsiError):
             sv.set_schedule(**bad)
     sv.set_schedule(reset=True)

@@ -504,6 +504,16 @@ struct Engine {
     for (auto& b : rq) b.release();
     for (auto& b : rb) b.release();
   }
+  // device bytes the workspace holds now (a new setup reuses them)
+  size_t held_bytes() const {
+    size_t t = 0;
+    for (const DevBuf* b : {&chat, &rlkhat, &acc, &accD, &sq, &scoef, &sb, &sbh, &alpha, &pconst, &e, &d, &c01, &c01h,
+                            &c2, &D, &rcoef, &jobs, &gen_poly, &gen_p, &cplanes, &sall})
+      t += b->cap;
+    for (const auto& b : rq) t += b.cap;
+    for (const auto& b : rb) t += b.cap;
+    return t;
+  }
 
   // Transforms of the engine, event-timed (rows per launch) while the server's timer is on.
   void tfwd(const void* in, void* out, int rows, int nprimes, int first, hipStream_t s, NttLoad ld = LOAD_U64) {
@@ -1388,10 +1398,12 @@ extern "C" int pepsi_server_eval_batch(pepsi_server* sv, uint32_t nq, const uint
       want.tile_batches != sv->bsched.tile_batches || want.run != sv->bsched.run) {
     // the requested tile when its workspace fits beside an 8 GiB reserve, else 16 batches (one
     // batch group of the select-and-sum kernels)
+    if (!(planes && want.run == PEPSI_RUN_ON)) sv->beng.sall.release();   // its memory goes to the tiles
     int tb = 16;
     if (want.tile_batches > 16) {
       size_t free_b = 0, total_b = 0;
       if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return fail(PEPSI_E_DEVICE, "hipMemGetInfo failed");
+      free_b += sv->beng.held_bytes() - sv->beng.sall.cap;    // the workspace's own buffers are reused
       const size_t fixed = (size_t)nq * (engine_slot_bytes(H) + (planes ? request_plane_bytes(H.consts, H.ell) : 0)) +
                            ((size_t)8 << 30);
       for (int cand : {64, 32})

@@ -400,7 +400,7 @@ def paper32_leg(pk, steps, seed):
     }
 
 
-def batched_leg(pk, params, server, server_items, cfg, nq, steps, seed, plain_value):
+def batched_leg(pk, params, server, server_items, cfg, nq, steps, seed, plain_value, ab=True):
     """Config 'batched': nq queries, m log-uniform in [64, 2048], 25% planted, evaluated together
     under the library's schedule for nq queries (the whole call one captured HIP graph, replayed).
     Also: the same batch with eager launches (the graph's A/B), and with the select-and-sum on the
@@ -444,14 +444,14 @@ def batched_leg(pk, params, server, server_items, cfg, nq, steps, seed, plain_va
     tm = server.timing(enable=False)
     # A/B: eager launches; one select-and-sum launch per tile instead of per run; the select-and-sum
     # on the vector units
-    server.set_schedule(graph=pk.GRAPH_OFF)
-    t_eager = timed(1)
-    t_tiles = None
-    if sched.get("run") == "one select-and-sum launch per run of tiles":
+    t_eager = t_tiles = valu = None
+    if ab:
+        server.set_schedule(graph=pk.GRAPH_OFF)
+        t_eager = timed(1)
+    if ab and sched.get("run") == "one select-and-sum launch per run of tiles":
         server.set_schedule(run=pk.RUN_OFF)
         t_tiles = timed(1)
-    valu = None
-    if server.plane_groups > 0:
+    if ab and server.plane_groups > 0:
         server.set_schedule(select_kernel=pk.SELECT_VALU)
         vs = server.schedule(nq).as_dict()
         t_valu = timed(1)
@@ -472,7 +472,7 @@ def batched_leg(pk, params, server, server_items, cfg, nq, steps, seed, plain_va
         "ms_per_query": round(1e3 * t / nq, 3),
         "speedup_vs_plain": round(value / plain_value, 3),
         "schedule": sched,
-        "eager_ms_per_query": round(1e3 * t_eager / nq, 3),
+        "eager_ms_per_query": None if t_eager is None else round(1e3 * t_eager / nq, 3),
         "per_tile_select_sum_ms_per_query": None if t_tiles is None else round(1e3 * t_tiles / nq, 3),
         "select_sum_ms_per_batch": round(tm.select_sum_ms, 2),
         "checked_cardinalities": nq,
@@ -648,6 +648,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=64, help="queries per batched launch (0: skip the batched leg)")
     ap.add_argument("--batch-steps", type=int, default=2)
+    ap.add_argument("--no-batch-ab", action="store_true",
+                    help="batched leg: only the library's schedule (no eager, per-tile or vector-unit A/B runs)")
     ap.add_argument("--seed", type=int, default=2024)
     ap.add_argument("--psi-sum-steps", type=int, default=5, help="steps of the PSI-Sum leg (0: skip it)")
     ap.add_argument("--paper32-steps", type=int, default=5,
@@ -811,7 +813,7 @@ def main():
         del src, dst
     if args.batch > 0:
         line["batched"] = batched_leg(pk, params, server, server_items, cfg, args.batch, args.batch_steps,
-                                      args.seed + 7, value)
+                                      args.seed + 7, value, ab=not args.no_batch_ab)
     if args.psi_sum_steps > 0 and args.config == "paper":
         server.close()
         line["psi_sum"] = psi_sum_leg(pk, params, server_items, cfg, args.psi_sum_steps, args.seed + 9)

@@ -159,7 +159,7 @@ void select_sum_planes(const Tables& T, const Consts& hc, const int8_t* Pp, cons
                        const int* qslot, int nq, int nb, int ell, uint64_t* S, hipStream_t s);
 // The same over a run of ngroups consecutive 16-batch groups (nb <= 16 ngroups batches) in one
 // launch, the request planes staged once per (l, k) and query octet in LDS: needs
-// plane_kblocks(ell) <= PL_RUN_KBS (64.5 KB of LDS at 9 blocks).
+// plane_kblocks(ell) <= PL_RUN_KBS (64.25 KB of LDS at 9 blocks).
 constexpr int PL_RUN_KBS = 9;
 void select_sum_planes_run(const Tables& T, const Consts& hc, const int8_t* Pp, int ngroups, const int8_t* Cp,
                            long cps, const int* qslot, int nq, int nb, int ell, uint64_t* S, hipStream_t s);

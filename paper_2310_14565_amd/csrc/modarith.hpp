@@ -91,6 +91,11 @@ PEPSI_HD uint64_t mulmod(uint64_t a, uint64_t b, const Prime& P) {
   u128 x = (u128)a * b;
   return reduce116((uint64_t)x, (uint64_t)(x >> 64), P);
 }
+// Congruent to a b and below 3p, for a b < 2^116.
+PEPSI_HD uint64_t mulmod_lazy(uint64_t a, uint64_t b, const Prime& P) {
+  u128 x = (u128)a * b;
+  return reduce116_lazy((uint64_t)x, (uint64_t)(x >> 64), P);
+}
 PEPSI_HD uint64_t addmod(uint64_t a, uint64_t b, uint64_t p) {
   uint64_t s = a + b;
   return s >= p ? s - p : s;

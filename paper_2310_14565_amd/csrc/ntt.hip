@@ -27,8 +27,16 @@ namespace {
 
 // Each thread holds E = 2^EL residues of a row; a row's log N stages run as passes of EL stages
 // (the last pass takes what is left), with one exchange through padded LDS between passes.
+// A row fills 64 KiB of LDS at N = 8192, so a CU holds two rows at a time: with 8 residues per
+// thread (1024 threads, 16 waves per row) that is 8 waves per SIMD to hide latency, against 4
+// with 16 residues, for one more exchange. The inverse transform that forms the tensor on load
+// (four operand rows per word) keeps 16, and so do the transforms over t.
 template <int LOGN>
-constexpr int ntt_el() { return 4; }
+constexpr int ntt_el() { return LOGN == 13 ? 3 : 4; }
+template <int LOGN, int IL>
+constexpr int ntt_inv_el() { return IL == INV_TENSOR ? 4 : ntt_el<LOGN>(); }
+template <int LOGN>
+constexpr int ntt_t_el() { return 4; }
 // Whether a last pass of d stages reads or writes global memory from registers (each thread then
 // moves runs of 2^d consecutive words) instead of going through LDS.
 constexpr bool ntt_direct(int d) { return d <= 1; }
@@ -40,6 +48,23 @@ __device__ __forceinline__ int elem_index(int tid, int u, int m) {
   constexpr int N = 1 << LOGN, T = N >> EL, LOW = N >> (S0 + D);
   const int g = tid + T * u;
   return (g / LOW) * (N >> S0) + m * LOW + (g % LOW);
+}
+// lds_idx(elem_index(tid, u, m)) as a part that depends on the thread and u plus a compile-time
+// offset for m, so that the 2^D accesses of a group share one address and differ in the offset
+// field. With a = (g / LOW) 2^(LOGN - S0) and r = g mod LOW the index is a + m LOW + r, and its
+// padding word count (index >> 5) splits into a >> 5, (m LOW) >> 5 and r >> 5: either a and m LOW
+// are multiples of 32, or LOW < 32 divides 32 (then r < LOW adds no carry), or the block
+// 2^(LOGN - S0) < 32 divides 32 (then nothing inside a block carries past a multiple of 32).
+template <int LOGN, int EL, int S0, int D>
+__device__ __forceinline__ int lds_base(int tid, int u) {
+  constexpr int N = 1 << LOGN, T = N >> EL, LOW = N >> (S0 + D);
+  const int g = tid + T * u;
+  const int a = (g / LOW) * (N >> S0), r = g % LOW;
+  return a + (a >> 5) + r + (r >> 5);
+}
+template <int LOGN, int S0, int D>
+constexpr int lds_off(int m) {
+  return m * ((1 << LOGN) >> (S0 + D)) + ((m * ((1 << LOGN) >> (S0 + D))) >> 5);
 }
 
 // Forward stages [S0, S0 + D) on 2^(EL - D) groups of 2^D registers.
@@ -124,18 +149,20 @@ __device__ __forceinline__ void inv_pass(uint64_t* x, int tid, const uint64_t* _
 template <int LOGN, int EL, int S0, int D, class V>
 __device__ __forceinline__ void to_lds(V* lds, const V* x, int tid) {
 #pragma unroll
-  for (int u = 0; u < (1 << (EL - D)); ++u)
+  for (int u = 0; u < (1 << (EL - D)); ++u) {
+    V* base = lds + lds_base<LOGN, EL, S0, D>(tid, u);
 #pragma unroll
-    for (int m = 0; m < (1 << D); ++m)
-      lds[lds_idx(elem_index<LOGN, EL, S0, D>(tid, u, m))] = x[u * (1 << D) + m];
+    for (int m = 0; m < (1 << D); ++m) base[lds_off<LOGN, S0, D>(m)] = x[u * (1 << D) + m];
+  }
 }
 template <int LOGN, int EL, int S0, int D, class V>
 __device__ __forceinline__ void from_lds(V* x, const V* lds, int tid) {
 #pragma unroll
-  for (int u = 0; u < (1 << (EL - D)); ++u)
+  for (int u = 0; u < (1 << (EL - D)); ++u) {
+    const V* base = lds + lds_base<LOGN, EL, S0, D>(tid, u);
 #pragma unroll
-    for (int m = 0; m < (1 << D); ++m)
-      x[u * (1 << D) + m] = lds[lds_idx(elem_index<LOGN, EL, S0, D>(tid, u, m))];
+    for (int m = 0; m < (1 << D); ++m) x[u * (1 << D) + m] = base[lds_off<LOGN, S0, D>(m)];
+  }
 }
 
 // Forward passes starting at stage S0 (> 0); the previous pass has left its outputs in LDS. With
@@ -291,26 +318,34 @@ struct InvRow {
       }
     }
   }
+  // The first inverse pass takes words below 4p, so the products are reduced lazily (below 3p),
+  // and each component loads only the operand rows it uses.
   __device__ __forceinline__ uint64_t at(int N, int j) const {
     if constexpr (IL == 0) {
       return in[row * N + j];
     } else if constexpr (IL == INV_SQUARES) {
-      const uint64_t a = x0[j], b = x1[j];
-      if (comp == 0) return mulmod(a, a, pr);
-      if (comp == 1) return mulmod(addmod(a, a, pr.p), b, pr);
-      return mulmod(b, b, pr);
+      if (comp == 0) {
+        const uint64_t a = x0[j];
+        return mulmod_lazy(a, a, pr);
+      }
+      if (comp == 2) {
+        const uint64_t b = x1[j];
+        return mulmod_lazy(b, b, pr);
+      }
+      const uint64_t a = x0[j];
+      return mulmod_lazy(a + a, x1[j], pr);            // 2a < 2p: the product is below 2^109
     } else {
-      if (comp == 2) return mulmod(x1[j], y1[j], pr);
+      if (comp == 2) return mulmod_lazy(x1[j], y1[j], pr);
       const uint64_t a = ax ? addmod(x0[j], ax, pr.p) : x0[j];
       const uint64_t c = ay ? addmod(y0[j], ay, pr.p) : y0[j];
-      if (comp == 0) return mulmod(a, c, pr);
+      if (comp == 0) return mulmod_lazy(a, c, pr);
       const u128 m = (u128)a * y1[j] + (u128)x1[j] * c;
-      return reduce116((uint64_t)m, (uint64_t)(m >> 64), pr);
+      return reduce116_lazy((uint64_t)m, (uint64_t)(m >> 64), pr);
     }
   }
 };
 
-template <int LOGN, int IL = 0, int EL = ntt_el<LOGN>()>
+template <int LOGN, int IL = 0, int EL = ntt_inv_el<LOGN, IL>()>
 __global__ void __launch_bounds__((1 << LOGN) >> EL)
 k_ntt_inv(Tables T, const uint64_t* __restrict__ in, uint64_t* __restrict__ out, int nprimes, int first, InvSrc src) {
   constexpr int N = 1 << LOGN, E = 1 << EL, TT = N >> EL, NP = (LOGN + EL - 1) / EL;
@@ -449,7 +484,7 @@ __device__ __forceinline__ void intt_t_row(uint32_t* x, uint32_t* lt, int tid, c
 // Same register passes as k_ntt_inv: each thread reads the codewords of E slots (coalesced) and
 // places their bits at the bit-reversed LDS positions; the last pass leaves coefficient m TT + tid
 // in register m.
-template <int LOGN, int EL = ntt_el<LOGN>()>
+template <int LOGN, int EL = ntt_t_el<LOGN>()>
 __global__ void __launch_bounds__((1 << LOGN) >> EL)
 k_encode_planes(Tables T, const uint16_t* __restrict__ cw, int h, int ell, int b0, uint32_t* __restrict__ poly) {
   constexpr int N = 1 << LOGN, E = 1 << EL, TT = N >> EL;
@@ -473,7 +508,7 @@ k_encode_planes(Tables T, const uint16_t* __restrict__ cw, int h, int ell, int b
 
 // Batch encoding of slot rows (slot s of row r at slots[r N + s]): the bit-reversed slots are
 // inverse-transformed over t like the bit planes of k_encode_planes.
-template <int LOGN, int EL = ntt_el<LOGN>()>
+template <int LOGN, int EL = ntt_t_el<LOGN>()>
 __global__ void __launch_bounds__((1 << LOGN) >> EL)
 k_encode(Tables T, const uint32_t* __restrict__ slots, uint32_t* __restrict__ poly) {
   constexpr int N = 1 << LOGN, E = 1 << EL, TT = N >> EL;
@@ -540,7 +575,7 @@ void ntt_forward_plaintexts(const Tables& T, int logn, const uint32_t* in, uint6
 template <int IL>
 void launch_inv(const Tables& T, int logn, const uint64_t* in, uint64_t* out, int rows, int nprimes, int first,
                 const InvSrc& src, hipStream_t s) {
-#define PEPSI_INV(LL) hipLaunchKernelGGL((k_ntt_inv<LL, IL>), dim3(rows), dim3((1 << LL) >> ntt_el<LL>()), 0, s, T, in, \
+#define PEPSI_INV(LL) hipLaunchKernelGGL((k_ntt_inv<LL, IL>), dim3(rows), dim3((1 << LL) >> ntt_inv_el<LL, IL>()), 0, s, T, in, \
                                          out, nprimes, first, src)
   switch (logn) {
     case 10: PEPSI_INV(10); break;
@@ -580,7 +615,7 @@ void ntt_inverse_products(const Tables& T, int logn, InvProducts mode, const uin
 void encode_slots(const Tables& T, int logn, const uint32_t* slots, uint32_t* poly, int rows,
                   hipStream_t s) {
   if (rows <= 0) return;
-#define PEPSI_ENC1(LL) hipLaunchKernelGGL(k_encode<LL>, dim3(rows), dim3((1 << LL) >> ntt_el<LL>()), 0, s, T, slots, \
+#define PEPSI_ENC1(LL) hipLaunchKernelGGL(k_encode<LL>, dim3(rows), dim3((1 << LL) >> ntt_t_el<LL>()), 0, s, T, slots, \
                                           poly)
   switch (logn) {
     case 10: PEPSI_ENC1(10); break;
@@ -600,7 +635,7 @@ void encode_server_planes(const Tables& T, int logn, const uint16_t* cw, int h, 
                           int nb, uint32_t* poly, hipStream_t s) {
   const int rows = nb * ell;
   if (rows <= 0) return;
-#define PEPSI_ENC(LL) hipLaunchKernelGGL(k_encode_planes<LL>, dim3(rows), dim3((1 << LL) >> ntt_el<LL>()), 0, s, T, \
+#define PEPSI_ENC(LL) hipLaunchKernelGGL(k_encode_planes<LL>, dim3(rows), dim3((1 << LL) >> ntt_t_el<LL>()), 0, s, T, \
                                          cw, h, ell, b0, poly)
   switch (logn) {
     case 10: PEPSI_ENC(10); break;

@@ -85,12 +85,18 @@ __device__ __forceinline__ uint64_t round_fp(const uint64_t* y, const double* in
 
 // Exact CRT: X = sum_k y_k * hat_k reduced into [0, M) by v subtractions of M.
 // Returns v; *gt = (2 X > M); X is written to xout when given.
-__device__ __noinline__ int crt_exact(const uint64_t* y, int cnt, const MWord* hat, const MWord& M,
+// The rare path of the kernels' roundings, inlined into them: a call would make every caller
+// keep its live values in callee-saved registers, and an X held in registers would set the
+// caller's register count, so X lives in scratch memory (volatile) and the loops stay rolled.
+__device__ __forceinline__ int crt_exact(const uint64_t* y, int cnt, const MWord* hat, const MWord& M,
                                       bool* gt, uint64_t* xout) {
-  uint64_t X[PEPSI_MW];
+  volatile uint64_t X[PEPSI_MW];
+#pragma unroll 1
   for (int w = 0; w < PEPSI_MW; ++w) X[w] = 0;
+#pragma unroll 1
   for (int k = 0; k < cnt; ++k) {
     uint64_t carry = 0;
+#pragma unroll 1
     for (int w = 0; w < PEPSI_MW; ++w) {
       const u128 t = (u128)y[k] * hat[k].w[w] + X[w] + carry;
       X[w] = (uint64_t)t;
@@ -100,11 +106,13 @@ __device__ __noinline__ int crt_exact(const uint64_t* y, int cnt, const MWord* h
   int v = 0;
   for (;;) {
     bool ge = true;                               // X >= M ?
+#pragma unroll 1
     for (int w = PEPSI_MW - 1; w >= 0; --w) {
       if (X[w] != M.w[w]) { ge = X[w] > M.w[w]; break; }
     }
     if (!ge) break;
     uint64_t borrow = 0;
+#pragma unroll 1
     for (int w = 0; w < PEPSI_MW; ++w) {
       const u128 d = (u128)X[w] - M.w[w] - borrow;
       X[w] = (uint64_t)d;
@@ -114,6 +122,7 @@ __device__ __noinline__ int crt_exact(const uint64_t* y, int cnt, const MWord* h
   }
   // 2X > M ?
   bool g = false;
+#pragma unroll 1
   for (int w = PEPSI_MW - 1; w >= 0; --w) {
     const uint64_t x2 = (X[w] << 1) | (w > 0 ? X[w - 1] >> 63 : 0);
     const uint64_t top = w == PEPSI_MW - 1 ? (X[w] >> 63) : 0;   // bit shifted out of the top word
@@ -122,13 +131,14 @@ __device__ __noinline__ int crt_exact(const uint64_t* y, int cnt, const MWord* h
   }
   *gt = g;
   if (xout)
+#pragma unroll 1
     for (int w = 0; w < PEPSI_MW; ++w) xout[w] = X[w];
   return v;
 }
 
 // Exact v = round(sum_i y_i / m_i) over Q (resp. B): the rare path of a centred extension.
 template <int L>
-__device__ __noinline__ uint64_t exact_round_q(const Consts& C, const uint64_t* yr, uint32_t* fallback) {
+__device__ __forceinline__ uint64_t exact_round_q(const Consts& C, const uint64_t* yr, uint32_t* fallback) {
   uint64_t y[L];
   for (int i = 0; i < L; ++i) y[i] = yr[i];
   bool gt;
@@ -137,7 +147,7 @@ __device__ __noinline__ uint64_t exact_round_q(const Consts& C, const uint64_t* 
   return v;
 }
 template <int K>
-__device__ __noinline__ uint64_t exact_round_b(const Consts& C, const uint64_t* yr, uint32_t* fallback) {
+__device__ __forceinline__ uint64_t exact_round_b(const Consts& C, const uint64_t* yr, uint32_t* fallback) {
   uint64_t y[K];
   for (int j = 0; j < K; ++j) y[j] = yr[j];
   bool gt;
@@ -994,8 +1004,16 @@ __global__ void __launch_bounds__(TPB) k_select_sum_planes(Tables T, const int8_
 // bytes per query) and reused by every group, so that a query's request planes are read once per
 // run instead of once per tile.  Workgroup = 4 waves on one (l, k) and one octet; wave w takes
 // groups w, w + 4, ...; the next code-position block's plaintext digits are loaded while the
-// current block's 49 products run.  The oblocks workgroups of one (l, k) are numbered
-// consecutively on one XCD and share its plaintext planes through L2.  Needs kbs <= PL_RUN_KBS.
+// current block's 49 products run.  Column m of the products is query m mod 8 of the octet, part
+// m / 8.  In LDS each (part, query) run of kbs x 448 bytes starts at part RUN_CS + query RUN_QS,
+// with RUN_QS = 16 (mod 256) and RUN_CS = 8 RUN_QS = 128 (mod 256): the 16-byte reads of the 16
+// columns then fall on 16 distinct 16-byte bank slots of every 256 bytes (and the 8 columns of a
+// half wave on 8 distinct slots of every 128), so the reads of a wave are free of bank conflicts.
+// The oblocks workgroups of one (l, k) are numbered consecutively on one XCD and share its
+// plaintext planes through L2.  Needs kbs <= PL_RUN_KBS.
+__host__ __device__ constexpr int run_qs(int kbs) {
+  return kbs * PL_DG * PL_K + (((16 - kbs * PL_DG * PL_K) % 256) + 256) % 256;
+}
 __global__ void __launch_bounds__(TPB) k_select_sum_planes_run(Tables T, const int8_t* __restrict__ Pp, long gbytes,
                                                               int ngroups, const int8_t* __restrict__ Cp, long cps,
                                                               const int* __restrict__ qslot, int nq, int nb, int kbs,
@@ -1007,20 +1025,23 @@ __global__ void __launch_bounds__(TPB) k_select_sum_planes_run(Tables T, const i
   const int oct = local % oblocks, lk = (local / oblocks) * 8 + (bid & 7);
   const int l = lk / N, k = lk % N;
   const int lane = threadIdx.x & 63, m = lane & 15, g4 = lane >> 4, wv = threadIdx.x >> 6;
-  const int qbytes = kbs * PL_DG * 2 * PL_K;              // one query's planes for this (l, k)
-  // stage the octet's request planes: 8 contiguous runs of qbytes, zeros past the last query
-  for (int x = threadIdx.x; x < 8 * qbytes / 16; x += TPB) {
-    const int qi = x / (qbytes / 16), r = x % (qbytes / 16);
+  const int QS = run_qs(kbs), CS = 8 * QS;
+  // stage the octet's request planes, source [kb][digit][part][64] per query, zeros past the
+  // last query
+  const int chunks = kbs * PL_DG * 2 * PL_K / 16;       // 16-byte chunks per query
+  for (int x = threadIdx.x; x < 8 * chunks; x += TPB) {
+    const int qi = x / chunks, r = x % chunks;
     const int q = oct * 8 + qi;
     uint4 v = {0, 0, 0, 0};
     if (q < nq)
-      __builtin_memcpy(&v, Cp + (size_t)(qslot ? qslot[q] : q) * cps + (size_t)lk * qbytes + (size_t)r * 16, 16);
-    __builtin_memcpy(sB + (size_t)qi * qbytes + (size_t)r * 16, &v, 16);
+      __builtin_memcpy(&v, Cp + (size_t)(qslot ? qslot[q] : q) * cps + ((size_t)lk * chunks + r) * 16, 16);
+    const int quarter = r & 3, part = (r >> 2) & 1, kd = r >> 3;   // kd = kb * PL_DG + digit
+    __builtin_memcpy(sB + part * CS + qi * QS + kd * PL_K + quarter * 16, &v, 16);
   }
   __syncthreads();
-  const int q = oct * 8 + (m >> 1), c = m & 1;
+  const int q = oct * 8 + (m & 7), c = m >> 3;
   const bool live = q < nq;
-  const int8_t* bq = sB + (size_t)(m >> 1) * qbytes + (size_t)c * PL_K + 16 * g4;
+  const int8_t* bq = sB + c * CS + (m & 7) * QS + 16 * g4;
   const Prime& pr = C.prm[l];
   uint64_t wgt[4];
   plane_group_weights(pr, wgt);
@@ -1042,8 +1063,7 @@ __global__ void __launch_bounds__(TPB) k_select_sum_planes_run(Tables T, const i
       }
       v4i bb[PL_DG];
 #pragma unroll
-      for (int u = 0; u < PL_DG; ++u)
-        bb[u] = *reinterpret_cast<const v4i*>(bq + ((size_t)kb * PL_DG + u) * 2 * PL_K);
+      for (int u = 0; u < PL_DG; ++u) bb[u] = *reinterpret_cast<const v4i*>(bq + (kb * PL_DG + u) * PL_K);
 #pragma unroll
       for (int v = 0; v < PL_DG; ++v)
 #pragma unroll
@@ -1507,7 +1527,7 @@ void select_sum_planes_run(const Tables& T, const Consts& hc, const int8_t* Pp, 
   const int oblocks = (nq + 7) / 8;
   const int lks = hc.L * hc.n;   // a multiple of 8
   const long gb = (long)plaintext_plane_group_bytes(hc, ell);
-  const size_t lds = (size_t)8 * kbs * PL_DG * 2 * PL_K;
+  const size_t lds = (size_t)2 * 8 * run_qs(kbs);
   hipLaunchKernelGGL(k_select_sum_planes_run, dim3(lks * oblocks), dim3(TPB), lds, s, T, Pp, gb, ngroups, Cp, cps,
                      qslot, nq, nb, kbs, S, oblocks);
 }

@@ -29,12 +29,12 @@ namespace {
 // (the last pass takes what is left), with one exchange through padded LDS between passes.
 // A row fills 64 KiB of LDS at N = 8192, so a CU holds two rows at a time: with 8 residues per
 // thread (1024 threads, 16 waves per row) that is 8 waves per SIMD to hide latency, against 4
-// with 16 residues, for one more exchange. The inverse transform that forms the tensor on load
-// (four operand rows per word) keeps 16, and so do the transforms over t.
+// with 16 residues, for one more exchange. Eight waves per SIMD need at most 64 VGPRs, which the
+// inverse transforms are held to (ntt_waves). The transforms over t keep 16 residues.
 template <int LOGN>
 constexpr int ntt_el() { return LOGN == 13 ? 3 : 4; }
-template <int LOGN, int IL>
-constexpr int ntt_inv_el() { return IL == INV_TENSOR ? 4 : ntt_el<LOGN>(); }
+template <int EL>
+constexpr int ntt_waves() { return EL == 3 ? 8 : 1; }   // minimum waves per SIMD (1: no bound)
 template <int LOGN>
 constexpr int ntt_t_el() { return 4; }
 // Whether a last pass of d stages reads or writes global memory from registers (each thread then
@@ -345,8 +345,8 @@ struct InvRow {
   }
 };
 
-template <int LOGN, int IL = 0, int EL = ntt_inv_el<LOGN, IL>()>
-__global__ void __launch_bounds__((1 << LOGN) >> EL)
+template <int LOGN, int IL = 0, int EL = ntt_el<LOGN>()>
+__global__ void __launch_bounds__((1 << LOGN) >> EL) __attribute__((amdgpu_waves_per_eu(ntt_waves<EL>())))
 k_ntt_inv(Tables T, const uint64_t* __restrict__ in, uint64_t* __restrict__ out, int nprimes, int first, InvSrc src) {
   constexpr int N = 1 << LOGN, E = 1 << EL, TT = N >> EL, NP = (LOGN + EL - 1) / EL;
   constexpr int SL = (NP - 1) * EL, DL = LOGN - SL;   // first inverse pass: stages [SL, LOGN)
@@ -575,7 +575,7 @@ void ntt_forward_plaintexts(const Tables& T, int logn, const uint32_t* in, uint6
 template <int IL>
 void launch_inv(const Tables& T, int logn, const uint64_t* in, uint64_t* out, int rows, int nprimes, int first,
                 const InvSrc& src, hipStream_t s) {
-#define PEPSI_INV(LL) hipLaunchKernelGGL((k_ntt_inv<LL, IL>), dim3(rows), dim3((1 << LL) >> ntt_inv_el<LL, IL>()), 0, s, T, in, \
+#define PEPSI_INV(LL) hipLaunchKernelGGL((k_ntt_inv<LL, IL>), dim3(rows), dim3((1 << LL) >> ntt_el<LL>()), 0, s, T, in, \
                                          out, nprimes, first, src)
   switch (logn) {
     case 10: PEPSI_INV(10); break;

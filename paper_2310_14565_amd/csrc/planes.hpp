@@ -12,7 +12,8 @@
 // weights, V_g = sum_{s=4g}^{4g+3} T_s 256^(s - 4g), with |V_g| <= 7 ell 2^14 (1 + 2^8 + 2^16 +
 // 2^24) < 2^53 <= p for ell <= PL_MAX_ELL, so V_g + p lies in [0, 2p) and
 //   sum_j x_j y_j = sum_g V_g 2^(32 g)   (mod p)
-// is a sum of four products below 2p * p < 2^109, reduced once.
+// is a sum of four products, each below 2p * p < 2^109, so below 2^111: one 116-bit Barrett
+// reduction.
 #pragma once
 #include "modarith.hpp"
 
@@ -53,7 +54,7 @@ PEPSI_HD uint64_t plane_recombine(const int32_t (&T)[PL_WEIGHTS], const Prime& p
     for (int s = 4 * g; s < 4 * g + 4 && s < PL_WEIGHTS; ++s) V += (int64_t)T[s] << (8 * (s - 4 * g));
     tot += (u128)(uint64_t)(V + (int64_t)pr.p) * wgt[g];
   }
-  return reduce128((uint64_t)tot, (uint64_t)(tot >> 64), pr);
+  return reduce116((uint64_t)tot, (uint64_t)(tot >> 64), pr);   // tot < 4 (2p) p < 2^111
 }
 
 }  // namespace pepsi

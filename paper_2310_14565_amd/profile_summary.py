@@ -7,6 +7,9 @@
     python paper_2310_14565_amd/profile_summary.py counters PMC.db
         per-kernel VALU issue (VALUBusy = SQ_ACTIVE_INST_VALU / CUs / per-XCD GRBM_GUI_ACTIVE),
         VALU instructions, LDS bank conflicts per LDS instruction, from a --pmc database;
+    python paper_2310_14565_amd/profile_summary.py totals PMC.db
+        every counter summed per kernel, with the matrix pipe's busy share and the waves' wait
+        shares where those counters were taken;
     python paper_2310_14565_amd/profile_summary.py traffic FETCH.db WRITE.db BENCH.json
         per-kernel HBM bytes per dispatch from FETCH_SIZE and WRITE_SIZE (KiB), each scaled by
         what the counter reads for the copy kernel of bench.py --copy-calibration (torch.neg of
@@ -150,6 +153,32 @@ def traffic(fetch_db: str, write_db: str, calib_json: str | None):
             print("    per dispatch, written GB: " + " ".join(f"{ws * v / 1e9:.2f}" for v in wk))
 
 
+def totals(db_path: str):
+    """Every counter summed over each kernel's dispatches, with the matrix-pipe and wait shares."""
+    db = sqlite3.connect(db_path)
+    rows = db.execute("select dispatch_id, kernel_name, counter_name, value from counters_collection").fetchall()
+    agg = collections.defaultdict(lambda: collections.defaultdict(float))
+    disp = collections.defaultdict(set)
+    for d, k, c, v in rows:
+        agg[short(k)][c] += v
+        disp[short(k)].add(d)
+    for k, a in agg.items():
+        print(f"== {k}: {len(disp[k])} dispatches")
+        for c in sorted(a):
+            print(f"  {c:28s} {a[c]:.6g}")
+        grbm = a.get("GRBM_GUI_ACTIVE", 0) / XCD
+        if grbm and "SQ_VALU_MFMA_BUSY_CYCLES" in a:
+            print(f"  matrix pipe busy: {a['SQ_VALU_MFMA_BUSY_CYCLES'] / (4 * CU) / grbm:.3f} "
+                  f"(SQ_VALU_MFMA_BUSY_CYCLES / 1024 SIMDs / (GRBM_GUI_ACTIVE / 8))")
+        if a.get("SQ_WAVE_CYCLES"):
+            for c in ("SQ_WAIT_ANY", "SQ_WAIT_INST_ANY"):
+                if c in a:
+                    print(f"  {c} / SQ_WAVE_CYCLES: {a[c] / a['SQ_WAVE_CYCLES']:.3f}")
+        if a.get("SQ_INSTS_MFMA") and a.get("SQ_INSTS_VALU"):
+            print(f"  other VALU instructions per matrix instruction: "
+                  f"{(a['SQ_INSTS_VALU'] - a['SQ_INSTS_MFMA']) / a['SQ_INSTS_MFMA']:.2f}")
+
+
 def main():
     if len(sys.argv) < 3:
         print(__doc__)
@@ -159,6 +188,8 @@ def main():
         kernels(sys.argv[2])
     elif cmd == "counters":
         counters(sys.argv[2])
+    elif cmd == "totals":
+        totals(sys.argv[2])
     elif cmd == "traffic":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4] if len(sys.argv) > 4 else None)
     else:

@@ -1003,8 +1003,8 @@ __global__ void __launch_bounds__(TPB) k_select_sum_planes(Tables T, const int8_
 // the request planes of the workgroup's query octet for its (l, k) staged once in LDS (kbs x 896
 // bytes per query) and reused by every group, so that a query's request planes are read once per
 // run instead of once per tile.  Workgroup = 4 waves on one (l, k) and one octet; wave w takes
-// groups w, w + 4, ...; the next code-position block's plaintext digits are loaded while the
-// current block's 49 products run.  Column m of the products is query m mod 8 of the octet, part
+// groups w, w + 4, ...; the next code-position block's plaintext digits are loaded into one of
+// two register buffers while the current block's 49 products run from the other.  Column m of the products is query m mod 8 of the octet, part
 // m / 8.  In LDS each (part, query) run of kbs x 448 bytes starts at part RUN_CS + query RUN_QS,
 // with RUN_QS = 16 (mod 256) and RUN_CS = 8 RUN_QS = 128 (mod 256): the 16-byte reads of the 16
 // columns then fall on 16 distinct 16-byte bank slots of every 256 bytes (and the 8 columns of a
@@ -1050,17 +1050,12 @@ __global__ void __launch_bounds__(TPB) k_select_sum_planes_run(Tables T, const i
     v4i acc[PL_WEIGHTS];
 #pragma unroll
     for (int s2 = 0; s2 < PL_WEIGHTS; ++s2) acc[s2] = v4i{0, 0, 0, 0};
-    v4i a[PL_DG], an[PL_DG];
+    // two digit buffers used in turn: block kb + 1 loads into one while block kb multiplies from
+    // the other
+    v4i a0[PL_DG], a1[PL_DG];
 #pragma unroll
-    for (int v = 0; v < PL_DG; ++v) an[v] = *reinterpret_cast<const v4i*>(pa + (size_t)v * 16 * PL_K);
-    for (int kb = 0; kb < kbs; ++kb) {
-#pragma unroll
-      for (int v = 0; v < PL_DG; ++v) a[v] = an[v];
-      if (kb + 1 < kbs) {
-#pragma unroll
-        for (int v = 0; v < PL_DG; ++v)
-          an[v] = *reinterpret_cast<const v4i*>(pa + ((size_t)(kb + 1) * PL_DG + v) * 16 * PL_K);
-      }
+    for (int v = 0; v < PL_DG; ++v) a0[v] = *reinterpret_cast<const v4i*>(pa + (size_t)v * 16 * PL_K);
+    auto block = [&](const v4i (&a)[PL_DG], int kb) {
       v4i bb[PL_DG];
 #pragma unroll
       for (int u = 0; u < PL_DG; ++u) bb[u] = *reinterpret_cast<const v4i*>(bq + (kb * PL_DG + u) * PL_K);
@@ -1069,6 +1064,22 @@ __global__ void __launch_bounds__(TPB) k_select_sum_planes_run(Tables T, const i
 #pragma unroll
         for (int u = 0; u < PL_DG; ++u)
           acc[u + v] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[v], bb[u], acc[u + v], 0, 0, 0);
+    };
+    for (int kb = 0; kb < kbs; kb += 2) {
+      if (kb + 1 < kbs) {
+#pragma unroll
+        for (int v = 0; v < PL_DG; ++v)
+          a1[v] = *reinterpret_cast<const v4i*>(pa + ((size_t)(kb + 1) * PL_DG + v) * 16 * PL_K);
+      }
+      block(a0, kb);
+      if (kb + 1 < kbs) {
+        if (kb + 2 < kbs) {
+#pragma unroll
+          for (int v = 0; v < PL_DG; ++v)
+            a0[v] = *reinterpret_cast<const v4i*>(pa + ((size_t)(kb + 2) * PL_DG + v) * 16 * PL_K);
+        }
+        block(a1, kb + 1);
+      }
     }
     if (!live) continue;
 #pragma unroll

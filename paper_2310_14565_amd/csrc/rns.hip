@@ -85,12 +85,14 @@ __device__ __forceinline__ uint64_t round_fp(const uint64_t* y, const double* in
 
 // Exact CRT: X = sum_k y_k * hat_k reduced into [0, M) by v subtractions of M.
 // Returns v; *gt = (2 X > M); X is written to xout when given.
-// The rare path of the kernels' roundings, inlined into them: a call would make every caller
-// keep its live values in callee-saved registers, and an X held in registers would set the
-// caller's register count, so X lives in scratch memory (volatile) and the loops stay rolled.
+// The rare path of the kernels' roundings, inlined into them with its loops rolled: as a call it
+// would make every caller keep its live values in callee-saved registers.  (X is an ordinary
+// local array: a volatile one, kept in scratch memory, would count as a write to any memory, and
+// the constants the callers read after it would then come through vector loads into many
+// registers instead of scalar ones.)
 __device__ __forceinline__ int crt_exact(const uint64_t* y, int cnt, const MWord* hat, const MWord& M,
                                       bool* gt, uint64_t* xout) {
-  volatile uint64_t X[PEPSI_MW];
+  uint64_t X[PEPSI_MW];
 #pragma unroll 1
   for (int w = 0; w < PEPSI_MW; ++w) X[w] = 0;
 #pragma unroll 1
@@ -136,23 +138,32 @@ __device__ __forceinline__ int crt_exact(const uint64_t* y, int cnt, const MWord
   return v;
 }
 
+// Adds a kernel's count of exact-path coefficients to the device counter (when there is one).
+__device__ __forceinline__ void count_exact(uint32_t* fallback, uint32_t nexact) {
+  if (fallback && nexact) atomicAdd(fallback, nexact);
+}
+
 // Exact v = round(sum_i y_i / m_i) over Q (resp. B): the rare path of a centred extension.
+// Each use adds 1 to nexact; a kernel adds its count to the device counter once, after its last
+// store.  (An atomic on the way would make the compiler assume the constants read after it may
+// have changed: it would then read them with vector loads into many registers, not into
+// scalar ones.)
 template <int L>
-__device__ __forceinline__ uint64_t exact_round_q(const Consts& C, const uint64_t* yr, uint32_t* fallback) {
+__device__ __forceinline__ uint64_t exact_round_q(const Consts& C, const uint64_t* yr, uint32_t& nexact) {
   uint64_t y[L];
   for (int i = 0; i < L; ++i) y[i] = yr[i];
   bool gt;
   const uint64_t v = (uint64_t)crt_exact(y, L, C.qhat_w, C.Qw, &gt, nullptr) + (gt ? 1 : 0);
-  if (fallback) atomicAdd(fallback, 1u);
+  ++nexact;
   return v;
 }
 template <int K>
-__device__ __forceinline__ uint64_t exact_round_b(const Consts& C, const uint64_t* yr, uint32_t* fallback) {
+__device__ __forceinline__ uint64_t exact_round_b(const Consts& C, const uint64_t* yr, uint32_t& nexact) {
   uint64_t y[K];
   for (int j = 0; j < K; ++j) y[j] = yr[j];
   bool gt;
   const uint64_t v = (uint64_t)crt_exact(y, K, C.bhat_w, C.Bw, &gt, nullptr) + (gt ? 1 : 0);
-  if (fallback) atomicAdd(fallback, 1u);
+  ++nexact;
   return v;
 }
 
@@ -195,17 +206,17 @@ struct Acc3 {
 // Centred lift of x (residues mod q_0..q_{L-1}) into the residues mod b_0..b_{K-1}, K = L + 1.
 template <int L>
 __device__ __forceinline__ void ext_one(const Consts& C, const uint64_t* x, uint64_t* out,
-                                        uint32_t* fallback) {
+                                        uint32_t& nexact) {
   constexpr int K = L + 1;
   uint64_t y[L];
 #pragma unroll
   for (int i = 0; i < L; ++i) y[i] = shoup(x[i], C.qhat_inv[i], C.qhat_inv_shoup[i], C.prm[i].p);
   bool amb;
   uint64_t v = round_fp<L>(y, C.inv_q_d, &amb);
-  if (amb) v = exact_round_q<L>(C, y, fallback);
   Split27 ys[L];
 #pragma unroll
   for (int i = 0; i < L; ++i) ys[i] = split27(y[i]);
+  if (amb) v = exact_round_q<L>(C, y, nexact);
 #pragma unroll
   for (int j = 0; j < K; ++j) {
     const Prime& P = C.prm[L + j];
@@ -230,9 +241,11 @@ __global__ void __launch_bounds__(TPB) k_ext_q_to_b(Tables T, const uint64_t* __
   uint64_t x[L], o[K];
 #pragma unroll
   for (int i = 0; i < L; ++i) x[i] = in[(row * L + i) * N + k];
-  ext_one<L>(C, x, o, fallback);
+  uint32_t nexact = 0;
+  ext_one<L>(C, x, o, nexact);
 #pragma unroll
   for (int j = 0; j < K; ++j) out[row * ostride + (size_t)j * N + k] = o[j];
+  count_exact(fallback, nexact);
 }
 
 // Relinearised products in coefficient form and their extension to B: row r = job * 2 + c of
@@ -256,9 +269,11 @@ __global__ void __launch_bounds__(TPB) k_add_ext_q_to_b(Tables T, const uint64_t
     x[i] = addmod(c01[(row * L + i) * N + k], key[((unit * 2 + comp) * L + i) * N + k], C.prm[i].p);
     xq[(row * L + i) * N + k] = x[i];
   }
-  ext_one<L>(C, x, o, fallback);
+  uint32_t nexact = 0;
+  ext_one<L>(C, x, o, nexact);
 #pragma unroll
   for (int j = 0; j < K; ++j) xb[(row * K + j) * N + k] = o[j];
+  count_exact(fallback, nexact);
 }
 
 // alpha[b][r][p]: constant added at every NTT position of c0, limb p, for f_r = S + Delta [-r]_t.
@@ -279,13 +294,15 @@ __global__ void k_factor_constants(Tables T, const uint64_t* __restrict__ scoef,
     const uint64_t rd = mulmod(C.delta[i], (uint64_t)r, C.prm[i]);  // r Delta mod q_i
     xr[i] = submod(x[i], rd, q);
   }
-  ext_one<L>(C, x, e0, fallback);
-  ext_one<L>(C, xr, er, fallback);
+  uint32_t nexact = 0;
+  ext_one<L>(C, x, e0, nexact);
+  ext_one<L>(C, xr, er, nexact);
   uint64_t* out = alpha + (size_t)idx * (L + K);
 #pragma unroll
   for (int i = 0; i < L; ++i) out[i] = submod(xr[i], x[i], C.prm[i].p);
 #pragma unroll
   for (int j = 0; j < K; ++j) out[L + j] = submod(er[j], e0[j], C.prm[L + j].p);
+  count_exact(fallback, nexact);
 }
 
 // s = delta_2u + delta_2u+1 mod p and floor(s 2^64 / p) for every (pair, job u, prime p).
@@ -434,6 +451,7 @@ __global__ void __launch_bounds__(TPB) k_scale_round(Tables T, const uint64_t* _
 #pragma unroll
   for (int i = 0; i < L; ++i) fix_add96(a, y[i], C.theta[i]);
   bool amb;
+  uint32_t nexact = 0;
   uint64_t R = fix_round96(a, L, &amb);
   if (amb) {
     // frac(sum y_i r_i / q_i) > 1/2  <=>  the integer with residues y_i r_i (Q/q_i) exceeds Q/2
@@ -443,7 +461,7 @@ __global__ void __launch_bounds__(TPB) k_scale_round(Tables T, const uint64_t* _
     bool gt;
     crt_exact(z, L, C.qhat_w, C.Qw, &gt, nullptr);
     R = a.ip + (gt ? 1 : 0);
-    if (fallback) atomicAdd(fallback, 1u);
+    ++nexact;
   }
   // z_j = round(t d / Q) mod b_j
   uint64_t yb[K];
@@ -462,7 +480,7 @@ __global__ void __launch_bounds__(TPB) k_scale_round(Tables T, const uint64_t* _
     yb[j] = shoup(zj, C.bhat_inv[j], C.bhat_inv_shoup[j], pr.p);
   }
   uint64_t v = round_fp<K>(yb, C.inv_b_d, &amb);
-  if (amb) v = exact_round_b<K>(C, yb, fallback);
+  if (amb) v = exact_round_b<K>(C, yb, nexact);
   Split27 ybs[K];
 #pragma unroll
   for (int j = 0; j < K; ++j) ybs[j] = split27(yb[j]);
@@ -476,6 +494,7 @@ __global__ void __launch_bounds__(TPB) k_scale_round(Tables T, const uint64_t* _
     for (int j = 0; j < K; ++j) acc.mac(ybs[j], C.bhat_mod_q[j][i]);
     dst[(size_t)i * N + k] = acc.reduce(pr);
   }
+  count_exact(fallback, nexact);
 }
 
 // D_i = [c2 (Q/q_i)^-1]_{q_i} of every unit, as residues mod every q_j: D [unit][i][j][N].
@@ -903,26 +922,28 @@ __global__ void __launch_bounds__(TPB) k_plaintext_planes(Tables T, const uint64
     __builtin_memcpy(out + ((w * PL_DG + v) * 16 + b) * PL_K + 16 * g4, o[v], 16);
 }
 // Request planes of one query, layout [l][k][kb][digit][part][64], from its NTT form
-// [ell][2][L][N].  Workgroup = one (l, 64 positions, kb): wave w reads code positions
-// 16 w .. 16 w + 15 of both parts for its 64 positions (one 512-byte row per load) and writes
+// [ell][2][L][N].  Workgroup = one (l, 32 positions, kb): the threads of one half-wave read 8 code
+// positions of both parts for its 32 positions (one 256-byte row segment per load) and write
 // their digits byte by byte to LDS as [position][digit][part][64]; the workgroup then copies
-// each position's 896 contiguous bytes out.
-constexpr int RP_ROW = PL_DG * 2 * PL_K + 16;   // LDS bytes per position (padded)
+// each position's 896 contiguous bytes out.  29 KB of LDS per workgroup, so that 5 fit on a CU.
+constexpr int RP_POS = 32;                             // positions per workgroup
+constexpr int RP_ROW = PL_DG * 2 * PL_K + 16;          // LDS bytes per position (padded)
 __global__ void __launch_bounds__(TPB) k_request_planes(Tables T, const uint64_t* __restrict__ ch, int ell, int kbs,
                                                        int8_t* __restrict__ out) {
-  __shared__ __align__(16) int8_t sm[64 * RP_ROW];
+  __shared__ __align__(16) int8_t sm[RP_POS * RP_ROW];
+  constexpr int JH = TPB / RP_POS, JE = PL_K / JH;      // 8 thread groups of 8 code positions
   const Consts& C = *T.c;
   const int N = C.n, L = C.L;
   const int kb = (int)(blockIdx.x % kbs);
-  const int blk = (int)(blockIdx.x / kbs);            // (l, 64-position block)
-  const int k0 = (blk % (N / 64)) * 64, l = blk / (N / 64);
-  const int kk = threadIdx.x & 63, jq = threadIdx.x >> 6;
+  const int blk = (int)(blockIdx.x / kbs);            // (l, RP_POS-position block)
+  const int k0 = (blk % (N / RP_POS)) * RP_POS, l = blk / (N / RP_POS);
+  const int kk = threadIdx.x % RP_POS, jh = threadIdx.x / RP_POS;
   const uint64_t p = C.prm[l].p;
-  int8_t* row = sm + kk * RP_ROW + jq * 16;
+  int8_t* row = sm + kk * RP_ROW + jh * JE;
   for (int c = 0; c < 2; ++c)
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int j = kb * PL_K + jq * 16 + e;
+    for (int e = 0; e < JE; ++e) {
+      const int j = kb * PL_K + jh * JE + e;
       uint64_t x = 0;
       if (j < ell) {
         x = ch[(((size_t)j * 2 + c) * L + l) * N + k0 + kk];
@@ -937,7 +958,7 @@ __global__ void __launch_bounds__(TPB) k_request_planes(Tables T, const uint64_t
   constexpr int CH = PL_DG * 2 * PL_K / 16;             // 16-byte chunks per position
   int8_t* dst = out + ((((size_t)l * N + k0) * kbs + kb) * PL_DG * 2) * PL_K;
   const size_t kstride = (size_t)kbs * PL_DG * 2 * PL_K;
-  for (int x = threadIdx.x; x < 64 * CH; x += TPB) {
+  for (int x = threadIdx.x; x < RP_POS * CH; x += TPB) {
     const int pos = x / CH, r = x % CH;
     uint4 v;
     __builtin_memcpy(&v, sm + pos * RP_ROW + r * 16, 16);
@@ -1500,8 +1521,8 @@ void plaintext_planes(const Tables& T, const Consts& hc, const uint64_t* P, int 
 }
 void request_planes(const Tables& T, const Consts& hc, const uint64_t* ch, int ell, int8_t* out, hipStream_t s) {
   const int kbs = plane_kblocks(ell);
-  hipLaunchKernelGGL(k_request_planes, dim3((unsigned)((size_t)hc.L * (hc.n / 64) * kbs)), dim3(TPB), 0, s, T, ch,
-                     ell, kbs, out);
+  hipLaunchKernelGGL(k_request_planes, dim3((unsigned)((size_t)hc.L * (hc.n / RP_POS) * kbs)), dim3(TPB), 0, s, T,
+                     ch, ell, kbs, out);
 }
 void select_sum_planes(const Tables& T, const Consts& hc, const int8_t* Pp, const int8_t* Cp, long cps,
                        const int* qslot, int nq, int nb, int ell, uint64_t* S, hipStream_t s) {

@@ -87,12 +87,13 @@ def traffic_record(kernel: str):
 # eight single-issue operations.
 BUTTERFLY_MIX = {"v_mad_u64_u32": 3, "v_mul_hi_u32": 2, "v_mul_lo_u32": 4, "v_add_u32": 8}
 CHIP_LANE_ISSUE = 256 * 64 * 2.4e9          # 256 CUs x 64 lanes x 2.4 GHz, one VALU op per lane per clock
+PRODUCT_MADS = 3                             # v_mad_u64_u32 per exact 54-bit product (27-bit halves)
 
 
 def valu_roofline(pk, tm, n):
-    """Integer-VALU roofline of the transforms: measured issue rates of the butterfly's instructions
-    (pepsi_probe_valu) give the peak butterfly rate; the engine's event-timed transforms of the timed
-    steps give the achieved one."""
+    """Integer-VALU roofline of the transforms, rescales and extensions: measured issue rates of
+    their instructions (pepsi_probe_valu) give the peak butterfly and modular-product rates; the
+    engine's event-timed launches of the timed steps give the achieved ones."""
     rates = {k: pk.probe_valu(i) for i, k in enumerate(pk.VALU_KINDS)}
     sec_per_bfly = sum(cnt / rates[k] for k, cnt in BUTTERFLY_MIX.items())   # per lane, whole chip
     peak = 1.0 / sec_per_bfly
@@ -110,6 +111,20 @@ def valu_roofline(pk, tm, n):
                      "unit": "Gbutterfly/s", "frac": round(achieved / peak, 4),
                      "avg_launch_ms": round(ms / launches, 4), "rows_per_launch": round(rows / launches, 1),
                      "ns_per_row": round(1e6 * ms / rows, 2)}
+    # The exact rescales and Q -> B extensions, in 54-bit modular products (pepsi_timing): each
+    # costs at least three v_mad_u64_u32 (27-bit halves into 64-bit accumulators), so the peak is
+    # a third of that instruction's measured rate.
+    peak_prod = rates["v_mad_u64_u32"] / PRODUCT_MADS
+    out["product_mix"] = {"v_mad_u64_u32": PRODUCT_MADS}
+    for name, prods, ms, launches in (("k_scale_round", tm.rescale_products, tm.rescale_ms, tm.rescale_launches),
+                                      ("k_ext_q_to_b", tm.ext_products, tm.ext_ms, tm.ext_launches)):
+        if not launches or ms <= 0:
+            continue
+        achieved = prods / (ms / 1e3)
+        out[name] = {"bound": "alu", "achieved": round(achieved / 1e9, 1), "peak": round(peak_prod / 1e9, 1),
+                     "unit": "G modular products/s", "frac": round(achieved / peak_prod, 4),
+                     "avg_launch_ms": round(ms / launches, 4),
+                     "products_per_launch": int(prods / launches)}
     return out
 
 

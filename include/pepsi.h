@@ -406,7 +406,8 @@ void pepsi_serve_destroy(pepsi_serve* serve);
 /* Event timing of a server's evaluations, for measurement.  While enabled,
  * every select-and-sum launch (the kernel that streams the server plaintexts),
  * every forward and inverse transform of the request, the product tree and the
- * finish, and every whole evaluation are bracketed by HIP events on the
+ * finish, every exact rescale and Q -> B extension of the product tree, and every whole
+ * evaluation are bracketed by HIP events on the
  * evaluation's stream.  The call synchronises the device, folds finished event pairs into
  * the totals, then applies reset (zero the totals) and enable (1 on, 0 off). */
 typedef struct {
@@ -420,6 +421,17 @@ typedef struct {
   double ntt_fwd_ms;
   uint64_t ntt_inv_launches, ntt_inv_rows;  /* and their inverse transforms                   */
   double ntt_inv_ms;
+  /* The exact rescales round(t d / Q) of the product tree (k_scale_round) and the exact Q -> B
+   * extensions (k_ext_q_to_b, k_add_ext_q_to_b), with their 54-bit modular products: per
+   * coefficient, a rescale takes L + K products y_p = d_p (P/p)^-1 (L + K more with the first
+   * level's linear terms), K (L + 1) for the sums into B, K for their scaling and L (K + 1) for the
+   * sums back into Q; an extension L + K (L + 1).  A product is one Shoup multiplication or one
+   * term of an exact sum of products; each costs at least three 32 x 32 -> 64-bit multiply-adds
+   * (27-bit halves). */
+  uint64_t rescale_launches, rescale_products;
+  double rescale_ms;
+  uint64_t ext_launches, ext_products;
+  double ext_ms;
 } pepsi_timing;
 int pepsi_server_timing(pepsi_server* server, int enable, int reset, pepsi_timing* out);
 

@@ -85,7 +85,9 @@ class Timing(C.Structure):
     _fields_ = [("select_sum_launches", C.c_uint64), ("select_sum_bytes", C.c_uint64),
                 ("select_sum_ms", C.c_double), ("evals", C.c_uint64), ("eval_ms", C.c_double),
                 ("ntt_fwd_launches", C.c_uint64), ("ntt_fwd_rows", C.c_uint64), ("ntt_fwd_ms", C.c_double),
-                ("ntt_inv_launches", C.c_uint64), ("ntt_inv_rows", C.c_uint64), ("ntt_inv_ms", C.c_double)]
+                ("ntt_inv_launches", C.c_uint64), ("ntt_inv_rows", C.c_uint64), ("ntt_inv_ms", C.c_double),
+                ("rescale_launches", C.c_uint64), ("rescale_products", C.c_uint64), ("rescale_ms", C.c_double),
+                ("ext_launches", C.c_uint64), ("ext_products", C.c_uint64), ("ext_ms", C.c_double)]
 
 
 _SIGS = {

@@ -459,6 +459,8 @@ struct EventTimer {
       if (p.kind == 0) { tot.select_sum_launches++; tot.select_sum_ms += ms; tot.select_sum_bytes += p.bytes; }
       else if (p.kind == 2) { tot.ntt_fwd_launches++; tot.ntt_fwd_ms += ms; tot.ntt_fwd_rows += p.bytes; }
       else if (p.kind == 3) { tot.ntt_inv_launches++; tot.ntt_inv_ms += ms; tot.ntt_inv_rows += p.bytes; }
+      else if (p.kind == 4) { tot.rescale_launches++; tot.rescale_ms += ms; tot.rescale_products += p.bytes; }
+      else if (p.kind == 5) { tot.ext_launches++; tot.ext_ms += ms; tot.ext_products += p.bytes; }
       else { tot.evals++; tot.eval_ms += ms; }
       pool.push_back(p.a);
       pool.push_back(p.b);
@@ -535,6 +537,22 @@ struct Engine {
     ntt_inverse(P->T, P->H.logn, in, out, rows, nprimes, first, s);
     if (a) { (void)hipEventRecord(b, s); timer->pending.push_back({a, b, 3, (uint64_t)rows}); }
   }
+  // A rescale (kind 4) or Q -> B extension (kind 5) launch, event-timed with its 54-bit modular
+  // products (as counted in pepsi_timing) while the server's timer is on.
+  template <class F>
+  void timed_rns(int kind, uint64_t products, hipStream_t s, F&& launch) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (timer && timer->on && products > 0) { a = timer->get(); b = timer->get(); (void)hipEventRecord(a, s); }
+    launch();
+    if (a) { (void)hipEventRecord(b, s); timer->pending.push_back({a, b, kind, products}); }
+  }
+  // products per coefficient of a rescale (plus L + K with the first level's linear terms) and
+  // of an extension
+  uint64_t rescale_products() const {
+    const uint64_t L = P->H.L, K = P->H.K;
+    return (L + K) + K * (L + 1) + K + L * (K + 1);
+  }
+  uint64_t ext_products() const { return P->H.L + P->H.K * (P->H.L + 1); }
 
   size_t cstride() const { return (size_t)P->H.ell * 2 * P->H.L * P->H.n; }
   size_t rstride() const { return (size_t)P->H.L * 2 * P->H.L * P->H.n; }
@@ -657,8 +675,10 @@ struct Engine {
       relin_inner(P->T, H.consts, nullptr, D.as<uint64_t>(), key, (long)rstride(), qslot, 1, units_per_pair, nq, kh,
                   units, s);
       tinv(kh, kh, units * 2 * L, L, 0, s);
-      add_ext_q_to_b(P->T, H.consts, c01.as<uint64_t>(), kh, jobs_per_unit, rcoef.as<uint64_t>(), ext_out,
-                     njobs * 2, P->fallback.as<uint32_t>(), s);
+      timed_rns(5, (uint64_t)njobs * 2 * H.n * ext_products(), s, [&] {
+        add_ext_q_to_b(P->T, H.consts, c01.as<uint64_t>(), kh, jobs_per_unit, rcoef.as<uint64_t>(), ext_out,
+                       njobs * 2, P->fallback.as<uint32_t>(), s);
+      });
       tfwd(rcoef.p, out, njobs * 2 * L, L, 0, s);
       tfwd(ext_out, ext_out, njobs * 2 * K, K, L, s);
     } else {
@@ -675,9 +695,14 @@ struct Engine {
     const HostParams& H = P->H;
     uint64_t* dd = d.as<uint64_t>();
     tinv_products(INV_SQUARES, Sq, sbh.as<uint64_t>(), nullptr, dd, npairs, s);
-    scale_round_first(P->T, H.consts, dd, scoef.as<uint64_t>(), sb.as<uint64_t>(), alpha.as<uint64_t>(),
-                      pconst.as<uint64_t>(), H.h, npairs, c01.as<uint64_t>(), c2.as<uint64_t>(),
-                      P->fallback.as<uint32_t>(), s);
+    const uint64_t J0 = H.h / 2;
+    const uint64_t prod =
+        H.h < 2 ? 0 : (uint64_t)npairs * H.n * ((2 * J0 + 1) * rescale_products() + 2 * J0 * (H.L + H.K));
+    timed_rns(4, prod, s, [&] {
+      scale_round_first(P->T, H.consts, dd, scoef.as<uint64_t>(), sb.as<uint64_t>(), alpha.as<uint64_t>(),
+                        pconst.as<uint64_t>(), H.h, npairs, c01.as<uint64_t>(), c2.as<uint64_t>(),
+                        P->fallback.as<uint32_t>(), s);
+    });
   }
 
   // A later tree level: njobs independent products (TensorJob operands, tensored while their
@@ -686,7 +711,9 @@ struct Engine {
     const HostParams& H = P->H;
     uint64_t* dd = d.as<uint64_t>();
     tinv_products(INV_TENSOR, nullptr, nullptr, dev_jobs, dd, njobs, s);
-    scale_round(P->T, H.consts, dd, c01.as<uint64_t>(), c2.as<uint64_t>(), njobs, P->fallback.as<uint32_t>(), s);
+    timed_rns(4, (uint64_t)njobs * 3 * H.n * rescale_products(), s, [&] {
+      scale_round(P->T, H.consts, dd, c01.as<uint64_t>(), c2.as<uint64_t>(), njobs, P->fallback.as<uint32_t>(), s);
+    });
   }
 
   size_t cpstride() const { return request_plane_bytes(P->H.consts, P->H.ell); }
@@ -815,8 +842,10 @@ struct Engine {
       }
     }
     tinv(Sq, scoef.as<uint64_t>(), npairs * 2 * (int)L, (int)L, 0, s);
-    ext_q_to_b(P->T, H.consts, scoef.as<uint64_t>(), sb.as<uint64_t>(), (long)(K * n), npairs * 2,
-               P->fallback.as<uint32_t>(), s);
+    timed_rns(5, (uint64_t)npairs * 2 * n * ext_products(), s, [&] {
+      ext_q_to_b(P->T, H.consts, scoef.as<uint64_t>(), sb.as<uint64_t>(), (long)(K * n), npairs * 2,
+                 P->fallback.as<uint32_t>(), s);
+    });
     tfwd(sb.p, sbh.p, npairs * 2 * (int)K, (int)K, (int)L, s);
     factor_constants(P->T, H.consts, scoef.as<uint64_t>(), npairs, H.h, alpha.as<uint64_t>(), pconst.as<uint64_t>(),
                      P->fallback.as<uint32_t>(), s);

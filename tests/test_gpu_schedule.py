@@ -116,3 +116,28 @@ def test_schedule_arguments(setup):
             sv.set_schedule(**bad)
     sv.set_schedule(reset=True)
     assert sv.schedule(3).source in (0, 1)
+
+
+def test_event_timing_counts(setup):
+    """pepsi_server_timing: a plain evaluation's select-and-sum, transforms, rescales and
+    extensions are timed, with the product counts the header states (h = 4: two first-level
+    products per pair sharing their squares, one second-level product, the last level's
+    relinearisation deferred)."""
+    st = setup
+    sv, L, n = st["sv"], st["L"], st["n"]
+    K = L + 1
+    x = st["d"][0]
+    o = empty((2, L, n), np.uint64)
+    sv.timing(enable=True, reset=True)
+    sv.eval(x["cts"], x["rlk"], x["mask"], o)
+    tm = sv.timing(enable=False)
+    assert (to_host(o, np.uint64) == st["alone"][0]).all()
+    assert tm.evals == 1 and tm.eval_ms > 0
+    assert tm.select_sum_launches >= 1 and tm.select_sum_ms > 0
+    assert tm.ntt_fwd_rows > 0 and tm.ntt_inv_rows > 0
+    npairs = sv.max_load                       # batches at or above the fullest bin are skipped
+    base = (L + K) + K * (L + 1) + K + L * (K + 1)
+    j0 = 2
+    assert tm.rescale_products == npairs * n * ((2 * j0 + 1) * base + 2 * j0 * (L + K) + 3 * base)
+    assert tm.ext_products == npairs * n * (L + K * (L + 1)) * (2 + 2 * j0)
+    assert tm.rescale_launches >= 2 and tm.rescale_ms > 0 and tm.ext_launches >= 2 and tm.ext_ms > 0

@@ -43,10 +43,30 @@ constexpr bool ntt_direct(int d) { return d <= 1; }
 
 __device__ __forceinline__ int lds_idx(int j) { return j + (j >> 5); }
 
+// Group index of (thread, u) in a pass of D stages (G = 2^(EL - D) groups of 2^D registers per
+// thread): the G groups of a thread are 64 apart and the 64 G groups of a wave are contiguous.
+// A pass then keeps each wave on words [64 E w, 64 E (w + 1)) of the row (wave w, E = 2^EL) when
+// its blocks of 2^(LOGN - S0) words have spans LOW = 2^(LOGN - S0 - D) dividing 64 G, that is
+// when S0 >= LOGN - 6 - EL (wave_local); between two such passes a wave reads back only words it
+// wrote itself, so it needs no workgroup barrier.
+template <int EL, int D>
+__device__ __forceinline__ int group_of(int tid, int u) {
+  constexpr int G = 1 << (EL - D);
+  return G == 1 ? tid : (tid >> 6) * 64 * G + u * 64 + (tid & 63);
+}
+template <int LOGN, int EL>
+constexpr bool wave_local(int s0) { return s0 >= LOGN - 6 - EL; }
+// Orders a wave's LDS writes before its later reads of words other lanes wrote.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int LOGN, int EL, int S0, int D>
 __device__ __forceinline__ int elem_index(int tid, int u, int m) {
-  constexpr int N = 1 << LOGN, T = N >> EL, LOW = N >> (S0 + D);
-  const int g = tid + T * u;
+  constexpr int N = 1 << LOGN, LOW = N >> (S0 + D);
+  const int g = group_of<EL, D>(tid, u);
   return (g / LOW) * (N >> S0) + m * LOW + (g % LOW);
 }
 // lds_idx(elem_index(tid, u, m)) as a part that depends on the thread and u plus a compile-time
@@ -57,8 +77,8 @@ __device__ __forceinline__ int elem_index(int tid, int u, int m) {
 // 2^(LOGN - S0) < 32 divides 32 (then nothing inside a block carries past a multiple of 32).
 template <int LOGN, int EL, int S0, int D>
 __device__ __forceinline__ int lds_base(int tid, int u) {
-  constexpr int N = 1 << LOGN, T = N >> EL, LOW = N >> (S0 + D);
-  const int g = tid + T * u;
+  constexpr int N = 1 << LOGN, LOW = N >> (S0 + D);
+  const int g = group_of<EL, D>(tid, u);
   const int a = (g / LOW) * (N >> S0), r = g % LOW;
   return a + (a >> 5) + r + (r >> 5);
 }
@@ -71,11 +91,11 @@ constexpr int lds_off(int m) {
 template <int LOGN, int EL, int S0, int D>
 __device__ __forceinline__ void fwd_pass(uint64_t* x, int tid, const uint64_t* __restrict__ W,
                                          const uint64_t* __restrict__ Wq, uint64_t p) {
-  constexpr int N = 1 << LOGN, T = N >> EL, LOW = N >> (S0 + D), G = 1 << (EL - D);
+  constexpr int N = 1 << LOGN, LOW = N >> (S0 + D), G = 1 << (EL - D);
   const uint64_t four_p = 4 * p;
 #pragma unroll
   for (int u = 0; u < G; ++u) {
-    const int hi = (tid + T * u) / LOW;
+    const int hi = group_of<EL, D>(tid, u) / LOW;
 #pragma unroll
     for (int r = 0; r < D; ++r) {
       const int half = 1 << (D - 1 - r);
@@ -110,11 +130,11 @@ constexpr int inv_bound(int j, int m) {
 template <int LOGN, int EL, int S0, int D, bool RED>
 __device__ __forceinline__ void inv_pass(uint64_t* x, int tid, const uint64_t* __restrict__ W,
                                          const uint64_t* __restrict__ Wq, uint64_t p) {
-  constexpr int N = 1 << LOGN, T = N >> EL, LOW = N >> (S0 + D), G = 1 << (EL - D);
+  constexpr int N = 1 << LOGN, LOW = N >> (S0 + D), G = 1 << (EL - D);
   const uint64_t four_p = 4 * p;
 #pragma unroll
   for (int u = 0; u < G; ++u) {
-    const int hi = (tid + T * u) / LOW;
+    const int hi = group_of<EL, D>(tid, u) / LOW;
 #pragma unroll
     for (int r = D - 1; r >= 0; --r) {
       const int half = 1 << (D - 1 - r);
@@ -172,7 +192,9 @@ __device__ __forceinline__ void fwd_passes(uint64_t* x, uint64_t* lds, int tid,
                                            const uint64_t* __restrict__ W,
                                            const uint64_t* __restrict__ Wq, uint64_t p) {
   constexpr int D = (LOGN - S0 < EL) ? LOGN - S0 : EL;
-  __syncthreads();
+  // the previous pass (stages [S0 - EL, S0)) wrote what this one reads
+  if constexpr (wave_local<LOGN, EL>(S0 - EL) && wave_local<LOGN, EL>(S0)) wave_sync();
+  else __syncthreads();
   from_lds<LOGN, EL, S0, D>(x, lds, tid);
   fwd_pass<LOGN, EL, S0, D>(x, tid, W, Wq, p);
   if constexpr (S0 + D < LOGN) {
@@ -190,7 +212,9 @@ __device__ __forceinline__ void inv_passes(uint64_t* x, uint64_t* lds, int tid,
                                            const uint64_t* __restrict__ W,
                                            const uint64_t* __restrict__ Wq, uint64_t p) {
   constexpr int S0 = K * EL, D = (LOGN - S0 < EL) ? LOGN - S0 : EL;
-  __syncthreads();
+  // the previous pass (stages from S0 + EL up) wrote what this one reads
+  if constexpr (wave_local<LOGN, EL>(S0 + EL) && wave_local<LOGN, EL>(S0)) wave_sync();
+  else __syncthreads();
   from_lds<LOGN, EL, S0, D>(x, lds, tid);
   inv_pass<LOGN, EL, S0, D, true>(x, tid, W, Wq, p);
   to_lds<LOGN, EL, S0, D>(lds, x, tid);
@@ -375,6 +399,7 @@ k_ntt_inv(Tables T, const uint64_t* __restrict__ in, uint64_t* __restrict__ out,
       const int j = m * TT + tid;
       lds[lds_idx(j)] = src_row.at(N, j);
     }
+    __syncthreads();   // written in row order, read by the first pass's groups
     inv_passes<LOGN, EL, NP - 1>(x, lds, tid, W, Wq, p);
   }
   __syncthreads();
@@ -433,10 +458,10 @@ __device__ __forceinline__ uint32_t mulmod_t16(uint32_t a, uint32_t b) {
 // register layout of inv_pass.
 template <int LOGN, int EL, int S0, int D>
 __device__ __forceinline__ void inv_pass_t(uint32_t* x, int tid, const uint32_t* __restrict__ W) {
-  constexpr int N = 1 << LOGN, T = N >> EL, LOW = N >> (S0 + D), G = 1 << (EL - D);
+  constexpr int N = 1 << LOGN, LOW = N >> (S0 + D), G = 1 << (EL - D);
 #pragma unroll
   for (int u = 0; u < G; ++u) {
-    const int hi = (tid + T * u) / LOW;
+    const int hi = group_of<EL, D>(tid, u) / LOW;
 #pragma unroll
     for (int r = D - 1; r >= 0; --r) {
       const int half = 1 << (D - 1 - r);

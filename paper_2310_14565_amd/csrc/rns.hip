@@ -531,10 +531,21 @@ __global__ void __launch_bounds__(TPB) k_relin_inner(Tables T, const uint64_t* _
   const int N = C.n;
   const int k = blockIdx.x * TPB + threadIdx.x;
   const int j = blockIdx.y;
-  const size_t unit = blockIdx.z;
+  // The units of one query follow each other in launch order (when every query has as many), so
+  // that its key's rows stay in L2 while they are read; unit = pair * units_per_pair + r with
+  // pair = b * nq + q.
+  size_t unit = blockIdx.z;
+  int q;
+  const size_t per_q = gridDim.z / nq;
+  if (gridDim.z % ((size_t)nq * units_per_pair) == 0) {
+    q = (int)(blockIdx.z / per_q);
+    const size_t rz = blockIdx.z % per_q;
+    unit = ((rz / units_per_pair) * nq + q) * units_per_pair + rz % units_per_pair;
+  } else {
+    q = (int)((unit / units_per_pair) % nq);
+  }
   if (k >= N) return;
   const Prime& pr = C.prm[j];
-  const int q = (int)((unit / units_per_pair) % nq);
   const uint64_t* rlk = rlk_base + (size_t)(qslot ? qslot[q] : q) * rlk_stride;
   u128 a0 = 0, a1 = 0;
 #pragma unroll

@@ -1034,8 +1034,8 @@ __global__ void __launch_bounds__(TPB) k_select_sum_planes(Tables T, const int8_
 // The contraction over a run of ngroups consecutive 16-batch groups of planes in one launch, with
 // the request planes of the workgroup's query octet for its (l, k) staged once in LDS (kbs x 896
 // bytes per query) and reused by every group, so that a query's request planes are read once per
-// run instead of once per tile.  Workgroup = 4 waves on one (l, k) and one octet; wave w takes
-// groups w, w + 4, ...; the next code-position block's plaintext digits are loaded into one of
+// run instead of once per tile.  Workgroup = RUN_WAVES waves on one (l, k) and one octet; wave w
+// takes groups w, w + RUN_WAVES, ...; the next code-position block's plaintext digits are loaded into one of
 // two register buffers while the current block's 49 products run from the other.  Column m of the products is query m mod 8 of the octet, part
 // m / 8.  In LDS each (part, query) run of kbs x 448 bytes starts at part RUN_CS + query RUN_QS,
 // with RUN_QS = 16 (mod 256) and RUN_CS = 8 RUN_QS = 128 (mod 256): the 16-byte reads of the 16
@@ -1046,7 +1046,10 @@ __global__ void __launch_bounds__(TPB) k_select_sum_planes(Tables T, const int8_
 __host__ __device__ constexpr int run_qs(int kbs) {
   return kbs * PL_DG * PL_K + (((16 - kbs * PL_DG * PL_K) % 256) + 256) % 256;
 }
-__global__ void __launch_bounds__(TPB) k_select_sum_planes_run(Tables T, const int8_t* __restrict__ Pp, long gbytes,
+// RUN_WPE = 2 (the occupancy that the LDS allows) keeps the accumulators in ordinary VGPRs; without
+// it the compiler moves them to AGPRs and the products' results pass through extra moves.
+constexpr int RUN_WAVES = 4, RUN_TPB = 64 * RUN_WAVES, RUN_WPE = 2;
+__global__ void __launch_bounds__(RUN_TPB) __attribute__((amdgpu_waves_per_eu(RUN_WPE))) k_select_sum_planes_run(Tables T, const int8_t* __restrict__ Pp, long gbytes,
                                                               int ngroups, const int8_t* __restrict__ Cp, long cps,
                                                               const int* __restrict__ qslot, int nq, int nb, int kbs,
                                                               uint64_t* __restrict__ S, int oblocks) {
@@ -1061,7 +1064,7 @@ __global__ void __launch_bounds__(TPB) k_select_sum_planes_run(Tables T, const i
   // stage the octet's request planes, source [kb][digit][part][64] per query, zeros past the
   // last query
   const int chunks = kbs * PL_DG * 2 * PL_K / 16;       // 16-byte chunks per query
-  for (int x = threadIdx.x; x < 8 * chunks; x += TPB) {
+  for (int x = threadIdx.x; x < 8 * chunks; x += RUN_TPB) {
     const int qi = x / chunks, r = x % chunks;
     const int q = oct * 8 + qi;
     uint4 v = {0, 0, 0, 0};
@@ -1077,7 +1080,7 @@ __global__ void __launch_bounds__(TPB) k_select_sum_planes_run(Tables T, const i
   const Prime& pr = C.prm[l];
   uint64_t wgt[4];
   plane_group_weights(pr, wgt);
-  for (int g = wv; g < ngroups; g += 4) {
+  for (int g = wv; g < ngroups; g += RUN_WAVES) {
     const int8_t* pa = Pp + (size_t)g * gbytes + ((size_t)lk * kbs * PL_DG * 16 + m) * PL_K + 16 * g4;
     v4i acc[PL_WEIGHTS];
 #pragma unroll
@@ -1571,7 +1574,7 @@ void select_sum_planes_run(const Tables& T, const Consts& hc, const int8_t* Pp, 
   const int lks = hc.L * hc.n;   // a multiple of 8
   const long gb = (long)plaintext_plane_group_bytes(hc, ell);
   const size_t lds = (size_t)2 * 8 * run_qs(kbs);
-  hipLaunchKernelGGL(k_select_sum_planes_run, dim3(lks * oblocks), dim3(TPB), lds, s, T, Pp, gb, ngroups, Cp, cps,
+  hipLaunchKernelGGL(k_select_sum_planes_run, dim3(lks * oblocks), dim3(RUN_TPB), lds, s, T, Pp, gb, ngroups, Cp, cps,
                      qslot, nq, nb, kbs, S, oblocks);
 }
 void pointwise_mul(const Tables& T, const Consts& hc, const uint64_t* a, const uint64_t* b,

@@ -1063,21 +1063,42 @@ __global__ void __launch_bounds__(RUN_TPB) __attribute__((amdgpu_waves_per_eu(RU
   const int QS = run_qs(kbs), CS = 8 * QS;
   // stage the octet's request planes, source [kb][digit][part][64] per query, zeros past the
   // last query
+  // (all of a thread's loads in flight together -- at most two 16-byte chunks per query -- so that
+  // the staging costs about one memory latency; a missing query reads query 0's planes and stages
+  // zeros)
   const int chunks = kbs * PL_DG * 2 * PL_K / 16;       // 16-byte chunks per query
-  for (int x = threadIdx.x; x < 8 * chunks; x += RUN_TPB) {
-    const int qi = x / chunks, r = x % chunks;
+  static_assert(PL_RUN_KBS * PL_DG * 2 * PL_K / 16 <= 2 * RUN_TPB, "two chunks per thread and query");
+  int qs[8];
+#pragma unroll
+  for (int qi = 0; qi < 8; ++qi) {
     const int q = oct * 8 + qi;
-    uint4 v = {0, 0, 0, 0};
-    if (q < nq)
-      __builtin_memcpy(&v, Cp + (size_t)(qslot ? qslot[q] : q) * cps + ((size_t)lk * chunks + r) * 16, 16);
-    const int quarter = r & 3, part = (r >> 2) & 1, kd = r >> 3;   // kd = kb * PL_DG + digit
-    __builtin_memcpy(sB + part * CS + qi * QS + kd * PL_K + quarter * 16, &v, 16);
+    qs[qi] = q < nq ? (qslot ? qslot[q] : q) : 0;
   }
+  uint4 v[8][2];
+#pragma unroll
+  for (int qi = 0; qi < 8; ++qi) {
+    const int8_t* src = Cp + (size_t)qs[qi] * cps + (size_t)lk * chunks * 16;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int r = threadIdx.x + h * RUN_TPB;
+      if (r < chunks) __builtin_memcpy(&v[qi][h], src + (size_t)r * 16, 16);
+    }
+  }
+#pragma unroll
+  for (int qi = 0; qi < 8; ++qi)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int r = threadIdx.x + h * RUN_TPB;
+      if (r >= chunks) continue;
+      const uint4 w = oct * 8 + qi < nq ? v[qi][h] : uint4{0, 0, 0, 0};
+      const int quarter = r & 3, part = (r >> 2) & 1, kd = r >> 3;   // kd = kb * PL_DG + digit
+      __builtin_memcpy(sB + part * CS + qi * QS + kd * PL_K + quarter * 16, &w, 16);
+    }
   __syncthreads();
   const int q = oct * 8 + (m & 7), c = m >> 3;
   const bool live = q < nq;
   const int8_t* bq = sB + c * CS + (m & 7) * QS + 16 * g4;
-  const Prime& pr = C.prm[l];
+  const Prime pr = C.prm[l];                        // a copy: the stores to S do not reload it
   uint64_t wgt[4];
   plane_group_weights(pr, wgt);
   for (int g = wv; g < ngroups; g += RUN_WAVES) {

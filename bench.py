@@ -88,6 +88,8 @@ def traffic_record(kernel: str):
 BUTTERFLY_MIX = {"v_mad_u64_u32": 3, "v_mul_hi_u32": 2, "v_mul_lo_u32": 4, "v_add_u32": 8}
 CHIP_LANE_ISSUE = 256 * 64 * 2.4e9          # 256 CUs x 64 lanes x 2.4 GHz, one VALU op per lane per clock
 PRODUCT_MADS = 3                             # v_mad_u64_u32 per exact 54-bit product (27-bit halves)
+MFMA_DIGIT_PAIRS = 7 * 7                     # balanced int8 digits per 54-bit residue, squared
+INT8_DENSE_PEAK_T = 5000.0                   # MI355X dense int8 matrix peak, TOP/s
 
 
 def valu_roofline(pk, tm, n):
@@ -478,6 +480,20 @@ def batched_leg(pk, params, server, server_items, cfg, nq, steps, seed, plain_va
         log("[bench] batched results differ between schedules")
         sys.exit(1)
     value = nq * n * cfg["mu"] / t
+    roof = None
+    if sched["select_kernel"].startswith("int8 matrix") and tm.select_sum_launches and tm.select_sum_ms > 0:
+        # int8 multiply-adds of the digit-plane contraction: per computed batch, query, component,
+        # limb and slot, ell code positions x 7 x 7 digit pairs, 2 operations each
+        ops = server.max_load * nq * 2 * L * n * params.ell * MFMA_DIGIT_PAIRS * 2
+        achieved = ops / (tm.select_sum_ms / 1e3)
+        measured = pk.probe_mfma_int8()
+        roof = {"kernel": "k_select_sum_planes_run" if sched.get("run", "").startswith("one") else "k_select_sum_planes",
+                "bound": "mfma", "achieved": round(achieved / 1e12, 1), "peak": INT8_DENSE_PEAK_T,
+                "unit": "TOP/s (int8)", "frac": round(achieved / 1e12 / INT8_DENSE_PEAK_T, 4),
+                "measured_instruction_peak": round(measured / 1e12, 1),
+                "frac_of_measured": round(achieved / measured, 4),
+                "launches": int(tm.select_sum_launches), "avg_launch_ms": round(tm.select_sum_ms / tm.select_sum_launches, 3),
+                "ops_per_launch": int(ops / tm.select_sum_launches)}
     return {
         "queries": nq,
         "m_range": [int(sizes.min()), int(sizes.max())],
@@ -494,6 +510,7 @@ def batched_leg(pk, params, server, server_items, cfg, nq, steps, seed, plain_va
         "batches_computed": int(server.max_load),
         "value_computed_batches": round(nq * n * server.max_load / t, 1),
         "valu_select_sum": valu,
+        "roofline_mfma": roof,
     }
 
 

@@ -438,7 +438,10 @@ int pepsi_server_timing(pepsi_server* server, int enable, int reset, pepsi_timin
 /* Issue rate of one vector-ALU instruction on the current device, in lane operations per
  * second: eight independent chains of the instruction per thread, 8 waves per SIMD on every
  * compute unit, timed with events (the measured peaks of the integer-VALU roofline).  kind: 0
- * v_mad_u64_u32, 1 v_mul_hi_u32, 2 v_mul_lo_u32, 3 v_add_u32, 4 v_mad_u32_u24, 5 v_fma_f64.
+ * v_mad_u64_u32, 1 v_mul_hi_u32, 2 v_mul_lo_u32, 3 v_add_u32, 4 v_mad_u32_u24, 5 v_fma_f64,
+ * 6 v_mfma_i32_16x16x64_i8 (the digit-plane select-and-sum's matrix instruction; eight
+ * independent accumulator chains per wave; the result is then in int8 operations per second,
+ * 2 x 16 x 16 x 64 per wave instruction).
  * Synchronous; allocates and frees a small buffer.  Errors: PEPSI_E_ARG, PEPSI_E_DEVICE. */
 int pepsi_probe_valu(uint32_t kind, double* lane_ops_per_s);
 

@@ -433,6 +433,7 @@ def hash_elements(elements, bits: int) -> np.ndarray:
 
 
 VALU_KINDS = ("v_mad_u64_u32", "v_mul_hi_u32", "v_mul_lo_u32", "v_add_u32", "v_mad_u32_u24", "v_fma_f64")
+MFMA_INT8_KIND = 6          # pepsi_probe_valu kind of v_mfma_i32_16x16x64_i8, in int8 operations/s
 
 
 def probe_valu(kind: int) -> float:
@@ -440,6 +441,11 @@ def probe_valu(kind: int) -> float:
     v = C.c_double()
     _check(lib().pepsi_probe_valu(kind, C.byref(v)))
     return float(v.value)
+
+
+def probe_mfma_int8() -> float:
+    """Measured int8 operations per second of the matrix instruction v_mfma_i32_16x16x64_i8."""
+    return probe_valu(MFMA_INT8_KIND)
 
 
 def clock() -> float:

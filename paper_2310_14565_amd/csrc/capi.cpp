@@ -1845,7 +1845,7 @@ extern "C" int pepsi_mod_switch(const pepsi_params* P, const uint64_t* ct, uint6
 
 // ------------------------------------------------------------------ measurement
 extern "C" int pepsi_probe_valu(uint32_t kind, double* lane_ops_per_s) {
-  if (!lane_ops_per_s || kind > 5) return fail(PEPSI_E_ARG, "kind must be 0..5 and the output non-null");
+  if (!lane_ops_per_s || kind > 6) return fail(PEPSI_E_ARG, "kind must be 0..6 and the output non-null");
   const int rc = probe_valu((int)kind, lane_ops_per_s);
   if (rc == PEPSI_E_NOMEM) return fail(rc, "probe buffer allocation failed");
   if (rc) return fail(rc, "VALU probe failed");

@@ -1,7 +1,10 @@
 // Issue-rate probes of single vector-ALU instructions on the current GPU: the measured peaks of
 // the integer-VALU roofline.  Each thread runs eight independent chains of one instruction
 // (written in inline asm so that the compiler can neither fold nor replace it), enough waves fill
-// every SIMD, and the rate is lane-operations per second over the kernel's event time.
+// every SIMD, and the rate is lane-operations per second over the kernel's event time.  Kind 6
+// runs eight independent accumulator chains of the int8 matrix instruction the digit-plane
+// select-and-sum uses (through its builtin: a matrix product is not folded away while its result
+// is used), counted in int8 operations (2 x 16 x 16 x 64 per wave instruction).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -11,6 +14,7 @@ namespace pepsi {
 namespace {
 
 constexpr int PR_TPB = 256, PR_CHAINS = 8, PR_UNROLL = 4;
+typedef int v4i __attribute__((ext_vector_type(4)));
 
 template <int KIND>
 __global__ void __launch_bounds__(PR_TPB) k_probe_valu(uint32_t iters, uint32_t seed, uint64_t* __restrict__ sink) {
@@ -25,7 +29,7 @@ __global__ void __launch_bounds__(PR_TPB) k_probe_valu(uint32_t iters, uint32_t 
     w[i] = x[i];
     d[i] = (double)x[i];
   }
-  for (uint32_t it = 0; it < iters; ++it) {
+  for (uint32_t it = 0; it < (KIND == 6 ? 0u : iters); ++it) {
 #pragma unroll
     for (int r = 0; r < PR_UNROLL; ++r)
 #pragma unroll
@@ -38,9 +42,25 @@ __global__ void __launch_bounds__(PR_TPB) k_probe_valu(uint32_t iters, uint32_t 
         if constexpr (KIND == 5) asm volatile("v_fma_f64 %0, %0, %1, %2" : "+v"(d[i]) : "v"(dc), "v"(dc2));
       }
   }
+  v4i m[PR_CHAINS];
+  if constexpr (KIND == 6) {
+    const v4i ma = v4i{(int)x[0], (int)x[1], (int)x[2], (int)x[3]};
+    const v4i mb = v4i{(int)x[4], (int)x[5], (int)x[6], (int)c};
+#pragma unroll
+    for (int i = 0; i < PR_CHAINS; ++i) m[i] = v4i{i, 0, 0, 0};
+    for (uint32_t it = 0; it < iters; ++it)
+#pragma unroll
+      for (int r = 0; r < PR_UNROLL; ++r)
+#pragma unroll
+        for (int i = 0; i < PR_CHAINS; ++i) m[i] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ma, mb, m[i], 0, 0, 0);
+  }
   uint64_t acc = 0;
 #pragma unroll
   for (int i = 0; i < PR_CHAINS; ++i) acc += x[i] + w[i] + (uint64_t)d[i];
+  if constexpr (KIND == 6) {
+#pragma unroll
+    for (int i = 0; i < PR_CHAINS; ++i) acc += (uint32_t)(m[i][0] + m[i][1] + m[i][2] + m[i][3]);
+  }
   sink[(size_t)blockIdx.x * PR_TPB + threadIdx.x] = acc;
 }
 
@@ -51,7 +71,7 @@ int probe_valu(int kind, double* lane_ops_per_s) {
   if (hipGetDevice(&dev) != hipSuccess) return -7;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -7;
   const int blocks = cus * 4 * 8 * 64 / PR_TPB;         // 8 waves per SIMD, 4 SIMDs per CU
-  const uint32_t iters = 16384;
+  const uint32_t iters = kind == 6 ? 2048 : 16384;     // a matrix instruction takes 16+ cycles
   uint64_t* sink = nullptr;
   if (hipMalloc(&sink, (size_t)blocks * PR_TPB * 8) != hipSuccess) return -6;
   hipEvent_t a, b;
@@ -64,7 +84,8 @@ int probe_valu(int kind, double* lane_ops_per_s) {
       case 2: hipLaunchKernelGGL(k_probe_valu<2>, dim3(blocks), dim3(PR_TPB), 0, 0, n, 12345u, sink); break;
       case 3: hipLaunchKernelGGL(k_probe_valu<3>, dim3(blocks), dim3(PR_TPB), 0, 0, n, 12345u, sink); break;
       case 4: hipLaunchKernelGGL(k_probe_valu<4>, dim3(blocks), dim3(PR_TPB), 0, 0, n, 12345u, sink); break;
-      default: hipLaunchKernelGGL(k_probe_valu<5>, dim3(blocks), dim3(PR_TPB), 0, 0, n, 12345u, sink); break;
+      case 5: hipLaunchKernelGGL(k_probe_valu<5>, dim3(blocks), dim3(PR_TPB), 0, 0, n, 12345u, sink); break;
+      default: hipLaunchKernelGGL(k_probe_valu<6>, dim3(blocks), dim3(PR_TPB), 0, 0, n, 12345u, sink); break;
     }
   };
   launch(64);                                           // warm-up
@@ -78,7 +99,7 @@ int probe_valu(int kind, double* lane_ops_per_s) {
   (void)hipEventDestroy(b);
   (void)hipFree(sink);
   if (e != hipSuccess || ms <= 0) return -7;
-  const double ops = (double)blocks * PR_TPB * iters * PR_UNROLL * PR_CHAINS;
+  const double ops = (double)blocks * PR_TPB * iters * PR_UNROLL * PR_CHAINS * (kind == 6 ? 2 * 16 * 16 * 64 / 64 : 1);
   *lane_ops_per_s = ops / (ms * 1e-3);
   return 0;
 }

@@ -168,3 +168,20 @@ def test_select_sum_matches_oracle():
     out = empty((2, gp.L, n), np.uint64)
     gp.select_sum(to_dev(cts), to_dev(pos), out)
     assert (to_host(out, np.uint64) == ctx.select_sum(cts, pos, h)).all()
+
+
+def test_issue_rate_probes_are_plausible():
+    """The measured instruction rates that set the VALU and matrix rooflines: positive, and not
+    above what the chip can issue (256 CUs x 64 lanes at up to 2.4 GHz, two VALU operations per
+    lane per clock for the simplest ones, and the published 5.0 POP/s dense int8 matrix peak, each
+    with 20% headroom)."""
+    say("issue-rate probes")
+    import paper_2310_14565_amd as pk
+    lane_issue = 256 * 64 * 2.4e9
+    for kind, name in enumerate(pk.VALU_KINDS):
+        r = pk.probe_valu(kind)
+        assert 0.01 * lane_issue < r < 2.4 * lane_issue, (name, r)
+    m = pk.probe_mfma_int8()
+    assert 0.1 * 5.0e15 < m < 1.2 * 5.0e15, m
+    with pytest.raises(Exception):
+        pk.probe_valu(7)

@@ -3,7 +3,8 @@
     python paper_2310_14565_amd/profile_summary.py kernels KT.db
         per-kernel time per evaluation of the plain path (from the first k_select_sum to the
         VALU probes, per k_select_sum launch) and of the batched path (from there to the
-        vector-unit A/B, per query), from a --kernel-trace database;
+        matrix-instruction probe or the vector-unit A/B, per query), from a --kernel-trace
+        database;
     python paper_2310_14565_amd/profile_summary.py counters PMC.db
         per-kernel VALU issue (VALUBusy = SQ_ACTIVE_INST_VALU / CUs / per-XCD GRBM_GUI_ACTIVE),
         VALU instructions, LDS bank conflicts per LDS instruction, from a --pmc database;
@@ -64,12 +65,13 @@ def kernels(db_path: str):
             print(f"  {t / div:9.4f} {100 * t / tot:5.1f}% {c / div:10.2f} {1e3 * t / c:10.2f}  {n}")
 
     # bench.py order: plain evaluations (one k_select_sum each), the VALU probes, then the batched
-    # leg (one k_request_planes per query), then its vector-unit A/B (k_select_sum_multi)
+    # leg (one k_request_planes per query), then its matrix-instruction probe and its
+    # vector-unit A/B (k_select_sum_multi); the batched window ends at whichever comes first
     a = first(lambda n: n == "k_select_sum")
     p = first(lambda n: "probe" in n, a)
     window(a, p, "plain path", "k_select_sum")
     b0 = first(lambda n: "k_request_planes" in n, p)
-    bm = first(lambda n: "k_select_sum_multi" in n, b0)
+    bm = first(lambda n: "k_select_sum_multi" in n or "probe" in n, b0)
     window(b0, bm, "batched path", "k_request_planes")
 
 

@@ -46,7 +46,8 @@ def test_kernels_windows_per_evaluation(tmp_path):
     for _ in range(4):                                   # four batched queries
         seq += [("pepsi::(anonymous namespace)::k_request_planes(Tables, int)", 2.0),
                 ("void pepsi::(anonymous namespace)::k_ntt_inv<13, 0, 3>(Tables)", 4.0)]
-    seq += [("pepsi::(anonymous namespace)::k_select_sum_multi(Tables, int)", 7.0)]
+    seq += [("void pepsi::(anonymous namespace)::k_probe_valu<6>(unsigned)", 30.0),
+            ("pepsi::(anonymous namespace)::k_select_sum_multi(Tables, int)", 7.0)]
     db = str(tmp_path / "kt.db")
     kernel_db(db, seq)
     out = run("kernels", db)

@@ -1493,7 +1493,7 @@ void relin_digits(const Tables& T, const Consts& hc, const uint64_t* c2, uint64_
 void relin_inner(const Tables& T, const Consts& hc, const uint64_t* c01h, const uint64_t* Dhat,
                  const uint64_t* rlk, long rlk_stride, const int* qslot, int jobs_per_unit, int units_per_pair,
                  int nq, uint64_t* out, int units, hipStream_t s) {
-  if (units <= 0) return;
+  if (units <= 0 || nq <= 0 || units_per_pair <= 0 || jobs_per_unit <= 0) return;   // the kernel divides by them
   PEPSI_L_LAUNCH(k_relin_inner, hc.L, grid_for(hc.n, hc.L, units), dim3(TPB), s, T, c01h, Dhat, rlk,
                  rlk_stride, qslot, jobs_per_unit, units_per_pair, nq, out);
 }

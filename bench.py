@@ -487,7 +487,8 @@ def batched_leg(pk, params, server, server_items, cfg, nq, steps, seed, plain_va
         ops = server.max_load * nq * 2 * L * n * params.ell * MFMA_DIGIT_PAIRS * 2
         achieved = ops / (tm.select_sum_ms / 1e3)
         measured = pk.probe_mfma_int8()
-        roof = {"kernel": "k_select_sum_planes_run" if sched.get("run", "").startswith("one") else "k_select_sum_planes",
+        run_mode = sched.get("run") == "one select-and-sum launch per run of tiles"
+        roof = {"kernel": "k_select_sum_planes_run" if run_mode else "k_select_sum_planes",
                 "bound": "mfma", "achieved": round(achieved / 1e12, 1), "peak": INT8_DENSE_PEAK_T,
                 "unit": "TOP/s (int8)", "frac": round(achieved / 1e12 / INT8_DENSE_PEAK_T, 4),
                 "measured_instruction_peak": round(measured / 1e12, 1),

@@ -1040,7 +1040,7 @@ __global__ void __launch_bounds__(TPB) k_select_sum_planes(Tables T, const int8_
 // m / 8.  In LDS each (part, query) run of kbs x 448 bytes starts at part RUN_CS + query RUN_QS,
 // with RUN_QS = 16 (mod 256) and RUN_CS = 8 RUN_QS = 128 (mod 256): the 16-byte reads of the 16
 // columns then fall on 16 distinct 16-byte bank slots of every 256 bytes (and the 8 columns of a
-// half wave on 8 distinct slots of every 128), so the reads of a wave are free of bank conflicts.
+// half wave on 8 distinct slots of every 128), so that the reads of a wave spread over the banks.
 // The oblocks workgroups of one (l, k) are numbered consecutively on one XCD and share its
 // plaintext planes through L2.  Needs kbs <= PL_RUN_KBS.
 __host__ __device__ constexpr int run_qs(int kbs) {
